@@ -1,0 +1,282 @@
+"""Pins of the oracle's three stages (Algorithms 2-5) against hand-derived
+examples, special cases with exact answers and invariants the paper states."""
+import numpy as np
+import pytest
+
+import oracle
+from helpers import NONE, golden, line_points, pad_adj, pad_dists, pad_ids
+from workloads import build_input_pg, get_config, make_queries, make_vectors, split_sizes
+
+
+def _tiny():
+    g = golden("e2e_tiny.json")
+    X = line_points(g["points"])
+    subs = [(s["off"], pad_adj(s["adj"]), s["entry"]) for s in g["subs"]]
+    return g, X, subs
+
+
+def test_e2e_hand_example_stage1():
+    g, X, subs = _tiny()
+    ids, dd, _ = oracle.cross_query(X, subs, g["k"], g["L"])
+    assert ids.tolist() == g["stage1"]["ids"]
+    assert dd.tolist() == g["stage1"]["dists"]
+
+
+@pytest.mark.parametrize("stage,rounds", [("round1", 1), ("stage2", 2)])
+def test_e2e_hand_example_refine(stage, rounds):
+    g, X, subs = _tiny()
+    ids, dd, _ = oracle.cross_query(X, subs, g["k"], g["L"])
+    i2, d2, f2, T, st = oracle.refine(X, subs, ids, dd, rounds, k_rev=g["k_rev"])
+    exp = g[stage]
+    assert i2.tolist() == exp["ids"]
+    assert d2.tolist() == exp["dists"]
+    assert f2.tolist() == exp["flags"]
+    assert T.tolist() == exp["T"]
+    if "repaired" in exp:
+        assert st["repaired"] == exp["repaired"]
+
+
+def test_e2e_hand_example_prune_and_merge():
+    g, X, subs = _tiny()
+    s2 = g["stage2"]
+    oi, od, deg = oracle.prune(X, np.array(s2["ids"], np.uint32),
+                               np.array(s2["dists"], np.float32),
+                               np.array(s2["T"], np.uint32), g["R"])
+    assert oi.tolist() == pad_ids(g["stage3"]["ids"], g["R"]).tolist()
+    assert deg.tolist() == g["stage3"]["deg"]
+    mi, mdeg, ent = oracle.merge(X, subs, g["k"], g["L"], g["rounds"], g["R"],
+                                 k_rev=g["k_rev"])
+    assert mi.tolist() == oi.tolist() and ent == g["entry"]
+
+
+@pytest.mark.parametrize("case", golden("repair_cases.json")["cases"], ids=lambda c: c["name"])
+def test_repair_hand_examples(case):
+    k = case["k"]
+    ids = pad_ids(case["ids"], k)
+    dd = pad_dists(case["dists"], k)
+    flags = np.zeros_like(ids, dtype=np.uint8)
+    oi, od, of, T, nr = oracle.repair(ids, dd, flags)
+    assert oi.tolist() == pad_ids(case["out_ids"], k).tolist()
+    assert od.tolist() == pad_dists(case["out_dists"], k).tolist()
+    assert (of & 1).tolist() == case["out_new"]
+    assert T.tolist() == case["T"]
+    assert nr == case["repaired"]
+
+
+def _rand_lists(rng, N, k, fill=1.0):
+    ids = np.full((N, k), NONE, np.uint32)
+    dd = np.full((N, k), np.inf, np.float32)
+    for u in range(N):
+        m = k if rng.random() < fill else int(rng.integers(1, k + 1))
+        cand = rng.choice(np.setdiff1d(np.arange(N), [u]), m, replace=False)
+        d = rng.integers(1, 50, m).astype(np.float32)
+        order = np.lexsort((cand, d))
+        ids[u, :m] = cand[order]
+        dd[u, :m] = d[order]
+    return ids, dd
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_repair_invariants(seed):
+    # The outdegree bound is kept and full lists keep their degree (Section
+    # 4.2.2; a list with a free slot may take v*), T equals a recount, the number of
+    # zero-indegree vertices never grows, a repaired vertex gains exactly one
+    # in-edge and no vertex that had in-edges loses its last one.
+    rng = np.random.default_rng(seed)
+    N, k = 300, 4
+    ids, dd = _rand_lists(rng, N, k, fill=0.8 if seed % 2 else 1.0)
+    T0 = np.bincount(ids[ids != NONE].astype(np.int64), minlength=N)
+    oi, od, of, T, nr = oracle.repair(ids, dd)
+    deg0 = (ids != NONE).sum(1)
+    deg1 = (oi != NONE).sum(1)
+    assert (deg1 <= k).all() and (deg1 >= deg0).all()
+    assert (deg1[deg0 == k] == k).all()
+    assert (deg1 - deg0).sum() <= nr
+    recount = np.bincount(oi[oi != NONE].astype(np.int64), minlength=N)
+    assert (recount == T).all()
+    assert (T == 0).sum() <= (T0 == 0).sum()
+    assert nr == (T0 == 0).sum() - (T == 0).sum()
+    assert (T[T0 == 0] <= 1).all()
+    assert (T[T0 > 0] >= 1).all()
+    for u in range(N):
+        row = [(od[u, t], oi[u, t]) for t in range(k) if oi[u, t] != NONE]
+        assert row == sorted(row) and len({v for _, v in row}) == len(row)
+
+
+def test_min_L_closed_form():
+    # L >= ceil((k - min |C+|) / (h - 1)) (Section 4.1.2); worst case ceil(k/(h-1)).
+    assert oracle.min_L(16, 0, 2) == 16
+    assert oracle.min_L(24, 3, 8) == 3
+    assert oracle.min_L(32, 10, 5) == 6
+    assert oracle.min_L(32, 0, 20) == 2
+    assert oracle.min_L(8, 9, 3) == 1
+
+
+def _complete_subs(sizes):
+    subs, off = [], 0
+    for n in sizes:
+        adj = np.array([[j for j in range(n) if j != i] for i in range(n)], np.uint32)
+        subs.append((off, adj, 0))
+        off += n
+    return subs
+
+
+@pytest.mark.parametrize("sizes,k,L", [((20, 30), 8, 8), ((15, 25, 10), 12, 20),
+                                       ((30, 30), 16, 40)])
+def test_stage1_complete_graphs_give_exact_knng(sizes, k, L):
+    # With complete input graphs every search returns the exact top-L of its
+    # graph and C+ is the whole own sub-index, so top-k of the union is the
+    # exact k-NN (integer data: FP32 distances are exact, ties by id).
+    rng = np.random.default_rng(sum(sizes))
+    X = rng.integers(0, 256, (sum(sizes), 16)).astype(np.float32)
+    ids, dd, _ = oracle.cross_query(X, _complete_subs(sizes), k, L)
+    gi, gd = oracle.bruteforce(X, X, k, exclude=np.arange(sum(sizes)))
+    assert ids.tolist() == gi.tolist()
+    assert dd.astype(np.float64).tolist() == gd.tolist()
+
+
+def _cfg_small(name="cfg1ov", sizes=(1500, 1500)):
+    cfg = get_config(name).scaled(sizes)
+    X = make_vectors(cfg)
+    subs = []
+    for off, n in split_sizes(cfg):
+        pg = build_input_pg(X[off:off + n], cfg.r_in, cfg.metric)
+        subs.append((off, pg.adj, pg.entry))
+    return cfg, X, subs
+
+
+def test_stage1_candidate_sources_and_sampling():
+    cfg, X, subs = _cfg_small(sizes=(700, 500, 300))
+    ids, dd, st = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric, threads=1)
+    ids8, dd8, st8 = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric, threads=8)
+    assert (ids == ids8).all() and (dd == dd8).all() and st == st8
+    nodes = np.array([5, 699, 700, 1499, 1000], np.uint64)
+    si, sd, _ = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric, nodes=nodes)
+    assert (si == ids[nodes.astype(np.int64)]).all()
+    offs = [s[0] for s in subs]
+    for u in range(X.shape[0]):
+        g = np.searchsorted(offs, u, side="right") - 1
+        own = {offs[g] + int(v) for v in subs[g][1][u - offs[g]] if v != NONE}
+        for v in ids[u]:
+            if v == NONE:
+                continue
+            gv = np.searchsorted(offs, v, side="right") - 1
+            assert gv != g or int(v) in own
+            assert v != u
+
+
+def test_stage1_single_subindex_is_sorted_local_list():
+    cfg, X, subs = _cfg_small(sizes=(800,))
+    ids, dd, _ = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric)
+    adj = subs[0][1]
+    for u in range(0, 800, 37):
+        loc = [int(v) for v in adj[u] if v != NONE]
+        keys = sorted((oracle.distance(X[u], X[v]), v) for v in loc)[:cfg.k]
+        assert [v for _, v in keys] == [int(v) for v in ids[u] if v != NONE]
+
+
+def test_stage1_rerank_with_identical_copy_matches_fp32():
+    cfg, X, subs = _cfg_small(sizes=(600, 600))
+    a, ad, _ = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric)
+    b, bd, _ = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric, Xs=X.copy(),
+                                  rerank=cfg.k)
+    assert (a == b).all() and (ad == bd).all()
+
+
+def test_join_keeps_exact_knng():
+    # An exact k-NNG is a fixed point of Update: no pair can beat an entry of
+    # a true k-NN list (repair off, so only the join acts).
+    rng = np.random.default_rng(4)
+    X = rng.integers(0, 256, (400, 8)).astype(np.float32)
+    subs = [(0, np.zeros((200, 1), np.uint32), 0), (200, np.zeros((200, 1), np.uint32), 0)]
+    gi, gd = oracle.bruteforce(X, X, 10, exclude=np.arange(400))
+    i2, d2, f2, T, st = oracle.refine(X, subs, gi, gd.astype(np.float32), 3,
+                                      do_repair=False)
+    assert (i2 == gi).all() and (d2 == gd.astype(np.float32)).all()
+
+
+def test_join_needs_two_subindexes():
+    # Pairs must come from different sub-indexes (Algorithm 3): with h = 1 no
+    # pair qualifies and the lists are unchanged.
+    cfg, X, subs = _cfg_small(sizes=(900,))
+    ids, dd, _ = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric)
+    i2, d2, f2, T, st = oracle.refine(X, subs, ids, dd, 2, cfg.metric, do_repair=False)
+    assert st["proposals"] == 0 and (i2 == ids).all() and (f2 == 0).all()
+
+
+def test_join_keys_monotone_and_recall_up():
+    cfg, X, subs = _cfg_small()
+    ids, dd, _ = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric)
+    i1, d1, _, _, _ = oracle.refine(X, subs, ids, dd, 1, cfg.metric, do_repair=False)
+    assert (d1 <= dd).all()
+    for u in range(X.shape[0]):
+        row = list(zip(d1[u].tolist(), i1[u].tolist()))
+        assert row == sorted(row)
+        assert len(set(i1[u].tolist())) == len(row)
+    nodes = np.arange(0, X.shape[0], 7)
+    r0 = oracle.knng_recall(X, ids[nodes], nodes, cfg.k)
+    i2, d2, _, T, _ = oracle.refine(X, subs, ids, dd, cfg.rounds, cfg.metric)
+    r2 = oracle.knng_recall(X, i2[nodes], nodes, cfg.k)
+    assert r2 >= r0
+    recount = np.bincount(i2[i2 != NONE].astype(np.int64), minlength=X.shape[0])
+    assert (recount == T).all()
+
+
+def _path_knng(n, k):
+    X = line_points(np.arange(n) * 3)
+    gi, gd = oracle.bruteforce(X, X, k, exclude=np.arange(n))
+    return X, gi, gd.astype(np.float32)
+
+
+def test_prune_on_line_gives_path():
+    # Equally spaced points on a line: u's nearer neighbour on either side
+    # occludes every farther point on that side, so the RNG selection over
+    # the exact k-NNG is the path graph, which reverse filling keeps.
+    n, k = 30, 6
+    X, gi, gd = _path_knng(n, k)
+    T = np.full(n, 2, np.uint32)
+    oi, od, deg = oracle.prune(X, gi, gd, T, 8)
+    for u in range(n):
+        want = [v for v in (u - 1, u + 1) if 0 <= v < n]
+        assert [int(v) for v in oi[u] if v != NONE] == want
+
+
+def test_prune_keeps_only_in_edge():
+    # A neighbour with T = 1 is kept even when occluded (Algorithm 5).
+    n, k = 30, 6
+    X, gi, gd = _path_knng(n, k)
+    T = np.full(n, 2, np.uint32)
+    T[14] = 1
+    oi, od, deg = oracle.prune(X, gi, gd, T, 8)
+    # 14 is in the 6-NN lists of 11 and 12, occluded there by 13.
+    assert 14 in oi[11].tolist() and 14 in oi[12].tolist()
+    T[14] = 2
+    oi2, _, _ = oracle.prune(X, gi, gd, T, 8)
+    assert 14 not in oi2[11].tolist() and 14 not in oi2[12].tolist()
+
+
+def test_prune_degree_bound_and_rule():
+    cfg, X, subs = _cfg_small()
+    ids, dd, _ = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric)
+    i2, d2, _, T, _ = oracle.refine(X, subs, ids, dd, cfg.rounds, cfg.metric)
+    for R in (4, 16):
+        oi, od, deg = oracle.prune(X, i2, d2, T, R, cfg.metric)
+        assert (deg <= R).all()
+        assert ((oi != NONE).sum(1) == deg).all()
+        for u in range(0, X.shape[0], 11):
+            row = [(od[u, t], oi[u, t]) for t in range(deg[u])]
+            assert row == sorted(row) and u not in oi[u].tolist()
+
+
+def test_merge_end_to_end_quality():
+    cfg, X, subs = _cfg_small()
+    pg, deg, ent = oracle.merge(X, subs, cfg.k, cfg.L, cfg.rounds, cfg.R, cfg.metric)
+    N = X.shape[0]
+    assert (deg <= cfg.R).all() and (deg >= 1).all()
+    for u in range(N):
+        row = pg[u, :deg[u]]
+        assert u not in row.tolist() and len(set(row.tolist())) == deg[u]
+    from workloads import reach_fraction
+    assert reach_fraction(pg, ent) >= 0.99
+    Q = make_queries(cfg, 100)
+    assert oracle.search_recall(X, pg, ent, Q, 64, cfg.metric) >= 0.9
