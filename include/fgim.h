@@ -1,0 +1,224 @@
+/*
+ * fgim.h -- C ABI of the MI355X (gfx950) FGIM merge library (libfgim.so).
+ *
+ * FGIM (Wu et al., "FGIM: a Fast Graph-based Indexes Merging Framework for
+ * Approximate Nearest Neighbor Search", PACMMOD 2026) merges h proximity
+ * graphs G_i = (V_i, E_i), built over disjoint vector sets X_i with one
+ * distance delta, into one graph over X = U X_i (problem definition
+ * "Merging Graph-based Indexes for ANNS", Section 2.1).  It runs in three
+ * stages (Section 3.2): PGs -> k-NNG by cross-querying (Section 4.1,
+ * Algorithm 2), k-NNG refinement with indegree repair (Section 4.2,
+ * Algorithms 3 and 4) and k-NNG -> PG by neighbour selection plus reverse
+ * edges (Section 4.3, Algorithm 5).
+ *
+ * Conventions shared by every entry point:
+ *  - Ids are uint32.  Global id of local vertex v of sub-index i is
+ *    phi_i(v) = subs[i].row_offset + v (Section 4.1.3).  FGIM_NONE pads a
+ *    short list; its distance slot holds +inf.
+ *  - delta is squared L2, -<a,b> (inner product) or 1 - <a,b> (cosine; the
+ *    caller passes unit vectors, the library never normalises).  Distances
+ *    are FP32, summed in one fixed order: coordinates in chunks of 4 added
+ *    left to right with fused multiply-adds, chunk sums combined by a stride
+ *    tree over the chunk count padded to a power of two, -0 turned into +0.
+ *  - Every list is sorted by (delta ascending, id ascending); ties are
+ *    broken by id everywhere.
+ *  - Pointers marked "device" are HIP device pointers; the caller owns all
+ *    buffers and the library never frees them.  Scratch memory is allocated
+ *    stream-ordered on `stream` and released before the call returns.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
+ *    Argument errors are returned before anything is enqueued.  Calls that
+ *    must report FGIM_ERR_GRAPH (or fill a host-side result) synchronise the
+ *    stream before returning; the others return with the work in flight.
+ *  - With precision FGIM_FP32 the outputs do not depend on launch
+ *    configuration (lanes per distance, waves per CU, visited-cache size):
+ *    they are bit-identical across runs and tuning choices.
+ *  - Outputs are undefined after any error.  Calls on the same device that
+ *    overlap in time are independent (no shared state) unless they write the
+ *    same buffers.
+ */
+#ifndef FGIM_H
+#define FGIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FGIM_NONE 0xFFFFFFFFu
+#define FGIM_MAX_DIM 4096u
+#define FGIM_MAX_K 128u       /* k, R */
+#define FGIM_MAX_L 256u       /* beam width */
+#define FGIM_MAX_STRIDE 128u  /* adjacency row stride */
+
+typedef enum {
+    FGIM_OK = 0,
+    FGIM_ERR_INVALID_ARG = 1,   /* null pointer, size out of range, bad ranges */
+    FGIM_ERR_GRAPH = 2,         /* adjacency id out of range, self-loop or duplicate */
+    FGIM_ERR_OUT_OF_MEMORY = 3, /* scratch allocation failed */
+    FGIM_ERR_DEVICE = 4,        /* a HIP call failed */
+    FGIM_ERR_UNSUPPORTED = 5    /* valid request this build does not handle */
+} fgim_status;
+
+typedef enum { FGIM_L2 = 0, FGIM_IP = 1, FGIM_COSINE = 2 } fgim_metric;
+
+/* Arithmetic of the candidate scoring.  FP32 is the exact (parity) form.
+ * BF16 and FP8_E4M3 score candidates on a low-precision copy of the base
+ * vectors (round-to-nearest-even BF16; OCP E4M3 with one FP32 scale per
+ * vector, scale = max|x| / 448) and re-score each node's best candidates
+ * on the FP32 rows before any list is written. */
+typedef enum { FGIM_FP32 = 0, FGIM_BF16 = 1, FGIM_FP8_E4M3 = 2 } fgim_precision;
+
+/* One input proximity graph G_i (problem definition, Section 2.1). */
+typedef struct {
+    uint64_t row_offset;   /* phi_i offset: global id / base row of local vertex 0 */
+    uint32_t n;            /* |V_i|, >= 1 */
+    uint32_t adj_stride;   /* row stride of adj (the input degree bound R_in), 1..128 */
+    const uint32_t* adj;   /* device, n x adj_stride local ids, FGIM_NONE padded */
+    uint32_t entry;        /* local id of the entry point ep_i (< n) */
+} fgim_subindex;
+
+/* The base vectors X and the h input graphs.  Sub-indexes must be given in
+ * ascending row_offset order and tile [0, n_total) without gaps. */
+typedef struct {
+    const float* base;          /* device, n_total rows of ld floats; 16-byte aligned */
+    uint64_t n_total;           /* sum of n_i, < 2^32 - 1 */
+    uint32_t dim;               /* d: multiple of 4, 4..FGIM_MAX_DIM */
+    uint64_t ld;                /* row stride in floats: multiple of 4, >= dim */
+    fgim_metric metric;
+    const fgim_subindex* subs;  /* host array of h entries */
+    uint32_t h;                 /* number of sub-indexes, >= 1 */
+    /* Optional low-precision copy for the BF16 / FP8 forms (device,
+     * dense n_total x dim, as written by fgim_quantize).  When NULL the
+     * library quantises into scratch inside the call. */
+    const void* base_lp;
+    const float* base_lp_scale; /* device, n_total FP8 scales (FP8 only) */
+} fgim_dataset;
+
+typedef struct {
+    uint32_t k;          /* k-NNG degree, 1..FGIM_MAX_K (Algorithm 2 "outdegree bound k") */
+    uint32_t L;          /* cross-query beam width (Algorithm 1 pool size), 1..FGIM_MAX_L */
+    uint32_t R;          /* output PG degree, 1..FGIM_MAX_K (Algorithm 5 bound) */
+    uint32_t rounds;     /* refinement iterations I_max (Algorithm 3) */
+    fgim_precision precision;
+    uint32_t rerank;     /* candidates per search re-scored in FP32; 0 -> min(L, 2k) */
+    uint32_t k_rev;      /* cap of each reverse list in refinement; 0 -> k */
+    int autotune;        /* 0: L as given; 1: the tuner may lower L to the
+                            minimum-querying bound of Section 4.1.2 and picks
+                            the launch shape */
+    /* Launch shape (0 = choose automatically).  None of these changes an
+     * FP32 result bit. */
+    uint32_t lanes_per_dist;   /* lanes that share one distance: 1..64, power of 2 */
+    uint32_t waves_per_cu;     /* resident waves per compute unit of the beam kernel */
+    uint32_t visited_slots;    /* entries of the per-wave LDS visited cache (power of 2) */
+    uint32_t flags;            /* FGIM_FLAG_* */
+} fgim_params;
+
+#define FGIM_FLAG_NO_REPAIR 1u     /* refinement without indegree repair (test hook) */
+#define FGIM_FLAG_NO_GRAPH_CAPTURE 2u /* run refinement rounds eagerly, not as a hipGraph */
+
+/* Per-call counters; passing a non-NULL stats pointer synchronises the
+ * stream at the end of the call. */
+typedef struct {
+    double ms_stage[3];       /* wall time of stage 1, 2, 3 on the stream (hipEvents) */
+    double ms_beam_kernel;    /* duration of the stage-1 beam-search kernel alone */
+    uint64_t ndc;             /* distance computations of the beam searches */
+    uint64_t expansions;      /* pool entries expanded by the beam searches */
+    uint64_t searches;        /* beam searches run */
+    uint64_t proposals;       /* join proposals that passed the worst-entry screen */
+    uint64_t repaired;        /* zero-indegree vertices given an in-edge */
+    uint64_t rechecked;       /* join pairs re-scored after the MFMA screen */
+    uint32_t L_used;          /* beam width actually used */
+    uint32_t lanes_per_dist;  /* launch shape actually used */
+    uint32_t waves_per_cu;
+    uint32_t visited_slots;
+} fgim_stats;
+
+/*
+ * Stage 1, PGs -> k-NNG (Section 4.1, Algorithm 2).  For every vertex u of
+ * every G_i: the local candidates C+(u) are u's out-neighbours in G_i
+ * (Section 4.1.1, "Local Candidate Neighbors"); every other G_j is searched
+ * with Algorithm 1 (beam width L, from ep_j: "cross-querying", "Cross
+ * Candidate Neighbors"); the union is mapped to global ids by phi, sorted,
+ * and its first k entries form row phi_i(u) of the k-NNG.
+ * Outputs (device, n_total x k): knn_ids, knn_dist (canonical FP32 delta).
+ * Errors: FGIM_ERR_INVALID_ARG (arguments), FGIM_ERR_GRAPH (bad adjacency,
+ * checked on the device; the call then synchronises).
+ */
+fgim_status fgim_cross_query(const fgim_dataset* data, const fgim_params* params,
+                             uint32_t* knn_ids, float* knn_dist, fgim_stats* stats,
+                             void* stream);
+
+/*
+ * Stage 2, k-NNG refinement (Section 4.2, Algorithms 3 and 4), run as
+ * `rounds` synchronous rounds.  Each round: Visit splits each list and its
+ * reverse lists into new and old candidates, Update proposes every
+ * cross-sub-index pair of C_n^2 U C_n x C_o to both ends, every list keeps
+ * its k best of old entries and proposals, then indegree repair links each
+ * zero-indegree vertex into a neighbour's list.  All input entries count as
+ * new.  knn_ids / knn_dist (device, n_total x k) are read and rewritten;
+ * indegree (device, n_total, nullable) receives T after the last round.
+ */
+fgim_status fgim_refine(const fgim_dataset* data, const fgim_params* params,
+                        uint32_t* knn_ids, float* knn_dist, uint32_t* indegree,
+                        fgim_stats* stats, void* stream);
+
+/*
+ * Stage 3, k-NNG -> PG (Section 4.3, Algorithm 5).  Neighbour selection
+ * keeps v in N(u) (closest first) when T(v) = 1 or delta(u,v) < delta(w,v)
+ * for every kept w, up to R; connectivity enhancement then adds the reverse
+ * of every selected edge, sorts and keeps the first R.
+ * Inputs (device): knn_ids / knn_dist (n_total x k), indegree T (n_total).
+ * Outputs (device): pg_ids (n_total x R, FGIM_NONE padded), pg_deg (n_total).
+ */
+fgim_status fgim_prune(const fgim_dataset* data, const fgim_params* params,
+                       const uint32_t* knn_ids, const float* knn_dist,
+                       const uint32_t* indegree, uint32_t* pg_ids, uint32_t* pg_deg,
+                       void* stream);
+
+/*
+ * The three stages in one call (Section 3.2).  Outputs: pg_ids, pg_deg as
+ * fgim_prune; *entry (host) = global id of the merged graph's entry point,
+ * the entry of the largest sub-index (lowest index on ties).  Synchronises.
+ */
+fgim_status fgim_merge(const fgim_dataset* data, const fgim_params* params,
+                       uint32_t* pg_ids, uint32_t* pg_deg, uint32_t* entry,
+                       fgim_stats* stats, void* stream);
+
+/*
+ * Algorithm 1 (KNNSearch) for a batch of queries on one graph, used to
+ * evaluate a merged index (Recall@k, Section 2.1).  Graph: adj (device,
+ * n x stride ids into base), entry.  Queries (device, nq rows of ldq
+ * floats).  Outputs (device, nq x topk): the first topk pool entries.
+ * topk <= L.
+ */
+fgim_status fgim_search(const float* base, uint64_t n, uint32_t dim, uint64_t ld,
+                        fgim_metric metric, const uint32_t* adj, uint32_t stride,
+                        uint32_t entry, const float* queries, uint64_t nq, uint64_t ldq,
+                        uint32_t L, uint32_t topk, uint32_t* out_ids, float* out_dist,
+                        void* stream);
+
+/*
+ * Low-precision copy for the BF16 / FP8 forms.  BF16: codes = uint16
+ * [n x dim]; FP8_E4M3: codes = uint8 [n x dim] and scales (device, n).
+ * Same encodings as described at fgim_precision.
+ */
+fgim_status fgim_quantize(const float* base, uint64_t n, uint32_t dim, uint64_t ld,
+                          fgim_precision precision, void* codes, float* scales,
+                          void* stream);
+
+/* ceil((k - min_local) / (h - 1)), at least 1: the smallest L for which
+ * every vertex still collects k candidates (minimum querying strategy,
+ * Section 4.1.2).  0 when h < 2. */
+uint32_t fgim_min_beam_width(uint32_t k, uint32_t min_local, uint32_t h);
+
+const char* fgim_status_string(fgim_status status);
+/* Detail of the last error on the calling thread ("" if none). */
+const char* fgim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FGIM_H */

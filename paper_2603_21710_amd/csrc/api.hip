@@ -1,0 +1,497 @@
+// C ABI of libfgim: argument validation, stream-ordered scratch, launch
+// shape selection and the small utility kernels (graph validation, fills,
+// low-precision encoders).  The stage kernels live in beam_*.hip,
+// refine.hip and prune.hip.
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "fgim.h"
+#include "fgim_internal.h"
+#include "host_util.h"
+
+namespace fgim {
+
+thread_local std::string g_last_error;
+
+fgim_status fail(fgim_status s, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return s;
+}
+
+int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+    return 256;
+  return cus;
+}
+
+// ---------------------------------------------------------------------------
+// utility kernels
+
+__global__ void fill_u32_kernel(uint32_t* p, uint32_t v, uint64_t n) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    p[i] = v;
+}
+
+hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  uint64_t blocks = std::min<uint64_t>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+// One wavefront per adjacency row: every id must be FGIM_NONE or < n, not
+// the row's own id, and unique within the row.  Sets *err on a violation.
+__global__ void __launch_bounds__(256) validate_graph_kernel(const uint32_t* adj, uint32_t n,
+                                                             uint32_t stride, uint32_t* err) {
+  const uint32_t wave = threadIdx.x / 64;
+  const int lane = lane_id();
+  for (uint64_t row = blockIdx.x * 4ull + wave; row < n; row += gridDim.x * 4ull) {
+    const uint32_t v0 = lane < static_cast<int>(stride) ? adj[row * stride + lane] : kNone;
+    const uint32_t v1 = lane + 64 < static_cast<int>(stride) ? adj[row * stride + 64 + lane] : kNone;
+    bool bad = (v0 != kNone && (v0 >= n || v0 == row)) || (v1 != kNone && (v1 >= n || v1 == row));
+    for (int s = 1; s < 64; ++s) {
+      const uint32_t w0 = __shfl_xor(v0, s, 64);
+      bad |= v0 != kNone && w0 == v0;
+      if (stride > 64) {
+        const uint32_t w1 = __shfl_xor(v1, s, 64);
+        bad |= v1 != kNone && w1 == v1;
+      }
+    }
+    if (stride > 64) {
+      for (int s = 0; s < 64; ++s) {
+        const uint32_t w1 = __shfl(v1, s, 64);
+        bad |= v0 != kNone && w1 == v0;
+      }
+    }
+    if (ballot(bad) != 0 && lane == 0) atomicOr(err, 1u);
+  }
+}
+
+hipError_t validate_graph(const uint32_t* adj, uint32_t n, uint32_t stride, uint32_t* err,
+                          hipStream_t s) {
+  uint32_t blocks = std::min<uint32_t>((n + 3) / 4, 8192);
+  hipLaunchKernelGGL(validate_graph_kernel, dim3(blocks), dim3(256), 0, s, adj, n, stride, err);
+  return hipGetLastError();
+}
+
+// BF16: round to nearest even (NaN stays a quiet NaN).
+__device__ __forceinline__ uint16_t bf16_encode(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x007FFFFFu)) return static_cast<uint16_t>((u >> 16) | 0x40u);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+// OCP E4M3, round to nearest even, saturating at 448.  Below 2^-6 the code
+// is the subnormal mantissa round(|x| * 2^9) (8 carries into the smallest
+// normal, code 0x08); above, the FP32 mantissa is cut to 3 bits with
+// round-half-even on the 20 dropped bits.
+__device__ __forceinline__ uint8_t fp8_encode(float x) {
+  const uint32_t bits = __float_as_uint(x);
+  const uint32_t sign = (bits >> 24) & 0x80u;
+  const float a = __uint_as_float(bits & 0x7FFFFFFFu);
+  if (!(a < 448.0f)) return static_cast<uint8_t>(sign | 0x7Eu);
+  if (a < 0.015625f) {
+    const uint32_t m = static_cast<uint32_t>(__builtin_rintf(a * 512.0f));
+    return static_cast<uint8_t>(sign | m);
+  }
+  const uint32_t ab = bits & 0x7FFFFFFFu;
+  int e = static_cast<int>(ab >> 23) - 127;
+  const uint32_t mant = ab & 0x7FFFFFu;
+  uint32_t r = mant >> 20;
+  const uint32_t rem = mant & 0xFFFFFu;
+  if (rem > 0x80000u || (rem == 0x80000u && (r & 1u))) ++r;
+  if (r == 8u) {
+    r = 0;
+    ++e;
+  }
+  return static_cast<uint8_t>(sign | (static_cast<uint32_t>(e + 7) << 3) | r);
+}
+
+__global__ void __launch_bounds__(256) quantize_bf16_kernel(const float* X, uint64_t n, uint32_t dim,
+                                                            uint64_t ld, uint16_t* out) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n * dim;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t r = i / dim, c = i % dim;
+    out[i] = bf16_encode(X[r * ld + c]);
+  }
+}
+
+// one wavefront per row: scale = max|x| / 448, code = fp8(x * (448 / max|x|))
+__global__ void __launch_bounds__(256) quantize_fp8_kernel(const float* X, uint64_t n, uint32_t dim,
+                                                           uint64_t ld, uint8_t* out, float* scale) {
+  const uint32_t wave = threadIdx.x / 64;
+  const int lane = lane_id();
+  for (uint64_t row = blockIdx.x * 4ull + wave; row < n; row += gridDim.x * 4ull) {
+    const float* x = X + row * ld;
+    float amax = 0.0f;
+    for (uint32_t t = lane; t < dim; t += 64) amax = fmaxf(amax, fabsf(x[t]));
+    for (int st = 32; st >= 1; st /= 2) amax = fmaxf(amax, __shfl_xor(amax, st, 64));
+    const float inv = amax > 0.0f ? 448.0f / amax : 1.0f;
+    if (lane == 0) scale[row] = amax > 0.0f ? amax / 448.0f : 1.0f;
+    for (uint32_t t = lane; t < dim; t += 64) out[row * dim + t] = fp8_encode(x[t] * inv);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// host helpers
+
+bool is_pow2(uint64_t x) { return x && !(x & (x - 1)); }
+
+uint32_t ceil_pow2(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+uint32_t ilog2(uint32_t x) {
+  uint32_t l = 0;
+  while ((1u << l) < x) ++l;
+  return l;
+}
+
+fgim_status check_rows(const float* base, uint64_t n, uint32_t dim, uint64_t ld) {
+  if (!base) return fail(FGIM_ERR_INVALID_ARG, "base is NULL");
+  if (n == 0 || n >= 0xFFFFFFFFull) return fail(FGIM_ERR_INVALID_ARG, "row count %llu out of range", (unsigned long long)n);
+  if (dim < 4 || dim > FGIM_MAX_DIM || dim % 4)
+    return fail(dim % 4 ? FGIM_ERR_UNSUPPORTED : FGIM_ERR_INVALID_ARG, "dim %u must be a multiple of 4 in 4..%u", dim, FGIM_MAX_DIM);
+  if (ld < dim || ld % 4) return fail(FGIM_ERR_INVALID_ARG, "ld %llu must be a multiple of 4 and >= dim", (unsigned long long)ld);
+  if (reinterpret_cast<uintptr_t>(base) % 16) return fail(FGIM_ERR_INVALID_ARG, "base must be 16-byte aligned");
+  return FGIM_OK;
+}
+
+fgim_status check_dataset(const fgim_dataset* d, bool need_cross) {
+  if (!d) return fail(FGIM_ERR_INVALID_ARG, "dataset is NULL");
+  fgim_status st = check_rows(d->base, d->n_total, d->dim, d->ld);
+  if (st) return st;
+  if (d->metric != FGIM_L2 && d->metric != FGIM_IP && d->metric != FGIM_COSINE)
+    return fail(FGIM_ERR_INVALID_ARG, "unknown metric %d", (int)d->metric);
+  if (!d->subs || d->h == 0) return fail(FGIM_ERR_INVALID_ARG, "no sub-indexes");
+  if (d->h > 4096) return fail(FGIM_ERR_UNSUPPORTED, "h = %u sub-indexes (max 4096)", d->h);
+  uint64_t expect = 0;
+  for (uint32_t i = 0; i < d->h; ++i) {
+    const fgim_subindex& s = d->subs[i];
+    if (s.row_offset != expect)
+      return fail(FGIM_ERR_INVALID_ARG, "sub-index %u starts at %llu, expected %llu (ranges must tile [0, n_total) in order)",
+                  i, (unsigned long long)s.row_offset, (unsigned long long)expect);
+    if (s.n == 0) return fail(FGIM_ERR_INVALID_ARG, "sub-index %u is empty", i);
+    if (need_cross) {
+      if (!s.adj) return fail(FGIM_ERR_INVALID_ARG, "sub-index %u: adj is NULL", i);
+      if (s.adj_stride == 0 || s.adj_stride > FGIM_MAX_STRIDE)
+        return fail(FGIM_ERR_INVALID_ARG, "sub-index %u: adj_stride %u out of 1..%u", i, s.adj_stride, FGIM_MAX_STRIDE);
+      if (s.entry >= s.n) return fail(FGIM_ERR_INVALID_ARG, "sub-index %u: entry %u >= n %u", i, s.entry, s.n);
+    }
+    expect += s.n;
+  }
+  if (expect != d->n_total)
+    return fail(FGIM_ERR_INVALID_ARG, "sub-index sizes sum to %llu, n_total is %llu", (unsigned long long)expect,
+                (unsigned long long)d->n_total);
+  return FGIM_OK;
+}
+
+// Launch shape of the beam kernel.
+struct BeamShape {
+  uint32_t P, M, mmax, nr, vis_log2, waves;
+};
+
+fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* p, BeamShape* out) {
+  const uint32_t nc = dim / 4;
+  const uint32_t N = ceil_pow2(nc);
+  uint32_t P = p && p->lanes_per_dist ? p->lanes_per_dist : std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, N), N / 4));
+  if (!is_pow2(P) || P > 64 || P > N) return fail(FGIM_ERR_INVALID_ARG, "lanes_per_dist %u must be a power of 2 <= min(64, %u)", P, N);
+  const uint32_t M = N / P;
+  if (M > 16) return fail(FGIM_ERR_INVALID_ARG, "lanes_per_dist %u too small for dim %u", P, dim);
+  const uint32_t cap = std::max(L, k);
+  uint32_t nr = cap <= 64 ? 1 : (cap <= 128 ? 2 : 4);
+  uint32_t slots = p && p->visited_slots ? p->visited_slots : std::min<uint32_t>(8192, std::max<uint32_t>(1024, ceil_pow2(32 * L)));
+  if (!is_pow2(slots) || slots < 64 || slots > 16384) return fail(FGIM_ERR_INVALID_ARG, "visited_slots %u must be a power of 2 in 64..16384", slots);
+  uint32_t waves = p && p->waves_per_cu ? p->waves_per_cu : 16;
+  if (waves > 64) return fail(FGIM_ERR_INVALID_ARG, "waves_per_cu %u > 64", waves);
+  *out = BeamShape{P, M, M <= 4 ? 4u : 16u, nr, ilog2(slots), waves};
+  return FGIM_OK;
+}
+
+size_t beam_smem(const BeamShape& s) { return 64 * 8 + 64 * 4 + (size_t(4) << s.vis_log2); }
+
+hipError_t launch_beam(const BeamArgs& a, bool l2, int fmt, const BeamShape& s, hipStream_t st) {
+  dim3 grid(device_cus() * s.waves);
+  size_t smem = beam_smem(s);
+  if (fmt == kF32) return launch_beam_f32(a, l2, s.nr, s.mmax, grid, smem, st);
+  if (fmt == kBF16) return launch_beam_bf16(a, l2, s.nr, s.mmax, grid, smem, st);
+  return launch_beam_fp8(a, l2, s.nr, s.mmax, grid, smem, st);
+}
+
+uint32_t tuned_beam_width(const fgim_dataset* d, const fgim_params* p, uint32_t lo) {
+  (void)d;
+  return std::max(lo, p->L);
+}
+
+fgim_status quantize_into(const float* base, uint64_t n, uint32_t dim, uint64_t ld, fgim_precision prec,
+                          void* codes, float* scales, hipStream_t s) {
+  if (prec == FGIM_BF16) {
+    uint64_t blocks = std::min<uint64_t>((n * dim + 255) / 256, 65536);
+    hipLaunchKernelGGL(quantize_bf16_kernel, dim3(blocks), dim3(256), 0, s, base, n, dim, ld,
+                       static_cast<uint16_t*>(codes));
+  } else {
+    uint64_t blocks = std::min<uint64_t>((n + 3) / 4, 65536);
+    hipLaunchKernelGGL(quantize_fp8_kernel, dim3(blocks), dim3(256), 0, s, base, n, dim, ld,
+                       static_cast<uint8_t*>(codes), scales);
+  }
+  HIP_TRY(hipGetLastError());
+  return FGIM_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stage 1
+
+fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist,
+                             fgim_stats* stats, hipStream_t s, uint32_t* L_used) {
+  FGIM_TRY(check_dataset(d, true));
+  if (!p) return fail(FGIM_ERR_INVALID_ARG, "params is NULL");
+  if (!ids || !dist) return fail(FGIM_ERR_INVALID_ARG, "output is NULL");
+  if (p->k == 0 || p->k > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "k = %u out of 1..%u", p->k, FGIM_MAX_K);
+  if (p->L == 0 || p->L > FGIM_MAX_L) return fail(FGIM_ERR_INVALID_ARG, "L = %u out of 1..%u", p->L, FGIM_MAX_L);
+  if (p->precision != FGIM_FP32 && p->precision != FGIM_BF16 && p->precision != FGIM_FP8_E4M3)
+    return fail(FGIM_ERR_INVALID_ARG, "unknown precision %d", (int)p->precision);
+  uint32_t L = p->L;
+  if (p->autotune) {
+    uint32_t min_local = 0;  // worst case: a vertex without local neighbours
+    uint32_t lo = fgim_min_beam_width(p->k, min_local, d->h);
+    L = tuned_beam_width(d, p, lo);
+  }
+  uint32_t rerank = p->rerank ? p->rerank : std::min<uint32_t>(L, 2 * p->k);
+  if (p->precision != FGIM_FP32 && (rerank < p->k || rerank > L)) {
+    if (p->rerank) return fail(FGIM_ERR_INVALID_ARG, "rerank %u must be in k..L", p->rerank);
+    rerank = std::min(L, std::max(rerank, p->k));
+  }
+  BeamShape shape;
+  FGIM_TRY(beam_shape(d->dim, L, p->k, p, &shape));
+
+  Scratch scr(s);
+  uint32_t* hdr = nullptr;  // [0] queue head, [1] error flag
+  unsigned long long* cnt = nullptr;
+  SubDev* subs = nullptr;
+  FGIM_TRY(scr.get(&hdr, 4));
+  FGIM_TRY(scr.get(&cnt, 4));
+  FGIM_TRY(scr.get(&subs, d->h));
+  std::vector<SubDev> hs(d->h);
+  for (uint32_t i = 0; i < d->h; ++i)
+    hs[i] = SubDev{d->subs[i].row_offset, d->subs[i].adj, d->subs[i].n, d->subs[i].adj_stride, d->subs[i].entry, 0};
+  HIP_TRY(hipMemcpyAsync(subs, hs.data(), sizeof(SubDev) * d->h, hipMemcpyHostToDevice, s));
+  HIP_TRY(fill_u32(hdr, 0u, 4, s));
+  HIP_TRY(fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, 8, s));
+  for (uint32_t i = 0; i < d->h; ++i) HIP_TRY(validate_graph(d->subs[i].adj, d->subs[i].n, d->subs[i].adj_stride, hdr + 1, s));
+
+  const void* lp = d->base_lp;
+  const float* lps = d->base_lp_scale;
+  if (p->precision != FGIM_FP32 && !lp) {
+    if (p->precision == FGIM_BF16) {
+      uint16_t* c = nullptr;
+      FGIM_TRY(scr.get(&c, d->n_total * d->dim));
+      FGIM_TRY(quantize_into(d->base, d->n_total, d->dim, d->ld, p->precision, c, nullptr, s));
+      lp = c;
+    } else {
+      uint8_t* c = nullptr;
+      float* sc = nullptr;
+      FGIM_TRY(scr.get(&c, d->n_total * d->dim));
+      FGIM_TRY(scr.get(&sc, d->n_total));
+      FGIM_TRY(quantize_into(d->base, d->n_total, d->dim, d->ld, p->precision, c, sc, s));
+      lp = c;
+      lps = sc;
+    }
+  }
+  if (p->precision == FGIM_FP8_E4M3 && !lps) return fail(FGIM_ERR_INVALID_ARG, "FP8 copy given without scales");
+
+  BeamArgs a{};
+  a.X = d->base;
+  a.ld = d->ld;
+  a.nc = d->dim / 4;
+  a.metric = d->metric;
+  a.xb = p->precision == FGIM_BF16 ? static_cast<const uint16_t*>(lp) : nullptr;
+  a.x8 = p->precision == FGIM_FP8_E4M3 ? static_cast<const uint8_t*>(lp) : nullptr;
+  a.x8s = lps;
+  a.dim = d->dim;
+  a.subs = subs;
+  a.h = d->h;
+  a.L = L;
+  a.k = p->k;
+  a.rerank = rerank;
+  a.n_items = d->n_total;
+  a.out_ids = ids;
+  a.out_dist = dist;
+  a.counter = hdr;
+  a.err = hdr + 1;
+  a.stats = cnt;
+  a.vis_log2 = shape.vis_log2;
+  a.P = shape.P;
+  a.M = shape.M;
+  a.search_mode = 0;
+
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (stats) {
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, s));
+  }
+  int fmt = p->precision == FGIM_FP32 ? kF32 : (p->precision == FGIM_BF16 ? kBF16 : kFP8);
+  HIP_TRY(launch_beam(a, d->metric == FGIM_L2, fmt, shape, s));
+  if (stats) HIP_TRY(hipEventRecord(e1, s));
+
+  uint32_t herr = 0;
+  unsigned long long hc[3] = {0, 0, 0};
+  HIP_TRY(hipMemcpyAsync(&herr, hdr + 1, 4, hipMemcpyDeviceToHost, s));
+  if (stats) HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (stats) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    stats->ms_beam_kernel = ms;
+    stats->ndc = hc[0];
+    stats->expansions = hc[1];
+    stats->searches = hc[2];
+    stats->L_used = L;
+    stats->lanes_per_dist = shape.P;
+    stats->waves_per_cu = shape.waves;
+    stats->visited_slots = 1u << shape.vis_log2;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  }
+  if (L_used) *L_used = L;
+  if (herr) return fail(FGIM_ERR_GRAPH, "an adjacency list holds an out-of-range id, a self-loop or a duplicate");
+  return FGIM_OK;
+}
+
+}  // namespace fgim
+
+using namespace fgim;
+
+extern "C" {
+
+const char* fgim_status_string(fgim_status s) {
+  switch (s) {
+    case FGIM_OK: return "ok";
+    case FGIM_ERR_INVALID_ARG: return "invalid argument";
+    case FGIM_ERR_GRAPH: return "malformed adjacency list";
+    case FGIM_ERR_OUT_OF_MEMORY: return "out of device memory";
+    case FGIM_ERR_DEVICE: return "HIP error";
+    case FGIM_ERR_UNSUPPORTED: return "unsupported";
+  }
+  return "unknown status";
+}
+
+const char* fgim_last_error(void) { return g_last_error.c_str(); }
+
+uint32_t fgim_min_beam_width(uint32_t k, uint32_t min_local, uint32_t h) {
+  if (h < 2) return 0;
+  if (min_local >= k) return 1;
+  const uint32_t need = k - min_local;
+  const uint32_t l = (need + h - 2) / (h - 1);
+  return l ? l : 1;
+}
+
+fgim_status fgim_cross_query(const fgim_dataset* data, const fgim_params* params, uint32_t* knn_ids,
+                             float* knn_dist, fgim_stats* stats, void* stream) {
+  g_last_error.clear();
+  if (stats) memset(stats, 0, sizeof(*stats));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (stats) {
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    HIP_TRY(hipEventRecord(a, s));
+  }
+  fgim_status st = cross_query_impl(data, params, knn_ids, knn_dist, stats, s, nullptr);
+  if (stats && st == FGIM_OK) {
+    HIP_TRY(hipEventRecord(b, s));
+    HIP_TRY(hipEventSynchronize(b));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, a, b));
+    stats->ms_stage[0] = ms;
+  }
+  if (a) (void)hipEventDestroy(a);
+  if (b) (void)hipEventDestroy(b);
+  return st;
+}
+
+fgim_status fgim_search(const float* base, uint64_t n, uint32_t dim, uint64_t ld, fgim_metric metric,
+                        const uint32_t* adj, uint32_t stride, uint32_t entry, const float* queries,
+                        uint64_t nq, uint64_t ldq, uint32_t L, uint32_t topk, uint32_t* out_ids,
+                        float* out_dist, void* stream) {
+  g_last_error.clear();
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FGIM_TRY(check_rows(base, n, dim, ld));
+  if (metric != FGIM_L2 && metric != FGIM_IP && metric != FGIM_COSINE) return fail(FGIM_ERR_INVALID_ARG, "unknown metric");
+  if (!adj || stride == 0 || stride > FGIM_MAX_STRIDE) return fail(FGIM_ERR_INVALID_ARG, "bad adjacency (stride %u)", stride);
+  if (entry >= n) return fail(FGIM_ERR_INVALID_ARG, "entry %u >= n", entry);
+  if (nq == 0) return FGIM_OK;
+  if (!queries || ldq < dim || ldq % 4 || reinterpret_cast<uintptr_t>(queries) % 16)
+    return fail(FGIM_ERR_INVALID_ARG, "bad query matrix");
+  if (nq >= 0xFFFFFFFFull) return fail(FGIM_ERR_INVALID_ARG, "too many queries");
+  if (L == 0 || L > FGIM_MAX_L || topk == 0 || topk > L) return fail(FGIM_ERR_INVALID_ARG, "need 1 <= topk <= L <= %u", FGIM_MAX_L);
+  if (!out_ids || !out_dist) return fail(FGIM_ERR_INVALID_ARG, "output is NULL");
+  BeamShape shape;
+  FGIM_TRY(beam_shape(dim, L, topk, nullptr, &shape));
+  Scratch scr(s);
+  uint32_t* hdr = nullptr;
+  SubDev* sub = nullptr;
+  FGIM_TRY(scr.get(&hdr, 4));
+  FGIM_TRY(scr.get(&sub, 1));
+  SubDev hs{0, adj, static_cast<uint32_t>(n), stride, entry, 0};
+  HIP_TRY(hipMemcpyAsync(sub, &hs, sizeof(hs), hipMemcpyHostToDevice, s));
+  HIP_TRY(fill_u32(hdr, 0u, 4, s));
+  HIP_TRY(validate_graph(adj, static_cast<uint32_t>(n), stride, hdr + 1, s));
+  BeamArgs a{};
+  a.X = base;
+  a.ld = ld;
+  a.nc = dim / 4;
+  a.metric = metric;
+  a.dim = dim;
+  a.subs = sub;
+  a.h = 1;
+  a.L = L;
+  a.k = topk;
+  a.rerank = topk;
+  a.n_items = nq;
+  a.out_ids = out_ids;
+  a.out_dist = out_dist;
+  a.counter = hdr;
+  a.err = hdr + 1;
+  a.stats = nullptr;
+  a.vis_log2 = shape.vis_log2;
+  a.P = shape.P;
+  a.M = shape.M;
+  a.search_mode = 1;
+  a.Q = queries;
+  a.ldq = ldq;
+  HIP_TRY(launch_beam(a, metric == FGIM_L2, kF32, shape, s));
+  uint32_t herr = 0;
+  HIP_TRY(hipMemcpyAsync(&herr, hdr + 1, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (herr) return fail(FGIM_ERR_GRAPH, "the graph holds an out-of-range id, a self-loop or a duplicate");
+  return FGIM_OK;
+}
+
+fgim_status fgim_quantize(const float* base, uint64_t n, uint32_t dim, uint64_t ld, fgim_precision precision,
+                          void* codes, float* scales, void* stream) {
+  g_last_error.clear();
+  FGIM_TRY(check_rows(base, n, dim, ld));
+  if (precision != FGIM_BF16 && precision != FGIM_FP8_E4M3)
+    return fail(FGIM_ERR_INVALID_ARG, "precision must be BF16 or FP8_E4M3");
+  if (!codes || (precision == FGIM_FP8_E4M3 && !scales)) return fail(FGIM_ERR_INVALID_ARG, "output is NULL");
+  return quantize_into(base, n, dim, ld, precision, codes, scales, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,416 @@
+// Persistent wavefront-per-query beam search (Algorithm 1) and stage 1 of
+// FGIM, PGs -> k-NNG (Section 4.1, Algorithm 2), for gfx950.
+//
+// One 64-lane wavefront owns one work item at a time and pops the next from
+// a global queue.  Stage-1 item u: score u's local out-neighbours, run the
+// beam search in every other sub-index, and fold everything into a running
+// top-k; search item q: one beam search in one graph.
+//
+// The pool C (at most L <= 64*NR entries) lives in registers, sorted, one
+// entry per lane per register, with an "expanded" bit.  The query row lives
+// in registers too.  Each expansion reads one adjacency row (one id per
+// lane, coalesced), filters ids through a per-wave visited cache in LDS,
+// scores the new ids with P lanes per distance (coalesced float4 row
+// gathers, canonical sum, xor-butterfly reduction) and inserts the keys that
+// beat the current L-th entry.
+//
+// Visited cache.  The cache is direct-mapped and may forget ids (a later id
+// with the same slot overwrites an earlier one); it never reports an id that
+// was not scored in this search.  Forgetting cannot change the result: a
+// re-scored id is either still in the pool -- its key is identical, so the
+// insertion sees a duplicate and drops it -- or it left the pool earlier,
+// which means its key exceeded the L-th key at that time; the L-th key never
+// increases, so the id is dropped again.  The pool evolves exactly as with
+// an exact visited set, for any cache size.
+#pragma once
+
+#include "fgim_device.h"
+
+namespace fgim {
+
+struct SubDev {
+  uint64_t off;
+  const uint32_t* adj;
+  uint32_t n;
+  uint32_t stride;
+  uint32_t entry;
+  uint32_t pad_;
+};
+
+enum RowFmt : int { kF32 = 0, kBF16 = 1, kFP8 = 2 };
+
+struct BeamArgs {
+  const float* X;          // FP32 rows (query rows in stage 1, re-ranking)
+  uint64_t ld;
+  uint32_t nc;             // chunks of 4 coordinates (dim / 4)
+  int metric;
+  const uint16_t* xb;      // BF16 copy (dense, dim per row) or null
+  const uint8_t* x8;       // FP8 copy or null
+  const float* x8s;        // FP8 scales
+  uint32_t dim;
+  const SubDev* subs;
+  uint32_t h;
+  uint32_t L;
+  uint32_t k;              // top-k of stage 1 / results kept by a search
+  uint32_t rerank;         // entries per search re-scored in FP32 (low precision)
+  uint64_t n_items;
+  uint32_t* out_ids;
+  float* out_dist;
+  uint32_t* counter;       // work-queue head, zero at launch
+  const uint32_t* err;     // non-zero: a graph failed validation; do nothing
+  unsigned long long* stats;  // ndc, expansions, searches (nullable)
+  uint32_t vis_log2;       // visited-cache slots = 1 << vis_log2
+  uint32_t P;              // lanes per distance
+  uint32_t M;              // chunks per lane = padded chunk count / P
+  int search_mode;         // 1: items are rows of Q searched in subs[0]
+  const float* Q;
+  uint64_t ldq;
+};
+
+struct WaveLds {
+  uint32_t* vis;
+  uint32_t* cand;   // 64 ids (rows relative to the graph offset)
+  uint64_t* ckey;   // 64 keys
+};
+
+template <int NR>
+struct Pool {
+  uint64_t key[NR];
+  uint32_t exp;     // bit r: entry r*64+lane is expanded
+
+  FGIM_DEV void clear() {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) key[r] = kSentinel;
+    exp = 0;
+  }
+
+  // key of entry `cap-1`, the one a new key has to beat
+  FGIM_DEV uint64_t theta(uint32_t cap) const {
+    uint32_t e = cap - 1;
+    uint64_t v = kSentinel;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (static_cast<uint32_t>(r) == e / 64) v = readlane64(key[r], e % 64);
+    return v;
+  }
+
+  // Insert uniform key c keeping the first `cap` entries; c is dropped when
+  // it is already present (same id => same key) or does not make the cut.
+  FGIM_DEV void insert(uint64_t c, uint32_t cap) {
+    int pos = 0;
+    bool dup = false;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      pos += popc64(ballot(key[r] < c));
+      dup |= ballot(key[r] == c) != 0;
+    }
+    if (dup || static_cast<uint32_t>(pos) >= cap) return;
+    uint64_t carry = kSentinel;
+    uint32_t carry_exp = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      uint64_t last = readlane64(key[r], 63);
+      uint32_t expr = (exp >> r) & 1u;
+      uint32_t last_exp = readlane(expr, 63);
+      uint64_t up = shift_up64(key[r], carry);
+      uint32_t up_exp = shift_up32(expr, carry_exp);
+      int e = r * 64 + lane_id();
+      uint64_t nk = e < pos ? key[r] : (e == pos ? c : up);
+      uint32_t ne = e < pos ? expr : (e == pos ? 0u : up_exp);
+      if (static_cast<uint32_t>(e) >= cap) {
+        nk = kSentinel;
+        ne = 0;
+      }
+      key[r] = nk;
+      exp = (exp & ~(1u << r)) | (ne << r);
+      carry = last;
+      carry_exp = last_exp;
+    }
+  }
+
+  // insert every lane's candidate key (kSentinel = none) that beats theta
+  FGIM_DEV int insert_batch(uint64_t ck, uint32_t cap) {
+    int n = 0;
+    uint64_t th = theta(cap);
+    uint64_t mask = ballot(ck < th);
+    while (mask) {
+      int j = ffs64(mask);
+      uint64_t c = readlane64(ck, j);
+      insert(c, cap);
+      ++n;
+      if (lane_id() == j) ck = kSentinel;
+      th = theta(cap);
+      mask = ballot(ck < th);
+    }
+    return n;
+  }
+
+  // position of the first unexpanded entry, or -1
+  FGIM_DEV int first_unexpanded() const {
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      uint64_t m = ballot(key[r] != kSentinel && !((exp >> r) & 1u));
+      if (m) return r * 64 + ffs64(m);
+    }
+    return -1;
+  }
+
+  FGIM_DEV uint64_t at(int pos) const {
+    uint64_t v = kSentinel;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (r == pos / 64) v = readlane64(key[r], pos % 64);
+    return v;
+  }
+
+  FGIM_DEV void mark_expanded(int pos) {
+    if (lane_id() == pos % 64) exp |= 1u << (pos / 64);
+  }
+};
+
+// Score candidates cand[0..m) (row ids relative to `goff`) against the query
+// held in q; key = (delta, key_off + id).  Group g of P lanes scores
+// candidates g, g+G, ... (G = 64/P).  All lanes must call this.
+template <bool L2, int MMAX, class Row>
+FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, const float4 (&q)[MMAX],
+                          const BeamArgs& a, const WaveLds& lds, int m) {
+  const int P = static_cast<int>(a.P);
+  const int M = static_cast<int>(a.M);
+  const int G = 64 / P;
+  const int g = lane_id() / P;
+  const int l = lane_id() % P;
+  for (int base = 0; base < m; base += G) {
+    const int c = base + g;
+    const bool act = c < m;
+    const uint32_t rid = lds.cand[act ? c : 0];
+    float s[MMAX];
+#pragma unroll
+    for (int mi = 0; mi < MMAX; ++mi) {
+      s[mi] = 0.0f;
+      const uint32_t ch = static_cast<uint32_t>(l + mi * P);
+      if (mi < M && act && ch < a.nc) s[mi] = chunk_sum<L2 ? kL2 : kIP>(q[mi], rows.chunk(goff + rid, ch));
+    }
+#pragma unroll
+    for (int st = MMAX / 2; st >= 1; st /= 2) {
+      if (2 * st <= M) {
+#pragma unroll
+        for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
+      }
+    }
+    float r = s[0];
+#pragma unroll
+    for (int st = 32; st >= 1; st /= 2)
+      if (st < P) r = r + shfl_xor_f(r, st);
+    float d;
+    if (a.metric == kL2) d = finish<kL2>(r);
+    else if (a.metric == kIP) d = finish<kIP>(r);
+    else d = finish<kCos>(r);
+    if (act && l == 0) lds.ckey[c] = make_key(d, key_off + rid);
+  }
+}
+
+FGIM_DEV uint32_t vis_slot(uint32_t v, uint32_t log2) {
+  return (v * 2654435761u) >> (32 - log2);
+}
+
+// Algorithm 1 from ep on the graph whose rows start at goff; leaves the
+// final pool (keys with local ids) in `pool`.
+template <bool L2, int MMAX, int NR, class Row>
+FGIM_DEV void beam_search(Pool<NR>& pool, const Row& rows, uint64_t goff, const uint32_t* adj,
+                          uint32_t stride, uint32_t ep, const float4 (&q)[MMAX], const BeamArgs& a,
+                          const WaveLds& lds, unsigned long long& ndc, unsigned long long& nexp) {
+  const uint32_t S = 1u << a.vis_log2;
+  for (uint32_t i = lane_id(); i < S; i += 64) lds.vis[i] = kNone;
+  if (lane_id() == 0) {
+    lds.vis[vis_slot(ep, a.vis_log2)] = ep;
+    lds.cand[0] = ep;
+  }
+  __syncthreads();
+  score_batch<L2, MMAX>(rows, goff, 0u, q, a, lds, 1);
+  __syncthreads();
+  pool.clear();
+  {
+    uint64_t k0 = lds.ckey[0];
+    if (lane_id() == 0) pool.key[0] = k0;
+  }
+  ndc += 1;
+  for (;;) {
+    const int pos = pool.first_unexpanded();
+    if (pos < 0) break;
+    pool.mark_expanded(pos);
+    nexp += 1;
+    const uint32_t u = key_id(pool.at(pos));
+    for (uint32_t t0 = 0; t0 < stride; t0 += 64) {
+      const uint32_t t = t0 + lane_id();
+      uint32_t v = t < stride ? adj[static_cast<uint64_t>(u) * stride + t] : kNone;
+      const bool valid = v != kNone;
+      const uint32_t slot = valid ? vis_slot(v, a.vis_log2) : 0u;
+      const bool seen = valid && lds.vis[slot] == v;
+      const bool isnew = valid && !seen;
+      if (isnew) lds.vis[slot] = v;
+      const uint64_t nm = ballot(isnew);
+      const int m = popc64(nm);
+      if (m == 0) continue;
+      if (isnew) lds.cand[mbcnt(nm)] = v;
+      __syncthreads();
+      score_batch<L2, MMAX>(rows, goff, 0u, q, a, lds, m);
+      __syncthreads();
+      ndc += static_cast<unsigned long long>(m);
+      const uint64_t ck = lane_id() < m ? lds.ckey[lane_id()] : kSentinel;
+      pool.insert_batch(ck, a.L);
+      __syncthreads();
+    }
+  }
+}
+
+template <bool L2, int MMAX>
+FGIM_DEV void load_query(float4 (&q)[MMAX], const float* row, const BeamArgs& a) {
+  const int P = static_cast<int>(a.P);
+  const int l = lane_id() % P;
+#pragma unroll
+  for (int mi = 0; mi < MMAX; ++mi) {
+    const uint32_t ch = static_cast<uint32_t>(l + mi * P);
+    if (mi < static_cast<int>(a.M) && ch < a.nc)
+      q[mi] = *reinterpret_cast<const float4*>(row + 4ull * ch);
+    else
+      q[mi] = make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+template <bool L2, int FMT, int NR, int MMAX>
+__global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  WaveLds lds;
+  lds.ckey = reinterpret_cast<uint64_t*>(smem);
+  lds.cand = reinterpret_cast<uint32_t*>(smem + 64 * sizeof(uint64_t));
+  lds.vis = lds.cand + 64;
+  if (*a.err != 0u) return;
+
+  RowF32 f32rows{a.X, a.ld};
+  unsigned long long ndc = 0, nexp = 0, nsearch = 0;
+  Pool<NR> pool;
+  Pool<NR> topk;
+  float4 q[MMAX];
+
+  for (;;) {
+    uint32_t item = 0;
+    if (lane_id() == 0) item = atomicAdd(a.counter, 1u);
+    item = uniform(shfl_u(item, 0));
+    if (item >= a.n_items) break;
+
+    if (a.search_mode) {
+      const SubDev g = a.subs[0];
+      load_query<L2, MMAX>(q, a.Q + static_cast<uint64_t>(item) * a.ldq, a);
+      if (FMT == kF32) {
+        beam_search<L2, MMAX, NR>(pool, f32rows, g.off, g.adj, g.stride, g.entry, q, a, lds, ndc, nexp);
+      } else if (FMT == kBF16) {
+        RowBF16 rb{a.xb, a.dim};
+        beam_search<L2, MMAX, NR>(pool, rb, g.off, g.adj, g.stride, g.entry, q, a, lds, ndc, nexp);
+      } else {
+        RowFP8 r8{a.x8, a.x8s, a.dim};
+        beam_search<L2, MMAX, NR>(pool, r8, g.off, g.adj, g.stride, g.entry, q, a, lds, ndc, nexp);
+      }
+      nsearch += 1;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const uint32_t e = r * 64 + lane_id();
+        if (e < a.k) {
+          const uint64_t kk = pool.key[r];
+          a.out_ids[static_cast<uint64_t>(item) * a.k + e] = kk == kSentinel ? kNone : key_id(kk);
+          a.out_dist[static_cast<uint64_t>(item) * a.k + e] = key_dist(kk);
+        }
+      }
+      continue;
+    }
+
+    // ---- stage 1 item: global vertex u ----
+    const uint64_t u = item;
+    uint32_t gi = 0;
+    for (uint32_t i = 0; i < a.h; ++i)
+      if (u >= a.subs[i].off) gi = i;
+    const SubDev si = a.subs[gi];
+    load_query<L2, MMAX>(q, a.X + u * a.ld, a);
+    topk.clear();
+
+    // local candidates C+(u): out-neighbours in G_i, scored on FP32 rows
+    const uint64_t lu = u - si.off;
+    for (uint32_t t0 = 0; t0 < si.stride; t0 += 64) {
+      const uint32_t t = t0 + lane_id();
+      const uint32_t v = t < si.stride ? si.adj[lu * si.stride + t] : kNone;
+      const bool valid = v != kNone;
+      const uint64_t nm = ballot(valid);
+      const int m = popc64(nm);
+      if (m == 0) continue;
+      if (valid) lds.cand[mbcnt(nm)] = v;
+      __syncthreads();
+      score_batch<L2, MMAX>(f32rows, si.off, static_cast<uint32_t>(si.off), q, a, lds, m);
+      __syncthreads();
+      const uint64_t ck = lane_id() < m ? lds.ckey[lane_id()] : kSentinel;
+      topk.insert_batch(ck, a.k);
+      __syncthreads();
+    }
+
+    // cross candidates C-(u): Algorithm 1 in every other G_j
+    for (uint32_t j = 0; j < a.h; ++j) {
+      if (j == gi) continue;
+      const SubDev sj = a.subs[j];
+      if (FMT == kF32) {
+        beam_search<L2, MMAX, NR>(pool, f32rows, sj.off, sj.adj, sj.stride, sj.entry, q, a, lds, ndc, nexp);
+      } else if (FMT == kBF16) {
+        RowBF16 rb{a.xb, a.dim};
+        beam_search<L2, MMAX, NR>(pool, rb, sj.off, sj.adj, sj.stride, sj.entry, q, a, lds, ndc, nexp);
+      } else {
+        RowFP8 r8{a.x8, a.x8s, a.dim};
+        beam_search<L2, MMAX, NR>(pool, r8, sj.off, sj.adj, sj.stride, sj.entry, q, a, lds, ndc, nexp);
+      }
+      nsearch += 1;
+      if (FMT == kF32) {
+        // FP32 keys: fold the search's first min(L, k) entries as global ids
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const uint32_t e = r * 64 + lane_id();
+          uint64_t ck = pool.key[r];
+          if (e >= a.k || ck == kSentinel) ck = kSentinel;
+          else ck = (ck & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(sj.off + key_id(ck));
+          topk.insert_batch(ck, a.k);
+        }
+      } else {
+        // low-precision keys: re-score the first `rerank` entries on FP32 rows
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const uint32_t e = r * 64 + lane_id();
+          const uint64_t pk = pool.key[r];
+          const bool take = e < a.rerank && pk != kSentinel;
+          const uint64_t nm = ballot(take);
+          const int m = popc64(nm);
+          if (m == 0) continue;
+          if (take) lds.cand[mbcnt(nm)] = key_id(pk);
+          __syncthreads();
+          score_batch<L2, MMAX>(f32rows, sj.off, static_cast<uint32_t>(sj.off), q, a, lds, m);
+          __syncthreads();
+          const uint64_t ck = lane_id() < m ? lds.ckey[lane_id()] : kSentinel;
+          topk.insert_batch(ck, a.k);
+          __syncthreads();
+        }
+      }
+    }
+
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t e = r * 64 + lane_id();
+      if (e < a.k) {
+        const uint64_t kk = topk.key[r];
+        a.out_ids[u * a.k + e] = kk == kSentinel ? kNone : key_id(kk);
+        a.out_dist[u * a.k + e] = key_dist(kk);
+      }
+    }
+  }
+
+  if (a.stats && lane_id() == 0) {
+    atomicAdd(&a.stats[0], ndc);
+    atomicAdd(&a.stats[1], nexp);
+    atomicAdd(&a.stats[2], nsearch);
+  }
+}
+
+}  // namespace fgim

@@ -1,0 +1,201 @@
+// Device-side building blocks of the FGIM kernels for gfx950 (CDNA4,
+// 64-lane wavefronts).
+//
+// Ordering keys.  Every list is ordered by (delta, id).  A key packs both in
+// a uint64: the high word is the FP32 bit pattern mapped to an unsigned
+// integer with the same order (flip all bits of negatives, set the sign bit
+// of non-negatives), the low word is the id.  Integer comparison of keys is
+// then the (delta ascending, id ascending) total order.  kSentinel (all
+// ones) sorts after every real key and marks an empty slot.
+//
+// Canonical distance.  The d coordinates form nc = d/4 chunks, padded with
+// zero chunks to N = 2^ceil(log2 nc).  A chunk is summed with four fused
+// multiply-adds from +0; the chunk sums are combined by the stride tree
+// s[c] += s[c + st] for st = N/2 ... 1.  With P lanes per distance (P a
+// power of two <= N), lane l owns chunks l, l+P, ... (M = N/P of them): the
+// strides >= P combine chunks of one lane and run in registers, the strides
+// < P run as xor butterflies across the P lanes.  Because FP32 addition is
+// commutative, every lane of the group ends with the same bits, and those
+// bits do not depend on P.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define FGIM_DEV __device__ __forceinline__
+
+namespace fgim {
+
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+constexpr uint64_t kSentinel = ~0ull;
+constexpr int kWave = 64;
+
+enum Metric : int { kL2 = 0, kIP = 1, kCos = 2 };
+
+FGIM_DEV uint32_t order_bits(float d) {
+  uint32_t u = __float_as_uint(d);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+FGIM_DEV float bits_to_dist(uint32_t o) {
+  uint32_t u = (o & 0x80000000u) ? (o & 0x7FFFFFFFu) : ~o;
+  return __uint_as_float(u);
+}
+
+FGIM_DEV uint64_t make_key(float d, uint32_t id) {
+  return (static_cast<uint64_t>(order_bits(d)) << 32) | id;
+}
+
+FGIM_DEV uint32_t key_id(uint64_t k) { return static_cast<uint32_t>(k); }
+
+FGIM_DEV float key_dist(uint64_t k) {
+  return k == kSentinel ? __builtin_inff() : bits_to_dist(static_cast<uint32_t>(k >> 32));
+}
+
+FGIM_DEV int lane_id() { return __lane_id(); }
+
+FGIM_DEV uint64_t ballot(bool p) { return __ballot(p); }
+
+FGIM_DEV int popc64(uint64_t m) { return __popcll(m); }
+
+// index of the lowest set bit of a non-zero mask
+FGIM_DEV int ffs64(uint64_t m) { return __ffsll(static_cast<unsigned long long>(m)) - 1; }
+
+// number of set bits of m below this lane
+FGIM_DEV int mbcnt(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(m >> 32),
+                                   __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(m), 0));
+}
+
+FGIM_DEV uint32_t readlane(uint32_t v, int l) { return __builtin_amdgcn_readlane(v, l); }
+
+FGIM_DEV uint64_t readlane64(uint64_t v, int l) {
+  uint32_t lo = __builtin_amdgcn_readlane(static_cast<uint32_t>(v), l);
+  uint32_t hi = __builtin_amdgcn_readlane(static_cast<uint32_t>(v >> 32), l);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+FGIM_DEV uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+FGIM_DEV float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, kWave); }
+
+FGIM_DEV uint32_t shfl_u(uint32_t v, int src) { return __shfl(v, src, kWave); }
+
+FGIM_DEV uint64_t shfl64(uint64_t v, int src) {
+  uint32_t lo = __shfl(static_cast<uint32_t>(v), src, kWave);
+  uint32_t hi = __shfl(static_cast<uint32_t>(v >> 32), src, kWave);
+  return (static_cast<uint64_t>(hi) << 32) | lo;
+}
+
+// lane i receives lane i-1's value; lane 0 receives `first`
+FGIM_DEV uint64_t shift_up64(uint64_t v, uint64_t first) {
+  uint64_t up = shfl64(v, lane_id() == 0 ? 0 : lane_id() - 1);
+  return lane_id() == 0 ? first : up;
+}
+
+FGIM_DEV uint32_t shift_up32(uint32_t v, uint32_t first) {
+  uint32_t up = shfl_u(v, lane_id() == 0 ? 0 : lane_id() - 1);
+  return lane_id() == 0 ? first : up;
+}
+
+// ---------------------------------------------------------------------------
+// chunk arithmetic (4 coordinates)
+
+template <int METRIC>
+FGIM_DEV float chunk_sum(const float4 q, const float4 x) {
+  float s = 0.0f;
+  if (METRIC == kL2) {
+    float e0 = q.x - x.x, e1 = q.y - x.y, e2 = q.z - x.z, e3 = q.w - x.w;
+    s = __builtin_fmaf(e0, e0, s);
+    s = __builtin_fmaf(e1, e1, s);
+    s = __builtin_fmaf(e2, e2, s);
+    s = __builtin_fmaf(e3, e3, s);
+  } else {
+    s = __builtin_fmaf(q.x, x.x, s);
+    s = __builtin_fmaf(q.y, x.y, s);
+    s = __builtin_fmaf(q.z, x.z, s);
+    s = __builtin_fmaf(q.w, x.w, s);
+  }
+  return s;
+}
+
+template <int METRIC>
+FGIM_DEV float finish(float r) {
+  float d = METRIC == kL2 ? r : (METRIC == kIP ? -r : 1.0f - r);
+  return d + 0.0f;
+}
+
+// in-lane stride tree over M chunk sums (strides M/2 ... 1)
+template <int M>
+FGIM_DEV float lane_tree(float (&s)[M]) {
+#pragma unroll
+  for (int st = M / 2; st >= 1; st /= 2) {
+#pragma unroll
+    for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
+  }
+  return s[0];
+}
+
+// cross-lane strides P/2 ... 1
+template <int P>
+FGIM_DEV float group_tree(float r) {
+#pragma unroll
+  for (int st = P / 2; st >= 1; st /= 2) r = r + shfl_xor_f(r, st);
+  return r;
+}
+
+// ---------------------------------------------------------------------------
+// row formats
+
+struct RowF32 {
+  const float* base;
+  uint64_t ld;
+  FGIM_DEV float4 chunk(uint64_t row, uint32_t c) const {
+    return *reinterpret_cast<const float4*>(base + row * ld + 4ull * c);
+  }
+};
+
+struct RowBF16 {
+  const uint16_t* base;  // dense rows of `dim`
+  uint32_t dim;
+  FGIM_DEV float4 chunk(uint64_t row, uint32_t c) const {
+    uint2 v = *reinterpret_cast<const uint2*>(base + row * dim + 4ull * c);
+    float4 f;
+    f.x = __uint_as_float(v.x << 16);
+    f.y = __uint_as_float(v.x & 0xFFFF0000u);
+    f.z = __uint_as_float(v.y << 16);
+    f.w = __uint_as_float(v.y & 0xFFFF0000u);
+    return f;
+  }
+};
+
+// OCP E4M3 ("fn"): bias 7, no infinities; decoded exactly into FP32.
+FGIM_DEV float fp8_decode(uint32_t c) {
+  uint32_t s = (c & 0x80u) << 24;
+  uint32_t e = (c >> 3) & 15u, m = c & 7u;
+  float mag;
+  if (e == 0) {
+    mag = static_cast<float>(m) * 0.001953125f;  // m * 2^-9
+  } else {
+    mag = __uint_as_float(((e + 120u) << 23) | (m << 20));
+  }
+  return __uint_as_float(__float_as_uint(mag) | s);
+}
+
+struct RowFP8 {
+  const uint8_t* base;  // dense rows of `dim`
+  const float* scale;
+  uint32_t dim;
+  FGIM_DEV float4 chunk(uint64_t row, uint32_t c) const {
+    uint32_t v = *reinterpret_cast<const uint32_t*>(base + row * dim + 4ull * c);
+    float s = scale[row];
+    float4 f;
+    f.x = s * fp8_decode(v & 0xFFu);
+    f.y = s * fp8_decode((v >> 8) & 0xFFu);
+    f.z = s * fp8_decode((v >> 16) & 0xFFu);
+    f.w = s * fp8_decode(v >> 24);
+    return f;
+  }
+};
+
+}  // namespace fgim

@@ -1,0 +1,60 @@
+// Host helpers shared by the library's translation units: error reporting,
+// stream-ordered scratch, launch helpers and dataset validation.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "fgim.h"
+
+namespace fgim {
+
+fgim_status fail(fgim_status s, const char* fmt, ...);
+int device_cus();
+hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
+fgim_status check_dataset(const fgim_dataset* d, bool need_cross);
+uint32_t tuned_beam_width(const fgim_dataset* d, const fgim_params* p, uint32_t lo);
+
+// Stream-ordered scratch, released (stream-ordered) at scope exit.
+struct Scratch {
+  hipStream_t s;
+  std::vector<void*> ptrs;
+  explicit Scratch(hipStream_t st) : s(st) {}
+  Scratch(const Scratch&) = delete;
+  Scratch& operator=(const Scratch&) = delete;
+  ~Scratch() {
+    for (void* p : ptrs) (void)hipFreeAsync(p, s);
+  }
+  template <class T>
+  fgim_status get(T** out, size_t count) {
+    void* p = nullptr;
+    size_t bytes = std::max<size_t>(count * sizeof(T), 16);
+    hipError_t e = hipMallocAsync(&p, bytes, s);
+    if (e != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return fail(FGIM_ERR_OUT_OF_MEMORY, "scratch allocation of %zu bytes failed", bytes);
+    }
+    ptrs.push_back(p);
+    *out = static_cast<T*>(p);
+    return FGIM_OK;
+  }
+};
+
+}  // namespace fgim
+
+#define FGIM_TRY(x)                 \
+  do {                              \
+    fgim_status st_ = (x);          \
+    if (st_ != FGIM_OK) return st_; \
+  } while (0)
+
+#define HIP_TRY(x)                                                                          \
+  do {                                                                                      \
+    hipError_t e_ = (x);                                                                    \
+    if (e_ != hipSuccess)                                                                   \
+      return ::fgim::fail(FGIM_ERR_DEVICE, "%s failed: %s", #x, hipGetErrorString(e_));     \
+  } while (0)

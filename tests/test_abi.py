@@ -1,0 +1,76 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports
+every entry point of include/fgim.h, and rejects bad arguments before it
+touches the device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2603_21710_amd as fg
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "fgim.h")).read()
+    return sorted(set(re.findall(r"^\S.*?\b(fgim_[a-z0-9_]+)\(", src, re.M)))
+
+
+def test_header_and_binding_agree():
+    assert sorted(fg.EXPORTS) == _declared()
+
+
+def test_library_exports_every_declared_symbol():
+    L = fg.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+
+
+def test_min_beam_width():
+    assert fg.min_beam_width(16, 0, 2) == 16
+    assert fg.min_beam_width(24, 3, 8) == 3
+    assert fg.min_beam_width(32, 40, 4) == 1
+    assert fg.min_beam_width(32, 0, 1) == 0
+
+
+def _dataset(n=100, dim=32, ld=None, subs=None, metric=0, base=0x10000):
+    subs = subs if subs is not None else [(0, 60, 8, 0x20000, 0), (60, 40, 8, 0x30000, 3)]
+    arr = (fg.Subindex * len(subs))(*[fg.Subindex(*s) for s in subs])
+    d = fg.Dataset(base, n, dim, ld or dim, metric, ctypes.addressof(arr), len(subs), None, None)
+    return d, arr
+
+
+@pytest.mark.parametrize("kw,pk", [
+    (dict(dim=30), {}),
+    (dict(dim=8192), {}),
+    (dict(ld=20), {}),
+    (dict(base=0), {}),
+    (dict(base=0x10004), {}),
+    (dict(metric=7), {}),
+    (dict(subs=[(0, 60, 8, 0x20000, 0), (61, 39, 8, 0x30000, 0)]), {}),
+    (dict(subs=[(0, 60, 8, 0x20000, 60), (60, 40, 8, 0x30000, 0)]), {}),
+    (dict(subs=[(0, 60, 0, 0x20000, 0), (60, 40, 8, 0x30000, 0)]), {}),
+    (dict(subs=[(0, 60, 8, 0, 0), (60, 40, 8, 0x30000, 0)]), {}),
+    (dict(subs=[(0, 60, 8, 0x20000, 0)]), {}),
+    ({}, dict(k=0)),
+    ({}, dict(L=0)),
+    ({}, dict(k=200)),
+    ({}, dict(L=300)),
+    ({}, dict(lanes_per_dist=3)),
+    ({}, dict(lanes_per_dist=16)),
+    ({}, dict(visited_slots=1000)),
+])
+def test_bad_arguments_rejected_on_host(kw, pk):
+    d, keep = _dataset(**kw)
+    p = fg.params(**{**dict(k=8, L=16), **pk})
+    rc = fg.lib().fgim_cross_query(ctypes.byref(d), ctypes.byref(p), 0x40000, 0x50000, None, None)
+    assert rc in (1, 5), fg.lib().fgim_last_error()
+    assert fg.lib().fgim_last_error()
+
+
+def test_null_outputs_rejected():
+    d, keep = _dataset()
+    p = fg.params(k=8, L=16)
+    assert fg.lib().fgim_cross_query(ctypes.byref(d), ctypes.byref(p), None, 0x50000, None, None) == 1
+    assert fg.lib().fgim_cross_query(None, ctypes.byref(p), 0x40000, 0x50000, None, None) == 1

@@ -51,7 +51,8 @@ def _knn(X: torch.Tensor, r: int, metric: str, exact: bool):
     sq = (X * X).sum(1)
     ids = torch.empty((n, r), dtype=torch.int64, device=X.device)
     dd = torch.empty((n, r), dtype=X.dtype, device=X.device)
-    block = max(1, min(n, (1 << 27) // max(1, n)))
+    budget = (1 << 30) if X.device.type == "cuda" else (1 << 27)
+    block = max(1, min(n, budget // max(1, n)))
     col = torch.arange(n, device=X.device)
     for s in range(0, n, block):
         e = min(n, s + block)
@@ -72,7 +73,7 @@ def _rng_prune(X: torch.Tensor, ids: torch.Tensor, du: torch.Tensor,
     """Keep candidate v of u iff delta(u, v) < delta(w, v) for every kept w."""
     n, r = ids.shape
     keep = torch.zeros((n, r), dtype=torch.bool, device=X.device)
-    block = max(1, (1 << 24) // max(1, r * r))
+    block = max(1, ((1 << 26) if X.device.type == "cuda" else (1 << 24)) // max(1, r * r))
     for s in range(0, n, block):
         e = min(n, s + block)
         Xc = X[ids[s:e]]                                  # [b, r, d]
