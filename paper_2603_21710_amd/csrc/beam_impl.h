@@ -96,7 +96,8 @@ struct Pool {
 
   // Insert uniform key c keeping the first `cap` entries; c is dropped when
   // it is already present (same id => same key) or does not make the cut.
-  FGIM_DEV void insert(uint64_t c, uint32_t cap) {
+  // The inserted entry's flag bit is `flag`.
+  FGIM_DEV void insert(uint64_t c, uint32_t cap, uint32_t flag = 0) {
     int pos = 0;
     bool dup = false;
 #pragma unroll
@@ -116,7 +117,7 @@ struct Pool {
       uint32_t up_exp = shift_up32(expr, carry_exp);
       int e = r * 64 + lane_id();
       uint64_t nk = e < pos ? key[r] : (e == pos ? c : up);
-      uint32_t ne = e < pos ? expr : (e == pos ? 0u : up_exp);
+      uint32_t ne = e < pos ? expr : (e == pos ? flag : up_exp);
       if (static_cast<uint32_t>(e) >= cap) {
         nk = kSentinel;
         ne = 0;
@@ -129,14 +130,14 @@ struct Pool {
   }
 
   // insert every lane's candidate key (kSentinel = none) that beats theta
-  FGIM_DEV int insert_batch(uint64_t ck, uint32_t cap) {
+  FGIM_DEV int insert_batch(uint64_t ck, uint32_t cap, uint32_t flag = 0) {
     int n = 0;
     uint64_t th = theta(cap);
     uint64_t mask = ballot(ck < th);
     while (mask) {
       int j = ffs64(mask);
       uint64_t c = readlane64(ck, j);
-      insert(c, cap);
+      insert(c, cap, flag);
       ++n;
       if (lane_id() == j) ck = kSentinel;
       th = theta(cap);

@@ -1,0 +1,61 @@
+// Device helpers shared by the refinement and prune kernels: list keys,
+// exclusive scan, CSR construction and the canonical distance between two
+// rows read by a group of P lanes.
+#pragma once
+
+#include "beam_impl.h"
+
+namespace fgim {
+
+constexpr uint8_t kFlagNew = 1;
+constexpr uint8_t kFlagReplaced = 2;
+
+// Exclusive scan of n uint32 counts into out[0..n] (out[n] = total).
+hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* block_tmp,
+                          hipStream_t s);
+uint64_t scan_tmp_words(uint64_t n);
+
+// canonical distance between rows a and b (pointers to row starts), computed
+// by a group of P lanes (sub-lane l); every lane of the group gets the result
+template <int MMAX>
+FGIM_DEV float pair_distance(const float* a, const float* b, int metric, uint32_t nc, int P, int M, int l,
+                             bool act) {
+  float s[MMAX];
+#pragma unroll
+  for (int mi = 0; mi < MMAX; ++mi) {
+    s[mi] = 0.0f;
+    const uint32_t ch = static_cast<uint32_t>(l + mi * P);
+    if (mi < M && act && ch < nc) {
+      const float4 x = *reinterpret_cast<const float4*>(a + 4 * ch);
+      const float4 y = *reinterpret_cast<const float4*>(b + 4 * ch);
+      s[mi] = metric == kL2 ? chunk_sum<kL2>(x, y) : chunk_sum<kIP>(x, y);
+    }
+  }
+#pragma unroll
+  for (int st = MMAX / 2; st >= 1; st /= 2) {
+    if (2 * st <= M) {
+#pragma unroll
+      for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
+    }
+  }
+  float r = s[0];
+#pragma unroll
+  for (int st = 32; st >= 1; st /= 2)
+    if (st < P) r = r + shfl_xor_f(r, st);
+  if (metric == kL2) return finish<kL2>(r);
+  if (metric == kIP) return finish<kIP>(r);
+  return finish<kCos>(r);
+}
+
+// sub-index of global id v given ascending offsets off[0..h)
+FGIM_DEV uint32_t sub_of(const uint64_t* off, uint32_t h, uint32_t v) {
+  uint32_t lo = 0, hi = h;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (v >= off[mid]) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace fgim

@@ -1,0 +1,294 @@
+// Stage 3 of FGIM: k-NNG -> PG (Section 4.3, Algorithm 5), and the
+// three-stage merge entry point.
+//
+//   select   one workgroup per vertex u: the k x k occlusion tile of u's list
+//            (delta(w, v) for every earlier w, canonical FP32, candidate rows
+//            staged in LDS), then the sequential scan of Algorithm 5 over
+//            64-bit masks: v is kept when T(v) = 1 or no kept w has
+//            delta(w, v) <= delta(u, v); at most R are kept.
+//   reverse  CSR of the selected edges by head (count / scan / scatter).
+//   fill     per vertex: first R of its selected neighbours and the vertices
+//            that selected it, (delta, id)-sorted and id-unique.
+#include <string.h>
+
+#include "fgim_internal.h"
+#include "graph_util.h"
+#include "host_util.h"
+
+namespace fgim {
+
+struct SelectArgs {
+  const float* X;
+  uint64_t ld;
+  uint32_t nc;
+  int metric;
+  uint64_t N;
+  uint32_t k, R;
+  const uint32_t* ids;
+  const float* dist;
+  const uint32_t* T;
+  uint32_t* sel_ids;   // N x R
+  float* sel_dist;
+  uint32_t* sel_n;
+  uint32_t P, M;
+  int stage_rows;
+};
+
+template <int MMAX>
+__global__ void __launch_bounds__(256) select_kernel(SelectArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* occl = reinterpret_cast<uint64_t*>(smem);       // k x 2 words
+  uint32_t* vid = reinterpret_cast<uint32_t*>(occl + 2 * a.k);
+  float* vd = reinterpret_cast<float*>(vid + a.k);
+  uint32_t* tv = reinterpret_cast<uint32_t*>(vd + a.k);
+  float* rows = reinterpret_cast<float*>(smem + ((a.k * (16 + 12) + 15) / 16) * 16);
+  const uint32_t d = a.nc * 4;
+  const int P = static_cast<int>(a.P), M = static_cast<int>(a.M);
+  const int gid = threadIdx.x / P, ngroups = 256 / P, l = threadIdx.x % P;
+
+  for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
+    uint32_t cnt = 0;
+    for (uint32_t t = threadIdx.x; t < a.k; t += 256) {
+      const uint32_t v = a.ids[u * a.k + t];
+      vid[t] = v;
+      vd[t] = a.dist[u * a.k + t];
+      tv[t] = v == kNone ? 0u : a.T[v];
+      occl[2 * t] = 0;
+      occl[2 * t + 1] = 0;
+    }
+    __syncthreads();
+    while (cnt < a.k && vid[cnt] != kNone) ++cnt;
+    if (a.stage_rows) {
+      for (uint32_t i = threadIdx.x; i < cnt * a.nc; i += 256) {
+        const uint32_t e = i / a.nc, ch = i % a.nc;
+        *reinterpret_cast<float4*>(rows + static_cast<uint64_t>(e) * d + 4 * ch) =
+            *reinterpret_cast<const float4*>(a.X + static_cast<uint64_t>(vid[e]) * a.ld + 4 * ch);
+      }
+      __syncthreads();
+    }
+    // occlusion tile: bit q of occl[p] set when delta(w_q, v_p) <= delta(u, v_p), q < p
+    const uint32_t slots = cnt * cnt;
+    for (uint32_t s0 = 0; s0 < slots; s0 += ngroups) {
+      const uint32_t s = s0 + gid;
+      const uint32_t p = s / (cnt ? cnt : 1), q = s % (cnt ? cnt : 1);
+      const bool valid = s < slots && q < p && tv[p] != 1u;
+      const float* rw = a.stage_rows ? rows + static_cast<uint64_t>(q) * d : a.X + static_cast<uint64_t>(vid[valid ? q : 0]) * a.ld;
+      const float* rv = a.stage_rows ? rows + static_cast<uint64_t>(p) * d : a.X + static_cast<uint64_t>(vid[valid ? p : 0]) * a.ld;
+      const float dwv = pair_distance<MMAX>(rw, rv, a.metric, a.nc, P, M, l, valid);
+      if (valid && l == 0 && !(vd[p] < dwv)) atomicOr(reinterpret_cast<unsigned long long*>(&occl[2 * p + q / 64]), 1ull << (q % 64));
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      uint64_t kept0 = 0, kept1 = 0;
+      uint32_t ns = 0;
+      for (uint32_t p = 0; p < cnt && ns < a.R; ++p) {
+        const bool keep = tv[p] == 1u || ((occl[2 * p] & kept0) == 0 && (occl[2 * p + 1] & kept1) == 0);
+        if (keep) {
+          if (p < 64) kept0 |= 1ull << p;
+          else kept1 |= 1ull << (p - 64);
+          a.sel_ids[u * a.R + ns] = vid[p];
+          a.sel_dist[u * a.R + ns] = vd[p];
+          ++ns;
+        }
+      }
+      a.sel_n[u] = ns;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void sel_count_kernel(const uint32_t* sel_ids, const uint32_t* sel_n, uint64_t N, uint32_t R, uint32_t* cnt) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < N * R;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    if (i % R < sel_n[i / R]) atomicAdd(&cnt[sel_ids[i]], 1u);
+}
+
+__global__ void sel_scatter_kernel(const uint32_t* sel_ids, const float* sel_dist, const uint32_t* sel_n, uint64_t N,
+                                   uint32_t R, uint32_t* cur, uint64_t* rev) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < N * R;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    if (i % R >= sel_n[i / R]) continue;
+    const uint32_t pos = atomicAdd(&cur[sel_ids[i]], 1u);
+    rev[pos] = make_key(sel_dist[i], static_cast<uint32_t>(i / R));
+  }
+}
+
+template <int NR>
+__global__ void __launch_bounds__(256) fill_kernel(const uint32_t* sel_ids, const float* sel_dist, const uint32_t* sel_n,
+                                                   const uint32_t* roff, const uint64_t* rev, uint64_t N, uint32_t R,
+                                                   uint32_t* pg_ids, uint32_t* pg_deg) {
+  const uint64_t nw = gridDim.x * 4ull;
+  for (uint64_t u = blockIdx.x * 4ull + threadIdx.x / 64; u < N; u += nw) {
+    Pool<NR> out;
+    out.clear();
+    const uint32_t ns = sel_n[u];
+    for (uint32_t b = 0; b < ns; b += 64) {
+      const uint32_t t = b + lane_id();
+      const uint64_t ck = t < ns ? make_key(sel_dist[u * R + t], sel_ids[u * R + t]) : kSentinel;
+      out.insert_batch(ck, R);
+    }
+    const uint32_t b0 = roff[u], b1 = roff[u + 1];
+    for (uint32_t b = b0; b < b1; b += 64) {
+      const uint64_t ck = b + lane_id() < b1 ? rev[b + lane_id()] : kSentinel;
+      out.insert_batch(ck, R);
+    }
+    uint32_t deg = 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t e = r * 64 + lane_id();
+      deg += popc64(ballot(e < R && out.key[r] != kSentinel));
+      if (e < R) pg_ids[u * R + e] = out.key[r] == kSentinel ? kNone : key_id(out.key[r]);
+    }
+    if (lane_id() == 0) pg_deg[u] = deg;
+  }
+}
+
+__global__ void validate_lists_kernel(const uint32_t* ids, uint64_t nk, uint64_t N, uint32_t* err) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    if (ids[i] != kNone && ids[i] >= N) atomicOr(err, 1u);
+}
+
+static uint32_t grid_n(uint64_t n, uint32_t per_block = 256) {
+  const uint64_t b = (n + per_block - 1) / per_block;
+  return static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(b, 1), 65536));
+}
+
+static uint32_t pow2_ceil(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32_t* ids, const float* dist,
+                       const uint32_t* T, uint32_t* pg_ids, uint32_t* pg_deg, hipStream_t s) {
+  FGIM_TRY(check_dataset(d, false));
+  if (!p) return fail(FGIM_ERR_INVALID_ARG, "params is NULL");
+  if (!ids || !dist || !T || !pg_ids || !pg_deg) return fail(FGIM_ERR_INVALID_ARG, "NULL buffer");
+  if (p->k == 0 || p->k > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "k = %u out of 1..%u", p->k, FGIM_MAX_K);
+  if (p->R == 0 || p->R > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "R = %u out of 1..%u", p->R, FGIM_MAX_K);
+  const uint64_t N = d->n_total, k = p->k, R = p->R;
+  if (N * std::max(k, R) >= 0xFFFFFFFFull) return fail(FGIM_ERR_UNSUPPORTED, "N x max(k, R) exceeds 32-bit offsets");
+  const uint32_t nc = d->dim / 4, Nch = pow2_ceil(nc);
+  const uint32_t P = std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, Nch), Nch / 4));
+  const uint32_t M = Nch / P;
+  const size_t head = ((k * (16 + 12) + 15) / 16) * 16;
+  const size_t rows = k * d->dim * 4;
+  const bool stage = head + rows <= 96 * 1024;
+  const size_t smem = head + (stage ? rows : 0);
+
+  Scratch scr(s);
+  uint32_t *sel_ids = nullptr, *sel_n = nullptr, *cnt = nullptr, *off = nullptr, *cur = nullptr, *tmp = nullptr,
+           *err = nullptr;
+  float* sel_dist = nullptr;
+  uint64_t* rev = nullptr;
+  FGIM_TRY(scr.get(&sel_ids, N * R));
+  FGIM_TRY(scr.get(&sel_dist, N * R));
+  FGIM_TRY(scr.get(&sel_n, N));
+  FGIM_TRY(scr.get(&cnt, N + 1));
+  FGIM_TRY(scr.get(&off, N + 1));
+  FGIM_TRY(scr.get(&cur, N + 1));
+  FGIM_TRY(scr.get(&rev, N * R));
+  FGIM_TRY(scr.get(&tmp, scan_tmp_words(N) + 16));
+  FGIM_TRY(scr.get(&err, 4));
+  HIP_TRY(fill_u32(err, 0u, 1, s));
+  hipLaunchKernelGGL(validate_lists_kernel, dim3(grid_n(N * k)), dim3(256), 0, s, ids, N * k, N, err);
+  uint32_t herr = 0;
+  HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n_total");
+
+  SelectArgs sa{d->base, d->ld, nc, d->metric, N, p->k, p->R, ids, dist, T, sel_ids, sel_dist, sel_n, P, M, stage};
+  const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));
+  if (M <= 4) {
+    if (smem > 64 * 1024)
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(select_kernel<4>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(smem)));
+    hipLaunchKernelGGL(select_kernel<4>, dim3(grid), dim3(256), smem, s, sa);
+  } else {
+    if (smem > 64 * 1024)
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(select_kernel<16>), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(smem)));
+    hipLaunchKernelGGL(select_kernel<16>, dim3(grid), dim3(256), smem, s, sa);
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(fill_u32(cnt, 0u, N, s));
+  hipLaunchKernelGGL(sel_count_kernel, dim3(grid_n(N * R)), dim3(256), 0, s, sel_ids, sel_n, N, p->R, cnt);
+  HIP_TRY(exclusive_scan(cnt, off, N, tmp, s));
+  HIP_TRY(hipMemcpyAsync(cur, off, 4 * N, hipMemcpyDeviceToDevice, s));
+  hipLaunchKernelGGL(sel_scatter_kernel, dim3(grid_n(N * R)), dim3(256), 0, s, sel_ids, sel_dist, sel_n, N, p->R, cur, rev);
+  if (R <= 64)
+    hipLaunchKernelGGL(fill_kernel<1>, dim3(grid_n(N, 4)), dim3(256), 0, s, sel_ids, sel_dist, sel_n, off, rev, N, p->R,
+                       pg_ids, pg_deg);
+  else
+    hipLaunchKernelGGL(fill_kernel<2>, dim3(grid_n(N, 4)), dim3(256), 0, s, sel_ids, sel_dist, sel_n, off, rev, N, p->R,
+                       pg_ids, pg_deg);
+  HIP_TRY(hipGetLastError());
+  return FGIM_OK;
+}
+
+fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist,
+                             fgim_stats* stats, hipStream_t s, uint32_t* L_used);
+fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist, uint32_t* T_out,
+                        fgim_stats* stats, hipStream_t s);
+
+}  // namespace fgim
+
+using namespace fgim;
+
+extern "C" {
+
+fgim_status fgim_prune(const fgim_dataset* data, const fgim_params* params, const uint32_t* knn_ids,
+                       const float* knn_dist, const uint32_t* indegree, uint32_t* pg_ids, uint32_t* pg_deg,
+                       void* stream) {
+  fail(FGIM_OK, "");
+  return prune_impl(data, params, knn_ids, knn_dist, indegree, pg_ids, pg_deg, static_cast<hipStream_t>(stream));
+}
+
+fgim_status fgim_merge(const fgim_dataset* data, const fgim_params* params, uint32_t* pg_ids, uint32_t* pg_deg,
+                       uint32_t* entry, fgim_stats* stats, void* stream) {
+  fail(FGIM_OK, "");
+  if (stats) memset(stats, 0, sizeof(*stats));
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  FGIM_TRY(check_dataset(data, true));
+  if (!params || !pg_ids || !pg_deg || !entry) return fail(FGIM_ERR_INVALID_ARG, "NULL argument");
+  if (params->R == 0 || params->R > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "R = %u out of 1..%u", params->R, FGIM_MAX_K);
+  const uint64_t N = data->n_total, k = params->k;
+  Scratch scr(s);
+  uint32_t *ids = nullptr, *T = nullptr;
+  float* dist = nullptr;
+  if (k == 0 || k > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "k = %u out of 1..%u", params->k, FGIM_MAX_K);
+  FGIM_TRY(scr.get(&ids, N * k));
+  FGIM_TRY(scr.get(&dist, N * k));
+  FGIM_TRY(scr.get(&T, N));
+  hipEvent_t ev[4] = {};
+  for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
+  HIP_TRY(hipEventRecord(ev[0], s));
+  fgim_stats st1{}, st2{};
+  FGIM_TRY(cross_query_impl(data, params, ids, dist, stats ? &st1 : nullptr, s, nullptr));
+  HIP_TRY(hipEventRecord(ev[1], s));
+  FGIM_TRY(refine_impl(data, params, ids, dist, T, stats ? &st2 : nullptr, s));
+  HIP_TRY(hipEventRecord(ev[2], s));
+  FGIM_TRY(prune_impl(data, params, ids, dist, T, pg_ids, pg_deg, s));
+  HIP_TRY(hipEventRecord(ev[3], s));
+  HIP_TRY(hipEventSynchronize(ev[3]));
+  uint32_t best = 0;
+  for (uint32_t i = 1; i < data->h; ++i)
+    if (data->subs[i].n > data->subs[best].n) best = i;
+  *entry = static_cast<uint32_t>(data->subs[best].row_offset + data->subs[best].entry);
+  if (stats) {
+    *stats = st1;
+    for (int i = 0; i < 3; ++i) {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+      stats->ms_stage[i] = ms;
+    }
+    stats->proposals = st2.proposals;
+    stats->repaired = st2.repaired;
+    stats->rechecked = st2.rechecked;
+  }
+  for (auto& e : ev) (void)hipEventDestroy(e);
+  return FGIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,766 @@
+// Stage 2 of FGIM: k-NNG refinement (Section 4.2, Algorithm 3) in
+// synchronous rounds, with indegree repair (Algorithm 4) after every round.
+//
+// Lists are held as sorted uint64 keys (delta, id) plus a flag word per slot
+// (bit 0 new, bit 1 replaced).  One round is a fixed sequence of kernels
+// with no host round trip, so it can be captured once in a hipGraph and
+// replayed:
+//   Visit   rev_count / scan / rev_scatter: reverse lists of new and old
+//           entries as a CSR (segment 2v: u with v new in u's list, 2v+1: old)
+//   Update  join: one workgroup per vertex u builds Cn(u) = fwd_new U
+//           rev_new and Co(u) = (fwd_old U rev_old) \ Cn (reverse lists cut
+//           to their k_rev best by (delta, u)), stages the candidate rows in
+//           LDS and scores every cross-sub-index pair of Cn^2 U Cn x Co in
+//           canonical FP32; a pair proposes each end to the other when it
+//           beats that end's current worst entry.  Proposals are appended to
+//           a global buffer and grouped by target with a CSR pass.
+//   apply   per target: first k of the snapshot list (entries turn old) and
+//           its proposals (entries new), one entry per id.
+//   repair  indegree histogram, ordered list of zero-indegree vertices, then
+//           Algorithm 4 in one wavefront (it is sequential by definition).
+// Every step's result is independent of scheduling: CSR segments are
+// consumed through order-independent top-k selections under the total
+// order of keys, so the output is bit-identical to the sequential oracle.
+#include <string.h>
+
+#include "fgim_internal.h"
+#include "graph_util.h"
+#include "host_util.h"
+
+namespace fgim {
+
+// ---------------------------------------------------------------------------
+// exclusive scan (three passes, 1024 elements per block)
+
+constexpr uint32_t kScanBlock = 1024;
+
+__global__ void __launch_bounds__(256) scan_sums_kernel(const uint32_t* in, uint64_t n, uint32_t* sums) {
+  __shared__ uint32_t red[256];
+  const uint64_t base = blockIdx.x * static_cast<uint64_t>(kScanBlock);
+  uint32_t s = 0;
+  for (uint32_t i = threadIdx.x; i < kScanBlock; i += 256) {
+    const uint64_t j = base + i;
+    if (j < n) s += in[j];
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int st = 128; st > 0; st >>= 1) {
+    if (threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = red[0];
+}
+
+// exclusive scan of the nb block sums in place; sums[nb] = total
+__global__ void __launch_bounds__(1024) scan_top_kernel(uint32_t* sums, uint64_t nb) {
+  __shared__ uint32_t buf[1024];
+  uint32_t carry = 0;
+  for (uint64_t base = 0; base < nb; base += 1024) {
+    const uint64_t j = base + threadIdx.x;
+    const uint32_t v = j < nb ? sums[j] : 0u;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {
+      const uint32_t t = threadIdx.x >= static_cast<uint32_t>(off) ? buf[threadIdx.x - off] : 0u;
+      __syncthreads();
+      buf[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (j < nb) sums[j] = carry + buf[threadIdx.x] - v;
+    const uint32_t tot = buf[1023];
+    __syncthreads();
+    carry += tot;
+  }
+  if (threadIdx.x == 0) sums[nb] = carry;
+}
+
+__global__ void __launch_bounds__(256) scan_apply_kernel(const uint32_t* in, uint64_t n, const uint32_t* sums,
+                                                         uint64_t nb, uint32_t* out) {
+  __shared__ uint32_t tsum[256];
+  const uint64_t base = blockIdx.x * static_cast<uint64_t>(kScanBlock) + threadIdx.x * 4ull;
+  uint32_t v[4], run = 0;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    v[i] = base + i < n ? in[base + i] : 0u;
+    run += v[i];
+  }
+  tsum[threadIdx.x] = run;
+  __syncthreads();
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t t = threadIdx.x >= static_cast<uint32_t>(off) ? tsum[threadIdx.x - off] : 0u;
+    __syncthreads();
+    tsum[threadIdx.x] += t;
+    __syncthreads();
+  }
+  uint32_t acc = sums[blockIdx.x] + tsum[threadIdx.x] - run;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    if (base + i < n) out[base + i] = acc;
+    acc += v[i];
+  }
+  if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = sums[nb];
+}
+
+uint64_t scan_tmp_words(uint64_t n) { return (n + kScanBlock - 1) / kScanBlock + 1; }
+
+hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* tmp, hipStream_t s) {
+  const uint64_t nb = (n + kScanBlock - 1) / kScanBlock;
+  if (nb == 0) return fill_u32(out, 0u, 1, s);
+  hipLaunchKernelGGL(scan_sums_kernel, dim3(static_cast<uint32_t>(nb)), dim3(256), 0, s, in, n, tmp);
+  hipLaunchKernelGGL(scan_top_kernel, dim3(1), dim3(1024), 0, s, tmp, nb);
+  hipLaunchKernelGGL(scan_apply_kernel, dim3(static_cast<uint32_t>(nb)), dim3(256), 0, s, in, n, tmp, nb, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// list conversion
+
+__global__ void to_keys_kernel(const uint32_t* ids, const float* dist, uint64_t nk, uint64_t* keys,
+                               uint32_t* flags) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t v = ids[i];
+    keys[i] = v == kNone ? kSentinel : make_key(dist[i] + 0.0f, v);
+    flags[i] = v == kNone ? 0u : kFlagNew;
+  }
+}
+
+__global__ void from_keys_kernel(const uint64_t* keys, uint64_t nk, uint32_t* ids, float* dist) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t k = keys[i];
+    ids[i] = k == kSentinel ? kNone : key_id(k);
+    dist[i] = key_dist(k);
+  }
+}
+
+__global__ void copy_u32_kernel(const uint32_t* a, uint32_t* b, uint64_t n) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    b[i] = a[i];
+}
+
+// ---------------------------------------------------------------------------
+// Visit: reverse lists
+
+__global__ void rev_count_kernel(const uint64_t* keys, const uint32_t* flags, uint64_t nk, uint32_t* cnt) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t k = keys[i];
+    if (k == kSentinel) continue;
+    const uint32_t seg = 2u * key_id(k) + ((flags[i] & kFlagNew) ? 0u : 1u);
+    atomicAdd(&cnt[seg], 1u);
+  }
+}
+
+// reverse entry of v in u's list: key (stored delta, u)
+__global__ void rev_scatter_kernel(const uint64_t* keys, const uint32_t* flags, uint64_t nk, uint32_t k,
+                                   uint32_t* cur, uint64_t* rev) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t kk = keys[i];
+    if (kk == kSentinel) continue;
+    const uint32_t seg = 2u * key_id(kk) + ((flags[i] & kFlagNew) ? 0u : 1u);
+    const uint32_t pos = atomicAdd(&cur[seg], 1u);
+    rev[pos] = (kk & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(i / k);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Update: the local join
+
+struct JoinArgs {
+  const float* X;
+  uint64_t ld;
+  uint32_t nc;
+  int metric;
+  uint64_t N;
+  uint32_t k;
+  uint32_t k_rev;
+  const uint64_t* keys;      // snapshot lists
+  const uint32_t* flags;     // flags before this round's Visit
+  const uint32_t* rev_off;   // 2N+1
+  const uint64_t* rev;       // reverse entries
+  const uint64_t* sub_off;   // h offsets
+  uint32_t h;
+  uint32_t cap;              // capacity of the proposal buffer
+  uint32_t* ptotal;          // proposals emitted (may exceed cap)
+  uint32_t* ptgt;
+  uint64_t* pkey;
+  uint32_t P, M;
+  uint32_t ccap;             // max |Cn| + |Co| = 2 (k + k_rev)
+  int stage_rows;            // candidate rows copied to LDS
+};
+
+// top-k_rev of a reverse segment by key, appended to list (ids) via counter
+template <int NR>
+FGIM_DEV void rev_top(const uint64_t* seg, uint32_t len, uint32_t krev, uint32_t* list, uint32_t* cnt) {
+  if (len <= krev) {
+    for (uint32_t i = lane_id(); i < len; i += 64) list[atomicAdd(cnt, 1u)] = key_id(seg[i]);
+    return;
+  }
+  Pool<NR> top;
+  top.clear();
+  for (uint32_t b = 0; b < len; b += 64) {
+    const uint64_t ck = b + lane_id() < len ? seg[b + lane_id()] : kSentinel;
+    top.insert_batch(ck, krev);
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const uint32_t e = r * 64 + lane_id();
+    if (e < krev && top.key[r] != kSentinel) list[atomicAdd(cnt, 1u)] = key_id(top.key[r]);
+  }
+}
+
+// wave-aggregated append of (tgt, key) for lanes with `emit`
+FGIM_DEV void emit_proposal(const JoinArgs& a, bool emit, uint32_t tgt, uint64_t key) {
+  const uint64_t m = ballot(emit);
+  if (!m) return;
+  uint32_t base = 0;
+  const int leader = ffs64(m);
+  if (lane_id() == leader) base = atomicAdd(a.ptotal, static_cast<uint32_t>(popc64(m)));
+  base = readlane(base, leader);
+  if (emit) {
+    const uint32_t pos = base + static_cast<uint32_t>(mbcnt(m));
+    if (pos < a.cap) {
+      a.ptgt[pos] = tgt;
+      a.pkey[pos] = key;
+    }
+  }
+}
+
+template <int NR, int MMAX>
+__global__ void __launch_bounds__(256) join_kernel(JoinArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t C = a.ccap;
+  uint32_t* arr_n = reinterpret_cast<uint32_t*>(smem);          // C
+  uint32_t* arr_o = arr_n + C;                                  // C
+  uint32_t* cid = arr_o + C;                                    // C: Cn then Co
+  uint32_t* cg = cid + C;                                       // sub-index
+  uint64_t* cw = reinterpret_cast<uint64_t*>(cg + C);           // worst key of the list
+  uint32_t* counters = reinterpret_cast<uint32_t*>(cw + C);     // 8
+  float* rows = reinterpret_cast<float*>(counters + 8);         // C x d (optional)
+  const uint32_t d = a.nc * 4;
+  const int wave = threadIdx.x / 64;
+  const int P = static_cast<int>(a.P);
+  const int M = static_cast<int>(a.M);
+  const int gid = threadIdx.x / P;
+  const int ngroups = 256 / P;
+  const int l = threadIdx.x % P;
+
+  for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
+    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+    __syncthreads();
+    // forward entries split by flag
+    for (uint32_t t = threadIdx.x; t < a.k; t += 256) {
+      const uint64_t kk = a.keys[u * a.k + t];
+      if (kk == kSentinel) continue;
+      if (a.flags[u * a.k + t] & kFlagNew) arr_n[atomicAdd(&counters[0], 1u)] = key_id(kk);
+      else arr_o[atomicAdd(&counters[1], 1u)] = key_id(kk);
+    }
+    // reverse entries, cut to k_rev by key
+    if (wave < 2) {
+      const uint32_t seg = 2u * static_cast<uint32_t>(u) + wave;
+      const uint32_t b0 = a.rev_off[seg], b1 = a.rev_off[seg + 1];
+      rev_top<NR>(a.rev + b0, b1 - b0, a.k_rev, wave == 0 ? arr_n : arr_o, &counters[wave]);
+    }
+    __syncthreads();
+    const uint32_t nn0 = counters[0], no0 = counters[1];
+    // Cn: unique ids of arr_n
+    for (uint32_t i = threadIdx.x; i < nn0; i += 256) {
+      const uint32_t v = arr_n[i];
+      bool dup = false;
+      for (uint32_t j = 0; j < i && !dup; ++j) dup = arr_n[j] == v;
+      if (!dup) cid[atomicAdd(&counters[2], 1u)] = v;
+    }
+    __syncthreads();
+    const uint32_t nn = counters[2];
+    // Co: unique ids of arr_o that are not in Cn
+    for (uint32_t i = threadIdx.x; i < no0; i += 256) {
+      const uint32_t v = arr_o[i];
+      bool dup = false;
+      for (uint32_t j = 0; j < i && !dup; ++j) dup = arr_o[j] == v;
+      for (uint32_t j = 0; j < nn && !dup; ++j) dup = cid[j] == v;
+      if (!dup) cid[nn + atomicAdd(&counters[3], 1u)] = v;
+    }
+    __syncthreads();
+    const uint32_t no = counters[3];
+    const uint32_t c = nn + no;
+    for (uint32_t i = threadIdx.x; i < c; i += 256) {
+      const uint32_t v = cid[i];
+      cg[i] = sub_of(a.sub_off, a.h, v);
+      cw[i] = a.keys[static_cast<uint64_t>(v) * a.k + a.k - 1];
+    }
+    if (a.stage_rows) {
+      for (uint32_t i = threadIdx.x; i < c * a.nc; i += 256) {
+        const uint32_t e = i / a.nc, ch = i % a.nc;
+        *reinterpret_cast<float4*>(rows + static_cast<uint64_t>(e) * d + 4 * ch) =
+            *reinterpret_cast<const float4*>(a.X + static_cast<uint64_t>(cid[e]) * a.ld + 4 * ch);
+      }
+    }
+    __syncthreads();
+    // pairs: slot s -> (i, j), i in Cn, j in Cn (j > i) or Co
+    const uint32_t width = c;
+    const uint64_t slots = static_cast<uint64_t>(nn) * width;
+    for (uint64_t s0 = 0; s0 < slots; s0 += ngroups) {
+      const uint64_t s = s0 + gid;
+      bool valid = s < slots;
+      uint32_t i = 0, j = 0;
+      if (valid) {
+        i = static_cast<uint32_t>(s / width);
+        j = static_cast<uint32_t>(s % width);
+        valid = (j >= nn || j > i) && cg[i] != cg[j];
+      }
+      const float* ra = a.stage_rows ? rows + static_cast<uint64_t>(i) * d : a.X + static_cast<uint64_t>(cid[i]) * a.ld;
+      const float* rb = a.stage_rows ? rows + static_cast<uint64_t>(j) * d : a.X + static_cast<uint64_t>(cid[j]) * a.ld;
+      const float dd = pair_distance<MMAX>(ra, rb, a.metric, a.nc, P, M, l, valid);
+      const uint32_t va = valid ? cid[i] : 0u, vb = valid ? cid[j] : 0u;
+      const uint64_t to_a = make_key(dd, vb), to_b = make_key(dd, va);
+      const bool lead = valid && l == 0;
+      emit_proposal(a, lead && to_a < cw[i], va, to_a);
+      emit_proposal(a, lead && to_b < cw[j], vb, to_b);
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// proposals grouped by target, then applied
+
+__global__ void prop_count_kernel(const uint32_t* ptgt, const uint32_t* ptotal, uint32_t cap, uint32_t* cnt) {
+  const uint32_t n = min(*ptotal, cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    atomicAdd(&cnt[ptgt[i]], 1u);
+}
+
+__global__ void prop_scatter_kernel(const uint32_t* ptgt, const uint64_t* pkey, const uint32_t* ptotal, uint32_t cap,
+                                    uint32_t* cur, uint64_t* sorted) {
+  const uint32_t n = min(*ptotal, cap);
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
+    sorted[atomicAdd(&cur[ptgt[i]], 1u)] = pkey[i];
+}
+
+// first k of snapshot (old) U proposals (new), one entry per id; every
+// list's new entries turn old
+template <int NR>
+__global__ void __launch_bounds__(256) apply_kernel(uint64_t* keys, uint32_t* flags, uint64_t N, uint32_t k,
+                                                    const uint32_t* poff, const uint64_t* sorted,
+                                                    uint32_t* ptotal_max, const uint32_t* ptotal) {
+  const uint64_t wave = blockIdx.x * 4ull + threadIdx.x / 64;
+  const uint64_t nw = gridDim.x * 4ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    atomicMax(ptotal_max, *ptotal);
+    atomicAdd(ptotal_max + 2, *ptotal);
+  }
+  for (uint64_t a = wave; a < N; a += nw) {
+    Pool<NR> list;
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t e = r * 64 + lane_id();
+      list.key[r] = e < k ? keys[a * k + e] : kSentinel;
+    }
+    list.exp = 0;
+    const uint32_t b0 = poff[a], b1 = poff[a + 1];
+    for (uint32_t b = b0; b < b1; b += 64) {
+      const uint64_t ck = b + lane_id() < b1 ? sorted[b + lane_id()] : kSentinel;
+      list.insert_batch(ck, k, 1u);
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t e = r * 64 + lane_id();
+      if (e < k) {
+        keys[a * k + e] = list.key[r];
+        flags[a * k + e] = (list.exp >> r) & 1u;
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// indegree and repair
+
+__global__ void indegree_kernel(const uint64_t* keys, uint64_t nk, uint32_t* T) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t kk = keys[i];
+    if (kk != kSentinel) atomicAdd(&T[key_id(kk)], 1u);
+  }
+}
+
+__global__ void zero_mask_kernel(const uint32_t* T, uint64_t N, uint32_t* mask) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < N;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    mask[i] = T[i] == 0u ? 1u : 0u;
+}
+
+__global__ void zero_compact_kernel(const uint32_t* mask, const uint32_t* off, uint64_t N, uint32_t* zero) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < N;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    if (mask[i]) zero[off[i]] = static_cast<uint32_t>(i);
+}
+
+FGIM_DEV uint64_t ld_agent64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+FGIM_DEV uint32_t ld_agent32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Algorithm 4 in one wavefront.  Zero-indegree vertices v* in ascending id;
+// neighbours v of v* from the closest; in N(v) the farthest entry that is not
+// marked replaced and whose indegree exceeds 1 is evicted, or a free slot is
+// used; v* enters N(v) at its sorted place, flagged new and replaced.
+// Lists of the v* themselves never change during the pass (no list holds a
+// zero-indegree vertex before its own turn).
+template <int NR>
+__global__ void __launch_bounds__(64) repair_kernel(uint64_t* keys, uint32_t* flags, uint32_t* T, const uint32_t* zero,
+                                                    const uint32_t* zcount, uint32_t k, uint32_t* nrep) {
+  const uint32_t Z = *zcount;
+  uint32_t fixed = 0;
+  for (uint32_t zi = 0; zi < Z; ++zi) {
+    const uint32_t vs = zero[zi];
+    for (uint32_t s = 0; s < k; ++s) {
+      const uint64_t ks = keys[static_cast<uint64_t>(vs) * k + s];
+      if (ks == kSentinel) break;
+      const uint32_t v = key_id(ks);
+      const uint64_t nk = (ks & 0xFFFFFFFF00000000ull) | vs;
+      uint64_t lk[NR];
+      uint32_t lf[NR];
+      bool cand[NR];
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const uint32_t e = r * 64 + lane_id();
+        lk[r] = e < k ? ld_agent64(&keys[static_cast<uint64_t>(v) * k + e]) : kSentinel;
+        lf[r] = e < k ? ld_agent32(&flags[static_cast<uint64_t>(v) * k + e]) : 0u;
+      }
+      uint64_t lastk = kSentinel;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (static_cast<uint32_t>(r) == (k - 1) / 64) lastk = readlane64(lk[r], (k - 1) % 64);
+      int drop = -1;
+      if (lastk != kSentinel) {
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+          const uint32_t e = r * 64 + lane_id();
+          cand[r] = e < k && !(lf[r] & kFlagReplaced) && ld_agent32(&T[key_id(lk[r])]) > 1u;
+        }
+#pragma unroll
+        for (int r = NR - 1; r >= 0; --r) {
+          const uint64_t m = ballot(cand[r]);
+          if (drop < 0 && m) drop = r * 64 + 63 - __clzll(static_cast<long long>(m));
+        }
+        if (drop < 0) continue;
+      }
+      // new position of every kept entry, and of v*
+      int pos = 0;
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int e = r * 64 + lane_id();
+        pos += popc64(ballot(e != drop && lk[r] < nk));
+      }
+      uint64_t dk = kSentinel;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (drop >= 0 && r == drop / 64) dk = readlane64(lk[r], drop % 64);
+      if (drop >= 0 && lane_id() == 0) {
+        const uint32_t vp = key_id(dk);
+        __hip_atomic_store(&T[vp], ld_agent32(&T[vp]) - 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const int e = r * 64 + lane_id();
+        if (e >= static_cast<int>(k) || e == drop || lk[r] == kSentinel) continue;
+        int ne = e - (drop >= 0 && e > drop ? 1 : 0);
+        if (ne >= pos) ++ne;
+        if (ne < static_cast<int>(k)) {
+          keys[static_cast<uint64_t>(v) * k + ne] = lk[r];
+          flags[static_cast<uint64_t>(v) * k + ne] = lf[r];
+        }
+      }
+      if (lane_id() == 0) {
+        keys[static_cast<uint64_t>(v) * k + pos] = nk;
+        flags[static_cast<uint64_t>(v) * k + pos] = kFlagNew | kFlagReplaced;
+        __hip_atomic_store(&T[vs], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
+      __threadfence();
+      ++fixed;
+      break;
+    }
+  }
+  if (lane_id() == 0) atomicAdd(nrep, fixed);
+}
+
+// ---------------------------------------------------------------------------
+// host driver
+
+struct RefineBufs {
+  uint64_t* keys;
+  uint32_t* flags;
+  uint32_t* rev_cnt;
+  uint32_t* rev_off;
+  uint32_t* rev_cur;
+  uint64_t* rev;
+  uint32_t* ptgt;
+  uint64_t* pkey;
+  uint32_t* pcnt;
+  uint32_t* poff;
+  uint32_t* pcur;
+  uint64_t* psorted;
+  uint32_t* T;
+  uint32_t* zmask;
+  uint32_t* zoff;
+  uint32_t* zero;
+  uint32_t* hdr;  // [0] proposals this round, [1] max per round, [2] repaired, [3] sum
+  uint32_t* scan_tmp;
+  uint64_t* sub_off;
+};
+
+static uint32_t grid_for(uint64_t n, uint32_t per_block = 256) {
+  const uint64_t b = (n + per_block - 1) / per_block;
+  return static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(b, 1), 65536));
+}
+
+hipError_t launch_join(const JoinArgs& ja, int nr, int mmax, uint32_t grid, size_t smem, hipStream_t s) {
+#define FGIM_JOIN_CASE(NR_, MM_)                                                               \
+  if (nr == NR_ && mmax == MM_) {                                                              \
+    hipLaunchKernelGGL((join_kernel<NR_, MM_>), dim3(grid), dim3(256), smem, s, ja);           \
+    return hipGetLastError();                                                                  \
+  }
+  FGIM_JOIN_CASE(1, 4)
+  FGIM_JOIN_CASE(2, 4)
+  FGIM_JOIN_CASE(1, 16)
+  FGIM_JOIN_CASE(2, 16)
+#undef FGIM_JOIN_CASE
+  return hipErrorInvalidValue;
+}
+
+struct RoundPlan {
+  uint64_t N;
+  uint32_t k, k_rev, cap;
+  bool repair;
+  JoinArgs ja;
+  int nr, mmax;
+  uint32_t join_grid;
+  size_t join_smem;
+};
+
+// one refinement round; only kernel launches (graph-capturable)
+hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
+  const uint64_t N = rp.N, nk = N * rp.k;
+  hipError_t e;
+  // Visit
+  if ((e = fill_u32(b.rev_cnt, 0u, 2 * N, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(rev_count_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, b.rev_cnt);
+  if ((e = exclusive_scan(b.rev_cnt, b.rev_off, 2 * N, b.scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(2 * N)), dim3(256), 0, s, b.rev_off, b.rev_cur, 2 * N);
+  hipLaunchKernelGGL(rev_scatter_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, b.rev_cur,
+                     b.rev);
+  // Update
+  if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
+  if ((e = launch_join(rp.ja, rp.nr, rp.mmax, rp.join_grid, rp.join_smem, s)) != hipSuccess) return e;
+  if ((e = fill_u32(b.pcnt, 0u, N, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(prop_count_kernel, dim3(4096), dim3(256), 0, s, b.ptgt, b.hdr, rp.cap, b.pcnt);
+  if ((e = exclusive_scan(b.pcnt, b.poff, N, b.scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.poff, b.pcur, N);
+  hipLaunchKernelGGL(prop_scatter_kernel, dim3(4096), dim3(256), 0, s, b.ptgt, b.pkey, b.hdr, rp.cap, b.pcur,
+                     b.psorted);
+  if (rp.nr == 1)
+    hipLaunchKernelGGL(apply_kernel<1>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, b.poff,
+                       b.psorted, b.hdr + 1, b.hdr);
+  else
+    hipLaunchKernelGGL(apply_kernel<2>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, b.poff,
+                       b.psorted, b.hdr + 1, b.hdr);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!rp.repair) return hipSuccess;
+  // indegree repair
+  if ((e = fill_u32(b.T, 0u, N, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, b.T);
+  hipLaunchKernelGGL(zero_mask_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, N, b.zmask);
+  if ((e = exclusive_scan(b.zmask, b.zoff, N, b.scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(zero_compact_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.zmask, b.zoff, N, b.zero);
+  if (rp.nr == 1)
+    hipLaunchKernelGGL(repair_kernel<1>, dim3(1), dim3(64), 0, s, b.keys, b.flags, b.T, b.zero, b.zoff + N, rp.k,
+                       b.hdr + 2);
+  else
+    hipLaunchKernelGGL(repair_kernel<2>, dim3(1), dim3(64), 0, s, b.keys, b.flags, b.T, b.zero, b.zoff + N, rp.k,
+                       b.hdr + 2);
+  return hipGetLastError();
+}
+
+uint32_t ceil_pow2_u(uint32_t x) {
+  uint32_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist, uint32_t* T_out,
+                        fgim_stats* stats, hipStream_t s) {
+  FGIM_TRY(check_dataset(d, false));
+  if (!p) return fail(FGIM_ERR_INVALID_ARG, "params is NULL");
+  if (!ids || !dist) return fail(FGIM_ERR_INVALID_ARG, "lists are NULL");
+  if (p->k == 0 || p->k > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "k = %u out of 1..%u", p->k, FGIM_MAX_K);
+  const uint32_t k_rev = p->k_rev ? p->k_rev : p->k;
+  if (k_rev > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "k_rev = %u > %u", k_rev, FGIM_MAX_K);
+  const uint64_t N = d->n_total, nk = N * p->k;
+  if (nk >= 0xFFFFFFFFull || 2 * N + 1 >= 0xFFFFFFFFull)
+    return fail(FGIM_ERR_UNSUPPORTED, "N x k = %llu list entries exceed 32-bit offsets", (unsigned long long)nk);
+  const bool repair = !(p->flags & FGIM_FLAG_NO_REPAIR);
+
+  const uint32_t dim = d->dim, nc = dim / 4;
+  const uint32_t Nch = ceil_pow2_u(nc);
+  const uint32_t P = std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, Nch), Nch / 4));
+  const uint32_t M = Nch / P;
+  const uint32_t ccap = 2 * (p->k + k_rev);
+  const size_t base_smem = static_cast<size_t>(ccap) * (4 * 4 + 8) + 8 * 4;
+  const size_t rows_smem = static_cast<size_t>(ccap) * dim * 4;
+  const bool stage_rows = base_smem + rows_smem <= 96 * 1024;
+
+  uint64_t cap = std::max<uint64_t>(N * std::max<uint32_t>(4 * p->k, 64), 1 << 16);
+  cap = std::min<uint64_t>(cap, 0xF0000000ull);
+
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    Scratch scr(s);
+    RefineBufs b{};
+    FGIM_TRY(scr.get(&b.keys, nk));
+    FGIM_TRY(scr.get(&b.flags, nk));
+    FGIM_TRY(scr.get(&b.rev_cnt, 2 * N + 1));
+    FGIM_TRY(scr.get(&b.rev_off, 2 * N + 1));
+    FGIM_TRY(scr.get(&b.rev_cur, 2 * N + 1));
+    FGIM_TRY(scr.get(&b.rev, nk));
+    FGIM_TRY(scr.get(&b.ptgt, cap));
+    FGIM_TRY(scr.get(&b.pkey, cap));
+    FGIM_TRY(scr.get(&b.pcnt, N + 1));
+    FGIM_TRY(scr.get(&b.poff, N + 1));
+    FGIM_TRY(scr.get(&b.pcur, N + 1));
+    FGIM_TRY(scr.get(&b.psorted, cap));
+    FGIM_TRY(scr.get(&b.T, N));
+    FGIM_TRY(scr.get(&b.zmask, N + 1));
+    FGIM_TRY(scr.get(&b.zoff, N + 1));
+    FGIM_TRY(scr.get(&b.zero, N + 1));
+    FGIM_TRY(scr.get(&b.hdr, 4));
+    FGIM_TRY(scr.get(&b.scan_tmp, scan_tmp_words(2 * N + 1) + 16));
+    FGIM_TRY(scr.get(&b.sub_off, d->h));
+    std::vector<uint64_t> hoff(d->h);
+    for (uint32_t i = 0; i < d->h; ++i) hoff[i] = d->subs[i].row_offset;
+    HIP_TRY(hipMemcpyAsync(b.sub_off, hoff.data(), 8 * d->h, hipMemcpyHostToDevice, s));
+    HIP_TRY(fill_u32(b.hdr, 0u, 4, s));
+    hipLaunchKernelGGL(to_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, ids, dist, nk, b.keys, b.flags);
+    HIP_TRY(hipGetLastError());
+
+    RoundPlan rp{};
+    rp.N = N;
+    rp.k = p->k;
+    rp.k_rev = k_rev;
+    rp.cap = static_cast<uint32_t>(cap);
+    rp.repair = repair;
+    rp.nr = std::max(p->k, k_rev) <= 64 ? 1 : 2;
+    rp.mmax = M <= 4 ? 4 : 16;
+    JoinArgs& ja = rp.ja;
+    ja.X = d->base;
+    ja.ld = d->ld;
+    ja.nc = nc;
+    ja.metric = d->metric;
+    ja.N = N;
+    ja.k = p->k;
+    ja.k_rev = k_rev;
+    ja.keys = b.keys;
+    ja.flags = b.flags;
+    ja.rev_off = b.rev_off;
+    ja.rev = b.rev;
+    ja.sub_off = b.sub_off;
+    ja.h = d->h;
+    ja.cap = rp.cap;
+    ja.ptotal = b.hdr;
+    ja.ptgt = b.ptgt;
+    ja.pkey = b.pkey;
+    ja.P = P;
+    ja.M = M;
+    ja.ccap = ccap;
+    ja.stage_rows = stage_rows;
+    rp.join_smem = base_smem + (stage_rows ? rows_smem : 0);
+    rp.join_grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));
+    if (rp.join_smem > 64 * 1024)
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(rp.nr == 1 ? (rp.mmax == 4 ? join_kernel<1, 4> : join_kernel<1, 16>)
+                                                                           : (rp.mmax == 4 ? join_kernel<2, 4> : join_kernel<2, 16>)),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(rp.join_smem)));
+
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (stats) {
+      HIP_TRY(hipEventCreate(&e0));
+      HIP_TRY(hipEventCreate(&e1));
+      HIP_TRY(hipEventRecord(e0, s));
+    }
+    const bool capture = !(p->flags & FGIM_FLAG_NO_GRAPH_CAPTURE) && p->rounds > 1;
+    if (capture) {
+      // Rounds are captured once and replayed.  Capture needs a stream other
+      // than the legacy null stream, so the rounds run on a library stream
+      // ordered after, and before, the caller's stream by events.
+      hipStream_t cs = nullptr;
+      HIP_TRY(library_stream(&cs));
+      hipEvent_t joined = nullptr, done = nullptr;
+      HIP_TRY(hipEventCreateWithFlags(&joined, hipEventDisableTiming));
+      HIP_TRY(hipEventCreateWithFlags(&done, hipEventDisableTiming));
+      HIP_TRY(hipEventRecord(joined, s));
+      HIP_TRY(hipStreamWaitEvent(cs, joined, 0));
+      hipGraph_t graph = nullptr;
+      hipGraphExec_t exec = nullptr;
+      HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+      hipError_t le = run_round(rp, b, cs);
+      hipError_t ce = hipStreamEndCapture(cs, &graph);
+      hipError_t ie = hipSuccess;
+      if (le == hipSuccess && ce == hipSuccess) ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+      hipError_t ge = hipSuccess;
+      for (uint32_t r = 0; r < p->rounds && le == hipSuccess && ce == hipSuccess && ie == hipSuccess && ge == hipSuccess; ++r)
+        ge = hipGraphLaunch(exec, cs);
+      HIP_TRY(hipEventRecord(done, cs));
+      HIP_TRY(hipStreamWaitEvent(s, done, 0));
+      HIP_TRY(hipStreamSynchronize(cs));
+      if (exec) (void)hipGraphExecDestroy(exec);
+      if (graph) (void)hipGraphDestroy(graph);
+      (void)hipEventDestroy(joined);
+      (void)hipEventDestroy(done);
+      hipError_t first = le != hipSuccess ? le : (ce != hipSuccess ? ce : (ie != hipSuccess ? ie : ge));
+      if (first != hipSuccess) return fail(FGIM_ERR_DEVICE, "refinement graph failed: %s", hipGetErrorString(first));
+    } else {
+      for (uint32_t r = 0; r < p->rounds; ++r) HIP_TRY(run_round(rp, b, s));
+    }
+    if (!repair || p->rounds == 0) {
+      HIP_TRY(fill_u32(b.T, 0u, N, s));
+      hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, b.T);
+      HIP_TRY(hipGetLastError());
+    }
+    uint32_t hh[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(hh, b.hdr, sizeof(hh), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hh[1] > cap) {
+      cap = std::min<uint64_t>(static_cast<uint64_t>(hh[1]) * 5 / 4 + 1024, 0xF0000000ull);
+      continue;  // proposals overflowed: run again with a larger buffer (same result)
+    }
+    hipLaunchKernelGGL(from_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, ids, dist);
+    HIP_TRY(hipGetLastError());
+    if (T_out) HIP_TRY(hipMemcpyAsync(T_out, b.T, 4 * N, hipMemcpyDeviceToDevice, s));
+    if (stats) {
+      HIP_TRY(hipEventRecord(e1, s));
+      HIP_TRY(hipEventSynchronize(e1));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+      stats->ms_stage[1] = ms;
+      stats->repaired = hh[2];
+      stats->proposals = hh[3];
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+    }
+    return FGIM_OK;
+  }
+  return fail(FGIM_ERR_OUT_OF_MEMORY, "join proposals keep overflowing the buffer");
+}
+
+}  // namespace fgim
+
+extern "C" fgim_status fgim_refine(const fgim_dataset* data, const fgim_params* params, uint32_t* knn_ids,
+                                   float* knn_dist, uint32_t* indegree, fgim_stats* stats, void* stream) {
+  fgim::fail(FGIM_OK, "");
+  if (stats) memset(stats, 0, sizeof(*stats));
+  return fgim::refine_impl(data, params, knn_ids, knn_dist, indegree, stats, static_cast<hipStream_t>(stream));
+}
