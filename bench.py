@@ -1,0 +1,248 @@
+"""Benchmark of the FGIM merge on one MI355X.
+
+One step = one fgim_merge call (stage 1 cross-querying, stage 2 refinement
+rounds with indegree repair, stage 3 prune + reverse fill) over the
+synthetic workload, with inputs resident in HBM.  Prints one JSON line.
+
+  python bench.py [--steps K] [--warmup W] [--config cfg2] [--precision fp32|bf16|fp8]
+                  [--no-cpu-baseline] [--no-recall] [--queries Q]
+
+Roofline of the dominant kernel (the stage-1 beam search): algorithmic bytes
+per launch (distance computations x row bytes + expansions x adjacency row
+bytes + per-vertex query, local candidates and output) over the kernel's
+duration, timed with hipEvents on the stream the kernel runs on.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+import torch  # noqa: E402
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "vectors merged/sec + k-NNG recall & search recall@10, FP32 vs BF16/FP8 form"
+BEAM_SOURCES = ["paper_2603_21710_amd/csrc/beam_impl.h", "paper_2603_21710_amd/csrc/fgim_device.h",
+                "paper_2603_21710_amd/csrc/beam_f32.hip", "paper_2603_21710_amd/csrc/beam_bf16.hip",
+                "paper_2603_21710_amd/csrc/beam_fp8.hip"]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def beam_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in BEAM_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(cfg_name: str, precision: str):
+    """HBM bytes per beam-kernel launch from the committed rocprofv3 counter
+    summary, or None when absent or taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"beam_kernel_{cfg_name}_{precision}_counters.md")
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("- ") and ": " in line:
+                k, v = line[2:].split(": ", 1)
+                vals[k.strip()] = v.strip().strip("`")
+    if vals.get("beam sources sha256") != beam_source_hash():
+        return None
+    try:
+        return float(vals["HBM bytes per launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def build_inputs(cfg, device):
+    from workloads import build_input_pg, make_vectors, reach_fraction, split_sizes
+    t0 = time.time()
+    X = make_vectors(cfg)
+    graphs, reach, deg = [], [], []
+    for off, n in split_sizes(cfg):
+        pg = build_input_pg(X[off:off + n], cfg.r_in, cfg.metric, device=device)
+        graphs.append((off, pg.adj, pg.entry))
+        reach.append(reach_fraction(pg.adj, pg.entry))
+        deg.append(pg.mean_degree)
+    log(f"inputs: N={X.shape[0]} d={X.shape[1]} h={len(graphs)} built in {time.time() - t0:.1f}s; "
+        f"input reach {min(reach):.4f}..{max(reach):.4f}, mean degree {np.mean(deg):.2f}")
+    return X, graphs, reach
+
+
+def cpu_baseline(cfg, X, graphs, budget_nodes: int):
+    """The oracle timed on this host: stage 1 on a seeded sample of vertices
+    of the full workload, stages 2-3 in full on a 2 x 20,000 draw of the same
+    distribution and parameters.  Returns vectors/s of the combined cost."""
+    import oracle
+    from workloads import build_input_pg, make_vectors, split_sizes
+    threads = oracle.default_threads()
+    rng = np.random.default_rng(12345)
+    nodes = np.sort(rng.choice(X.shape[0], min(budget_nodes, X.shape[0]), replace=False)).astype(np.uint64)
+    t0 = time.perf_counter()
+    oracle.cross_query(X, graphs, cfg.k, cfg.L, cfg.metric, nodes=nodes, threads=threads)
+    t_s1 = (time.perf_counter() - t0) / len(nodes)
+    small = cfg.scaled(tuple(min(s, 20000) for s in cfg.sizes[:2]) if cfg.h > 2 else (20000,) * cfg.h)
+    Xs = make_vectors(small)
+    gs = []
+    for off, n in split_sizes(small):
+        pg = build_input_pg(Xs[off:off + n], small.r_in, small.metric)
+        gs.append((off, pg.adj, pg.entry))
+    ids, dd, _ = oracle.cross_query(Xs, gs, small.k, small.L, small.metric, threads=threads)
+    t0 = time.perf_counter()
+    i2, d2, _, T, _ = oracle.refine(Xs, gs, ids, dd, small.rounds, small.metric, threads=threads)
+    oracle.prune(Xs, i2, d2, T, small.R, small.metric, threads=threads)
+    t_s23 = (time.perf_counter() - t0) / Xs.shape[0]
+    per_vec = t_s1 + t_s23
+    return {"value": 1.0 / per_vec, "unit": "vectors/s", "cores": threads, "kind": "oracle",
+            "sample": (f"stage 1 on {len(nodes)} seeded vertices of the full workload "
+                       f"({t_s1 * 1e3:.3f} ms/vertex); stages 2-3 in full on a "
+                       f"{'+'.join(str(s) for s in small.sizes)} draw of the same distribution "
+                       f"({t_s23 * 1e3:.3f} ms/vertex)")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="cfg2")
+    ap.add_argument("--precision", default=None, choices=[None, "fp32", "bf16", "fp8"])
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--queries", type=int, default=10000)
+    ap.add_argument("--cpu-nodes", type=int, default=20000)
+    ap.add_argument("--autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
+              "the merge is built and measured on a single MI355X", file=sys.stderr)
+        sys.exit(2)
+
+    import paper_2603_21710_amd as fg
+    from workloads import get_config, make_queries
+    from workloads.evaluate import exact_knn_fp64, tie_recall
+
+    cfg = get_config(args.config)
+    precision = args.precision or "fp32"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    X, graphs, reach = build_inputs(cfg, "cuda")
+    Xd = torch.from_numpy(X).to(dev)
+    gl = [(torch.from_numpy(a.view(np.int32)).to(dev), int(e)) for _, a, e in graphs]
+    lowp = lowp_scale = None
+    quant_ms = None
+    if precision != "fp32":
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        lowp, lowp_scale = fg.quantize(Xd, precision)
+        torch.cuda.synchronize()
+        quant_ms = (time.perf_counter() - t0) * 1e3
+    m = fg.Merge(Xd, gl, cfg.metric, lowp, lowp_scale)
+    p = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds, precision=precision,
+                  autotune=args.autotune)
+
+    for _ in range(args.warmup):
+        fg.merge(m, p)
+    torch.cuda.synchronize()
+    beam_ms, stage_ms = [], []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pg, deg, entry, st = fg.merge(m, p, stats=True)
+        beam_ms.append(st["ms_beam_kernel"])
+        stage_ms.append(st["ms_stage"])
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_per_step = wall * 1e3 / args.steps
+    value = X.shape[0] / (ms_per_step / 1e3)
+    log(f"merge: {ms_per_step:.2f} ms/step, stages {np.mean(stage_ms, 0).round(2).tolist()} ms, "
+        f"beam kernel {np.mean(beam_ms):.2f} ms")
+
+    # Algorithmic bytes of one beam-kernel launch.  The distance count is
+    # measured with the largest visited cache, which re-scores almost no
+    # vertex, so it is (slightly above) the count of Algorithm 1.
+    _, _, st_big = fg.cross_query(m, fg.params(k=cfg.k, L=st["L_used"], precision=precision,
+                                               visited_slots=16384, waves_per_cu=8), stats=True)
+    be = {"fp32": 4, "bf16": 2, "fp8": 1}[precision]
+    d, k = X.shape[1], cfg.k
+    ndc, nexp, searches = st_big["ndc"], st_big["expansions"], st_big["searches"]
+    local = sum(int((a != 0xFFFFFFFF).sum()) for _, a, _ in graphs)
+    stride_mean = float(np.mean([a.shape[1] for _, a, _ in graphs]))
+    row_bytes = d * be + (4 if precision == "fp8" else 0)
+    alg_bytes = (ndc * row_bytes + nexp * stride_mean * 4
+                 + X.shape[0] * (d * 4 + stride_mean * 4 + k * 8) + local * d * 4)
+    if precision != "fp32":
+        alg_bytes += searches * min(cfg.L, 2 * cfg.k) * d * 4
+    kern_s = float(np.mean(beam_ms)) / 1e3
+    achieved = alg_bytes / kern_s / 1e9
+    traffic = measured_traffic(cfg.name, precision)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "kernel": "beam_kernel (stage-1 cross-query)", "kernel_ms": round(kern_s * 1e3, 3),
+            "algorithmic_bytes": int(alg_bytes), "ndc_per_search": round(ndc / max(1, searches), 2),
+            "expansions_per_search": round(nexp / max(1, searches), 2),
+            "beam_sources_sha256": beam_source_hash()}
+
+    out = {"metric": METRIC, "value": round(value, 1), "unit": "vectors/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": {"fp32": "f32", "bf16": "bf16 scoring, f32 re-rank",
+                     "fp8": "fp8-e4m3 scoring, f32 re-rank"}[precision],
+           "data": "synthetic (seeded; stands in for the paper's datasets)",
+           "config": {"workload": cfg.name, "sizes": list(cfg.sizes), "dim": cfg.dim,
+                      "metric": cfg.metric, "r_in": cfg.r_in, "k": cfg.k, "L": st["L_used"],
+                      "rounds": cfg.rounds, "R": cfg.R, "precision": precision,
+                      "parallelism": "1 GPU"},
+           "stages_ms": [round(x, 3) for x in np.mean(stage_ms, 0).tolist()],
+           "roofline": roof}
+    if quant_ms is not None:
+        out["quantize_ms"] = round(quant_ms, 3)
+
+    if not args.no_recall:
+        t0 = time.time()
+        Q = make_queries(cfg, args.queries)
+        ids, dist, _ = fg.cross_query(m, p)
+        fg.refine(m, p, ids, dist)
+        knn = fg.as_uint32(ids)
+        rng = np.random.default_rng(7)
+        nodes = np.sort(rng.choice(X.shape[0], min(args.queries, X.shape[0]), replace=False))
+        _, gd = exact_knn_fp64(X, X[nodes], cfg.k, cfg.metric, exclude=nodes)
+        knng_recall = tie_recall(X, X[nodes], knn[nodes], gd[:, -1], cfg.k, cfg.metric)
+        _, qd = exact_knn_fp64(X, Q, 10, cfg.metric)
+        sr = {}
+        for Ls in (16, 32, 64, 128):
+            found, _ = fg.search(Xd, pg, entry, torch.from_numpy(Q).to(dev), Ls, 10, cfg.metric)
+            sr[str(Ls)] = round(tie_recall(X, Q, fg.as_uint32(found), qd[:, -1], 10, cfg.metric), 5)
+        out["quality"] = {"knng_recall": round(knng_recall, 5), "knng_recall_nodes": len(nodes),
+                          "search_recall@10": sr, "search_L_headline": 64,
+                          "queries": int(Q.shape[0]), "input_reach": [round(r, 4) for r in reach]}
+        if precision != "fp32":
+            p32 = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds)
+            pg32, _, e32, _ = fg.merge(fg.Merge(Xd, gl, cfg.metric), p32)
+            found, _ = fg.search(Xd, pg32, e32, torch.from_numpy(Q).to(dev), 64, 10, cfg.metric)
+            r32 = tie_recall(X, Q, fg.as_uint32(found), qd[:, -1], 10, cfg.metric)
+            out["quality"]["fp32_search_recall@10_L64"] = round(r32, 5)
+            out["quality"]["recall_gap_pp_L64"] = round((r32 - sr["64"]) * 100, 3)
+        log(f"quality: {out['quality']} ({time.time() - t0:.1f}s)")
+
+    if not args.no_cpu_baseline:
+        t0 = time.time()
+        out["cpu_baseline"] = cpu_baseline(cfg, X, graphs, args.cpu_nodes)
+        log(f"cpu baseline: {out['cpu_baseline']} ({time.time() - t0:.1f}s)")
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -47,6 +47,74 @@ FGIM_DEV float pair_distance(const float* a, const float* b, int metric, uint32_
   return finish<kCos>(r);
 }
 
+// canonical distance of the P-lane group's row (chunks held in x) to row b
+template <int MMAX>
+FGIM_DEV float row_distance(const float4 (&x)[MMAX], const float* b, int metric, uint32_t nc, int P, int M, int l) {
+  float s[MMAX];
+#pragma unroll
+  for (int mi = 0; mi < MMAX; ++mi) {
+    s[mi] = 0.0f;
+    const uint32_t ch = static_cast<uint32_t>(l + mi * P);
+    if (mi < M && ch < nc) {
+      const float4 y = *reinterpret_cast<const float4*>(b + 4 * ch);
+      s[mi] = metric == kL2 ? chunk_sum<kL2>(x[mi], y) : chunk_sum<kIP>(x[mi], y);
+    }
+  }
+#pragma unroll
+  for (int st = MMAX / 2; st >= 1; st /= 2) {
+    if (2 * st <= M) {
+#pragma unroll
+      for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
+    }
+  }
+  float r = s[0];
+#pragma unroll
+  for (int st = 32; st >= 1; st /= 2)
+    if (st < P) r = r + shfl_xor_f(r, st);
+  if (metric == kL2) return finish<kL2>(r);
+  if (metric == kIP) return finish<kIP>(r);
+  return finish<kCos>(r);
+}
+
+// row_distance with loads predicated on `act`; call from wave-uniform code
+template <int MMAX>
+FGIM_DEV float pair_distance_x(const float4 (&x)[MMAX], const float* b, int metric, uint32_t nc, int P, int M, int l,
+                               bool act) {
+  float s[MMAX];
+#pragma unroll
+  for (int mi = 0; mi < MMAX; ++mi) {
+    s[mi] = 0.0f;
+    const uint32_t ch = static_cast<uint32_t>(l + mi * P);
+    if (mi < M && act && ch < nc) {
+      const float4 y = *reinterpret_cast<const float4*>(b + 4 * ch);
+      s[mi] = metric == kL2 ? chunk_sum<kL2>(x[mi], y) : chunk_sum<kIP>(x[mi], y);
+    }
+  }
+#pragma unroll
+  for (int st = MMAX / 2; st >= 1; st /= 2) {
+    if (2 * st <= M) {
+#pragma unroll
+      for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
+    }
+  }
+  float r = s[0];
+#pragma unroll
+  for (int st = 32; st >= 1; st /= 2)
+    if (st < P) r = r + shfl_xor_f(r, st);
+  if (metric == kL2) return finish<kL2>(r);
+  if (metric == kIP) return finish<kIP>(r);
+  return finish<kCos>(r);
+}
+
+template <int MMAX>
+FGIM_DEV void load_row(float4 (&x)[MMAX], const float* row, uint32_t nc, int P, int M, int l) {
+#pragma unroll
+  for (int mi = 0; mi < MMAX; ++mi) {
+    const uint32_t ch = static_cast<uint32_t>(l + mi * P);
+    x[mi] = (mi < M && ch < nc) ? *reinterpret_cast<const float4*>(row + 4 * ch) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
 // sub-index of global id v given ascending offsets off[0..h)
 FGIM_DEV uint32_t sub_of(const uint64_t* off, uint32_t h, uint32_t v) {
   uint32_t lo = 0, hi = h;

@@ -41,13 +41,17 @@ __global__ void __launch_bounds__(256) select_kernel(SelectArgs a) {
   uint32_t* vid = reinterpret_cast<uint32_t*>(occl + 2 * a.k);
   float* vd = reinterpret_cast<float*>(vid + a.k);
   uint32_t* tv = reinterpret_cast<uint32_t*>(vd + a.k);
-  float* rows = reinterpret_cast<float*>(smem + ((a.k * (16 + 12) + 15) / 16) * 16);
-  const uint32_t d = a.nc * 4;
+  uint32_t* ctr = reinterpret_cast<uint32_t*>(smem + ((a.k * (16 + 12) + 15) / 16) * 16);  // 4 words
+  float* rows = reinterpret_cast<float*>(ctr + 4);
+  const uint32_t d = a.nc * 4 + 4;  // padded LDS row stride (spreads rows over banks)
   const int P = static_cast<int>(a.P), M = static_cast<int>(a.M);
-  const int gid = threadIdx.x / P, ngroups = 256 / P, l = threadIdx.x % P;
+  const int l = threadIdx.x % P;
 
   for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
-    uint32_t cnt = 0;
+    if (threadIdx.x == 0) {
+      ctr[0] = 0;
+      ctr[1] = 0;
+    }
     for (uint32_t t = threadIdx.x; t < a.k; t += 256) {
       const uint32_t v = a.ids[u * a.k + t];
       vid[t] = v;
@@ -55,27 +59,49 @@ __global__ void __launch_bounds__(256) select_kernel(SelectArgs a) {
       tv[t] = v == kNone ? 0u : a.T[v];
       occl[2 * t] = 0;
       occl[2 * t + 1] = 0;
+      if (v != kNone) atomicMax(&ctr[1], t + 1);
     }
     __syncthreads();
-    while (cnt < a.k && vid[cnt] != kNone) ++cnt;
+    const uint32_t cnt = ctr[1];
     if (a.stage_rows) {
       for (uint32_t i = threadIdx.x; i < cnt * a.nc; i += 256) {
-        const uint32_t e = i / a.nc, ch = i % a.nc;
-        *reinterpret_cast<float4*>(rows + static_cast<uint64_t>(e) * d + 4 * ch) =
+        const uint32_t e = i / a.nc, ch = i - e * a.nc;
+        *reinterpret_cast<float4*>(rows + e * d + 4 * ch) =
             *reinterpret_cast<const float4*>(a.X + static_cast<uint64_t>(vid[e]) * a.ld + 4 * ch);
       }
       __syncthreads();
     }
-    // occlusion tile: bit q of occl[p] set when delta(w_q, v_p) <= delta(u, v_p), q < p
-    const uint32_t slots = cnt * cnt;
-    for (uint32_t s0 = 0; s0 < slots; s0 += ngroups) {
-      const uint32_t s = s0 + gid;
-      const uint32_t p = s / (cnt ? cnt : 1), q = s % (cnt ? cnt : 1);
-      const bool valid = s < slots && q < p && tv[p] != 1u;
-      const float* rw = a.stage_rows ? rows + static_cast<uint64_t>(q) * d : a.X + static_cast<uint64_t>(vid[valid ? q : 0]) * a.ld;
-      const float* rv = a.stage_rows ? rows + static_cast<uint64_t>(p) * d : a.X + static_cast<uint64_t>(vid[valid ? p : 0]) * a.ld;
-      const float dwv = pair_distance<MMAX>(rw, rv, a.metric, a.nc, P, M, l, valid);
-      if (valid && l == 0 && !(vd[p] < dwv)) atomicOr(reinterpret_cast<unsigned long long*>(&occl[2 * p + q / 64]), 1ull << (q % 64));
+    // occlusion tile: bit q of occl[p] set when delta(w_q, v_p) <= delta(u, v_p),
+    // q < p; one P-lane group per row p (rows with T(v_p) = 1 are exempt).
+    // Rows are dealt to groups statically and every loop that contains a
+    // cross-lane shuffle is wave-uniform (inner trip count = the wave's
+    // largest row, predicated per group).
+    {
+      const uint32_t G = 64 / P, g = (threadIdx.x % 64) / P, wave = threadIdx.x / 64;
+      for (uint32_t base = wave * G; base < cnt; base += 4 * G) {
+        const uint32_t pp = base + g;
+        const bool act = pp < cnt && tv[pp] != 1u;
+        const uint32_t qmax = min(base + G, cnt) - 1;  // largest row index of this wave's batch
+        float4 x[MMAX];
+        const float* xr = a.stage_rows ? (act ? rows + pp * d : rows)
+                                       : a.X + (act ? static_cast<uint64_t>(vid[pp]) * a.ld : 0ull);
+        load_row<MMAX>(x, xr, a.nc, P, M, l);
+        const float dup = act ? vd[pp] : 0.0f;
+        uint64_t m0 = 0, m1 = 0;
+        for (uint32_t q = 0; q < qmax; ++q) {
+          const bool valid = act && q < pp;
+          const float* rw = a.stage_rows ? rows + q * d : a.X + static_cast<uint64_t>(vid[q]) * a.ld;
+          const float dwv = pair_distance_x<MMAX>(x, rw, a.metric, a.nc, P, M, l, valid);
+          if (valid && !(dup < dwv)) {
+            if (q < 64) m0 |= 1ull << q;
+            else m1 |= 1ull << (q - 64);
+          }
+        }
+        if (act && l == 0) {
+          occl[2 * pp] = m0;
+          occl[2 * pp + 1] = m1;
+        }
+      }
     }
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -172,8 +198,8 @@ fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32
   const uint32_t nc = d->dim / 4, Nch = pow2_ceil(nc);
   const uint32_t P = std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, Nch), Nch / 4));
   const uint32_t M = Nch / P;
-  const size_t head = ((k * (16 + 12) + 15) / 16) * 16;
-  const size_t rows = k * d->dim * 4;
+  const size_t head = ((k * (16 + 12) + 15) / 16) * 16 + 16;
+  const size_t rows = k * (d->dim + 4) * 4;
   const bool stage = head + rows <= 96 * 1024;
   const size_t smem = head + (stage ? rows : 0);
 

@@ -212,21 +212,39 @@ FGIM_DEV void rev_top(const uint64_t* seg, uint32_t len, uint32_t krev, uint32_t
   }
 }
 
-// wave-aggregated append of (tgt, key) for lanes with `emit`
-FGIM_DEV void emit_proposal(const JoinArgs& a, bool emit, uint32_t tgt, uint64_t key) {
-  const uint64_t m = ballot(emit);
-  if (!m) return;
-  uint32_t base = 0;
-  const int leader = ffs64(m);
-  if (lane_id() == leader) base = atomicAdd(a.ptotal, static_cast<uint32_t>(popc64(m)));
-  base = readlane(base, leader);
-  if (emit) {
-    const uint32_t pos = base + static_cast<uint32_t>(mbcnt(m));
-    if (pos < a.cap) {
-      a.ptgt[pos] = tgt;
-      a.pkey[pos] = key;
+// Proposals of one vertex's join are staged in LDS and flushed to the global
+// buffer with one atomic per vertex; a proposal that finds the stage full
+// goes straight to the global buffer.
+constexpr uint32_t kPropStage = 512;
+
+FGIM_DEV void stage_proposal(const JoinArgs& a, uint32_t tgt, uint64_t key, uint32_t* lds_cnt, uint32_t* stgt,
+                             uint64_t* skey) {
+  const uint32_t pos = atomicAdd(lds_cnt, 1u);
+  if (pos < kPropStage) {
+    stgt[pos] = tgt;
+    skey[pos] = key;
+  } else {
+    const uint32_t g = atomicAdd(a.ptotal, 1u);
+    if (g < a.cap) {
+      a.ptgt[g] = tgt;
+      a.pkey[g] = key;
     }
   }
+}
+
+// sort ids[0..n) by sub-index (stable) into out, with their sub-indexes
+FGIM_DEV void sort_by_sub(const uint32_t* ids, uint32_t n, const uint64_t* sub_off, uint32_t h, uint32_t* out,
+                          uint32_t* gout, uint32_t* gtmp) {
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) gtmp[i] = sub_of(sub_off, h, ids[i]);
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < n; i += blockDim.x) {
+    const uint32_t g = gtmp[i];
+    uint32_t pos = 0;
+    for (uint32_t j = 0; j < n; ++j) pos += (gtmp[j] < g) || (gtmp[j] == g && j < i);
+    out[pos] = ids[i];
+    gout[pos] = g;
+  }
+  __syncthreads();
 }
 
 template <int NR, int MMAX>
@@ -235,17 +253,17 @@ __global__ void __launch_bounds__(256) join_kernel(JoinArgs a) {
   const uint32_t C = a.ccap;
   uint32_t* arr_n = reinterpret_cast<uint32_t*>(smem);          // C
   uint32_t* arr_o = arr_n + C;                                  // C
-  uint32_t* cid = arr_o + C;                                    // C: Cn then Co
-  uint32_t* cg = cid + C;                                       // sub-index
-  uint64_t* cw = reinterpret_cast<uint64_t*>(cg + C);           // worst key of the list
+  uint32_t* cid = arr_o + C;                                    // C: Cn then Co, each sorted by sub-index
+  uint32_t* cg = cid + C;                                       // sub-index of cid
+  uint64_t* cw = reinterpret_cast<uint64_t*>(cg + C);           // worst key of cid's list
   uint32_t* counters = reinterpret_cast<uint32_t*>(cw + C);     // 8
-  float* rows = reinterpret_cast<float*>(counters + 8);         // C x d (optional)
-  const uint32_t d = a.nc * 4;
+  uint64_t* skey = reinterpret_cast<uint64_t*>(counters + 8);   // kPropStage
+  uint32_t* stgt = reinterpret_cast<uint32_t*>(skey + kPropStage);
+  float* rows = reinterpret_cast<float*>(stgt + kPropStage);    // C x (d + 4) (optional)
+  const uint32_t d = a.nc * 4 + 4;  // padded LDS row stride (spreads rows over banks)
   const int wave = threadIdx.x / 64;
   const int P = static_cast<int>(a.P);
   const int M = static_cast<int>(a.M);
-  const int gid = threadIdx.x / P;
-  const int ngroups = 256 / P;
   const int l = threadIdx.x % P;
 
   for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
@@ -266,7 +284,7 @@ __global__ void __launch_bounds__(256) join_kernel(JoinArgs a) {
     }
     __syncthreads();
     const uint32_t nn0 = counters[0], no0 = counters[1];
-    // Cn: unique ids of arr_n
+    // Cn: unique ids of arr_n (kept in arr_n's first slots via cid scratch)
     for (uint32_t i = threadIdx.x; i < nn0; i += 256) {
       const uint32_t v = arr_n[i];
       bool dup = false;
@@ -286,39 +304,79 @@ __global__ void __launch_bounds__(256) join_kernel(JoinArgs a) {
     __syncthreads();
     const uint32_t no = counters[3];
     const uint32_t c = nn + no;
-    for (uint32_t i = threadIdx.x; i < c; i += 256) {
-      const uint32_t v = cid[i];
-      cg[i] = sub_of(a.sub_off, a.h, v);
-      cw[i] = a.keys[static_cast<uint64_t>(v) * a.k + a.k - 1];
-    }
+    // order Cn and Co by sub-index: the partners of a Cn entry are then at
+    // most three contiguous ranges
+    for (uint32_t i = threadIdx.x; i < c; i += 256) arr_n[i] = cid[i];
+    __syncthreads();
+    sort_by_sub(arr_n, nn, a.sub_off, a.h, cid, cg, arr_o);
+    sort_by_sub(arr_n + nn, no, a.sub_off, a.h, cid + nn, cg + nn, arr_o);
+    for (uint32_t i = threadIdx.x; i < c; i += 256)
+      cw[i] = a.keys[static_cast<uint64_t>(cid[i]) * a.k + a.k - 1];
     if (a.stage_rows) {
       for (uint32_t i = threadIdx.x; i < c * a.nc; i += 256) {
-        const uint32_t e = i / a.nc, ch = i % a.nc;
-        *reinterpret_cast<float4*>(rows + static_cast<uint64_t>(e) * d + 4 * ch) =
+        const uint32_t e = i / a.nc, ch = i - e * a.nc;
+        *reinterpret_cast<float4*>(rows + e * d + 4 * ch) =
             *reinterpret_cast<const float4*>(a.X + static_cast<uint64_t>(cid[e]) * a.ld + 4 * ch);
       }
     }
     __syncthreads();
-    // pairs: slot s -> (i, j), i in Cn, j in Cn (j > i) or Co
-    const uint32_t width = c;
-    const uint64_t slots = static_cast<uint64_t>(nn) * width;
-    for (uint64_t s0 = 0; s0 < slots; s0 += ngroups) {
-      const uint64_t s = s0 + gid;
-      bool valid = s < slots;
-      uint32_t i = 0, j = 0;
-      if (valid) {
-        i = static_cast<uint32_t>(s / width);
-        j = static_cast<uint32_t>(s % width);
-        valid = (j >= nn || j > i) && cg[i] != cg[j];
+    // Each P-lane group takes Cn rows i (dealt statically) and scores the
+    // partners j: Cn entries past i's run of equal sub-index, and Co entries
+    // of another sub-index.  Loops that contain cross-lane shuffles are
+    // wave-uniform: they run to the wave's largest partner count, predicated
+    // per group.
+    {
+      const uint32_t G = 64 / P, g = (threadIdx.x % 64) / P;
+      for (uint32_t rbase = wave * G; rbase < nn; rbase += 4 * G) {
+        const uint32_t i = rbase + g;
+        const bool act = i < nn;
+        uint32_t cn_hi = 0, co_lo = nn, co_hi = nn, n1 = 0, n2 = 0, n3 = 0;
+        if (act) {
+          const uint32_t gi = cg[i];
+          cn_hi = i + 1;
+          while (cn_hi < nn && cg[cn_hi] == gi) ++cn_hi;
+          while (co_lo < c && cg[co_lo] < gi) ++co_lo;
+          co_hi = co_lo;
+          while (co_hi < c && cg[co_hi] == gi) ++co_hi;
+          n1 = nn - cn_hi;
+          n2 = co_lo - nn;
+          n3 = c - co_hi;
+        }
+        const uint32_t total = n1 + n2 + n3;
+        uint32_t tmax = total;
+#pragma unroll
+        for (int st = 32; st >= 1; st /= 2) tmax = max(tmax, static_cast<uint32_t>(__shfl_xor(static_cast<int>(tmax), st, 64)));
+        float4 x[MMAX];
+        const float* xr = a.stage_rows ? rows + (act ? i : 0u) * d : a.X + static_cast<uint64_t>(cid[act ? i : 0u]) * a.ld;
+        load_row<MMAX>(x, xr, a.nc, P, M, l);
+        const uint32_t vi = act ? cid[i] : 0u;
+        const uint64_t wi = act ? cw[i] : 0ull;
+        for (uint32_t t = 0; t < tmax; ++t) {
+          const bool valid = t < total;
+          const uint32_t j = !valid ? 0u : (t < n1 ? cn_hi + t : (t < n1 + n2 ? nn + (t - n1) : co_hi + (t - n1 - n2)));
+          const float* rb = a.stage_rows ? rows + j * d : a.X + static_cast<uint64_t>(cid[j]) * a.ld;
+          const float dd = pair_distance_x<MMAX>(x, rb, a.metric, a.nc, P, M, l, valid);
+          if (valid && l == 0) {
+            const uint32_t vj = cid[j];
+            const uint64_t to_i = make_key(dd, vj), to_j = make_key(dd, vi);
+            if (to_i < wi) stage_proposal(a, vi, to_i, &counters[4], stgt, skey);
+            if (to_j < cw[j]) stage_proposal(a, vj, to_j, &counters[4], stgt, skey);
+          }
+        }
       }
-      const float* ra = a.stage_rows ? rows + static_cast<uint64_t>(i) * d : a.X + static_cast<uint64_t>(cid[i]) * a.ld;
-      const float* rb = a.stage_rows ? rows + static_cast<uint64_t>(j) * d : a.X + static_cast<uint64_t>(cid[j]) * a.ld;
-      const float dd = pair_distance<MMAX>(ra, rb, a.metric, a.nc, P, M, l, valid);
-      const uint32_t va = valid ? cid[i] : 0u, vb = valid ? cid[j] : 0u;
-      const uint64_t to_a = make_key(dd, vb), to_b = make_key(dd, va);
-      const bool lead = valid && l == 0;
-      emit_proposal(a, lead && to_a < cw[i], va, to_a);
-      emit_proposal(a, lead && to_b < cw[j], vb, to_b);
+    }
+    // flush the stage with one global atomic
+    __syncthreads();
+    const uint32_t ns = min(counters[4], kPropStage);
+    if (threadIdx.x == 0 && ns) counters[5] = atomicAdd(a.ptotal, ns);
+    __syncthreads();
+    const uint32_t base = counters[5];
+    for (uint32_t t = threadIdx.x; t < ns; t += 256) {
+      const uint32_t pos = base + t;
+      if (pos < a.cap) {
+        a.ptgt[pos] = stgt[t];
+        a.pkey[pos] = skey[t];
+      }
     }
     __syncthreads();
   }
@@ -399,96 +457,186 @@ __global__ void zero_compact_kernel(const uint32_t* mask, const uint32_t* off, u
     if (mask[i]) zero[off[i]] = static_cast<uint32_t>(i);
 }
 
-FGIM_DEV uint64_t ld_agent64(const uint64_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+// The repair runs in a single workgroup, so workgroup-scope coherence is
+// all its waves need for the lists and indegrees they share.
+FGIM_DEV uint64_t ld_wg64(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-FGIM_DEV uint32_t ld_agent32(const uint32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+FGIM_DEV uint32_t ld_wg32(const uint32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// Algorithm 4 in one wavefront.  Zero-indegree vertices v* in ascending id;
-// neighbours v of v* from the closest; in N(v) the farthest entry that is not
-// marked replaced and whose indegree exceeds 1 is evicted, or a free slot is
-// used; v* enters N(v) at its sorted place, flagged new and replaced.
-// Lists of the v* themselves never change during the pass (no list holds a
-// zero-indegree vertex before its own turn).
+// Algorithm 4.  Zero-indegree vertices v* are taken in ascending id; the
+// neighbours v of v* are tried from the closest; in N(v) the farthest entry
+// that is not marked replaced and whose indegree exceeds 1 is evicted (or a
+// free slot is used), and v* enters N(v) at its sorted place, flagged new and
+// replaced.  Lists of the v* themselves never change during the pass (no
+// list holds a zero-indegree vertex before its own turn).
+//
+// The pass keeps this sequential order but runs speculatively: each of the
+// W wavefronts of the one workgroup computes the next step of the order
+// against the current state, then the batch commits its longest prefix in
+// which no step read a list or an indegree that an earlier step of the batch
+// writes (a step writes N(v), T(v') and T(v*); it read N(v) and T of N(v)'s
+// entries).  Steps that needed more than one attempt commit only as the
+// first step of a batch.  Committed steps therefore see exactly the state of
+// the sequential loop, and the next batch starts at the first uncommitted
+// step.
+
+// state read by one attempt (v = the neighbour of v* tried)
 template <int NR>
-__global__ void __launch_bounds__(64) repair_kernel(uint64_t* keys, uint32_t* flags, uint32_t* T, const uint32_t* zero,
-                                                    const uint32_t* zcount, uint32_t k, uint32_t* nrep) {
-  const uint32_t Z = *zcount;
-  uint32_t fixed = 0;
-  for (uint32_t zi = 0; zi < Z; ++zi) {
-    const uint32_t vs = zero[zi];
-    for (uint32_t s = 0; s < k; ++s) {
-      const uint64_t ks = keys[static_cast<uint64_t>(vs) * k + s];
-      if (ks == kSentinel) break;
-      const uint32_t v = key_id(ks);
-      const uint64_t nk = (ks & 0xFFFFFFFF00000000ull) | vs;
-      uint64_t lk[NR];
-      uint32_t lf[NR];
-      bool cand[NR];
+struct Attempt {
+  uint64_t lk[NR];
+  uint32_t lf[NR];
+  int drop;      // entry to evict, -1 for a free slot
+  bool ok;       // v* can enter N(v)
+};
+
+template <int NR>
+FGIM_DEV Attempt<NR> try_neighbour(const uint64_t* keys, const uint32_t* flags, const uint32_t* T, uint32_t v,
+                                   uint32_t k) {
+  Attempt<NR> at;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const uint32_t e = r * 64 + lane_id();
-        lk[r] = e < k ? ld_agent64(&keys[static_cast<uint64_t>(v) * k + e]) : kSentinel;
-        lf[r] = e < k ? ld_agent32(&flags[static_cast<uint64_t>(v) * k + e]) : 0u;
-      }
-      uint64_t lastk = kSentinel;
+  for (int r = 0; r < NR; ++r) {
+    const uint32_t e = r * 64 + lane_id();
+    at.lk[r] = e < k ? ld_wg64(&keys[static_cast<uint64_t>(v) * k + e]) : kSentinel;
+    at.lf[r] = e < k ? ld_wg32(&flags[static_cast<uint64_t>(v) * k + e]) : 0u;
+  }
+  uint64_t lastk = kSentinel;
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (static_cast<uint32_t>(r) == (k - 1) / 64) lastk = readlane64(lk[r], (k - 1) % 64);
-      int drop = -1;
-      if (lastk != kSentinel) {
+  for (int r = 0; r < NR; ++r)
+    if (static_cast<uint32_t>(r) == (k - 1) / 64) lastk = readlane64(at.lk[r], (k - 1) % 64);
+  at.drop = -1;
+  at.ok = true;
+  if (lastk != kSentinel) {
+    bool cand[NR];
 #pragma unroll
-        for (int r = 0; r < NR; ++r) {
-          const uint32_t e = r * 64 + lane_id();
-          cand[r] = e < k && !(lf[r] & kFlagReplaced) && ld_agent32(&T[key_id(lk[r])]) > 1u;
-        }
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t e = r * 64 + lane_id();
+      cand[r] = e < k && !(at.lf[r] & kFlagReplaced) && ld_wg32(&T[key_id(at.lk[r])]) > 1u;
+    }
 #pragma unroll
-        for (int r = NR - 1; r >= 0; --r) {
-          const uint64_t m = ballot(cand[r]);
-          if (drop < 0 && m) drop = r * 64 + 63 - __clzll(static_cast<long long>(m));
-        }
-        if (drop < 0) continue;
-      }
-      // new position of every kept entry, and of v*
-      int pos = 0;
+    for (int r = NR - 1; r >= 0; --r) {
+      const uint64_t m = ballot(cand[r]);
+      if (at.drop < 0 && m) at.drop = r * 64 + 63 - __clzll(static_cast<long long>(m));
+    }
+    at.ok = at.drop >= 0;
+  }
+  return at;
+}
+
+// write N(v) with entry `drop` removed (if any) and key nk inserted, and
+// update the indegrees
+template <int NR>
+FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, const Attempt<NR>& at, uint32_t v,
+                             uint32_t vs, uint64_t nk, uint32_t k) {
+  int pos = 0;
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int e = r * 64 + lane_id();
-        pos += popc64(ballot(e != drop && lk[r] < nk));
-      }
-      uint64_t dk = kSentinel;
+  for (int r = 0; r < NR; ++r) {
+    const int e = r * 64 + lane_id();
+    pos += popc64(ballot(e != at.drop && at.lk[r] < nk));
+  }
+  uint64_t dk = kSentinel;
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (drop >= 0 && r == drop / 64) dk = readlane64(lk[r], drop % 64);
-      if (drop >= 0 && lane_id() == 0) {
-        const uint32_t vp = key_id(dk);
-        __hip_atomic_store(&T[vp], ld_agent32(&T[vp]) - 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
+  for (int r = 0; r < NR; ++r)
+    if (at.drop >= 0 && r == at.drop / 64) dk = readlane64(at.lk[r], at.drop % 64);
+  if (at.drop >= 0 && lane_id() == 0) {
+    const uint32_t vp = key_id(dk);
+    __hip_atomic_store(&T[vp], ld_wg32(&T[vp]) - 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
 #pragma unroll
-      for (int r = 0; r < NR; ++r) {
-        const int e = r * 64 + lane_id();
-        if (e >= static_cast<int>(k) || e == drop || lk[r] == kSentinel) continue;
-        int ne = e - (drop >= 0 && e > drop ? 1 : 0);
-        if (ne >= pos) ++ne;
-        if (ne < static_cast<int>(k)) {
-          keys[static_cast<uint64_t>(v) * k + ne] = lk[r];
-          flags[static_cast<uint64_t>(v) * k + ne] = lf[r];
-        }
-      }
-      if (lane_id() == 0) {
-        keys[static_cast<uint64_t>(v) * k + pos] = nk;
-        flags[static_cast<uint64_t>(v) * k + pos] = kFlagNew | kFlagReplaced;
-        __hip_atomic_store(&T[vs], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      }
-      __threadfence();
-      ++fixed;
-      break;
+  for (int r = 0; r < NR; ++r) {
+    const int e = r * 64 + lane_id();
+    if (e >= static_cast<int>(k) || e == at.drop || at.lk[r] == kSentinel) continue;
+    int ne = e - (at.drop >= 0 && e > at.drop ? 1 : 0);
+    if (ne >= pos) ++ne;
+    if (ne < static_cast<int>(k)) {
+      keys[static_cast<uint64_t>(v) * k + ne] = at.lk[r];
+      flags[static_cast<uint64_t>(v) * k + ne] = at.lf[r];
     }
   }
-  if (lane_id() == 0) atomicAdd(nrep, fixed);
+  if (lane_id() == 0) {
+    keys[static_cast<uint64_t>(v) * k + pos] = nk;
+    flags[static_cast<uint64_t>(v) * k + pos] = kFlagNew | kFlagReplaced;
+    __hip_atomic_store(&T[vs], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+}
+
+constexpr int kRepairWaves = 16;
+
+template <int NR>
+__global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* keys, uint32_t* flags, uint32_t* T,
+                                                                   const uint32_t* zero, const uint32_t* zcount,
+                                                                   uint32_t k, uint32_t* nrep) {
+  __shared__ uint32_t s_list[kRepairWaves];   // N(v) written by step w (kNone: none)
+  __shared__ uint32_t s_evict[kRepairWaves];  // v' whose indegree step w lowers (kNone: none)
+  __shared__ uint32_t s_stop[kRepairWaves];   // step w cannot commit in this batch
+  const int w = threadIdx.x / 64;
+  const uint32_t Z = *zcount;
+  uint32_t fixed = 0;
+  for (uint32_t base = 0; base < Z;) {
+    const uint32_t zi = base + w;
+    const bool active = zi < Z;
+    const uint32_t vs = active ? zero[zi] : 0u;
+    Attempt<NR> at{};
+    at.ok = false;
+    uint32_t v = kNone;
+    uint64_t nk = 0;
+    int attempts = 0;
+    if (active) {
+      for (uint32_t s = 0; s < k; ++s) {
+        const uint64_t ks = keys[static_cast<uint64_t>(vs) * k + s];
+        if (ks == kSentinel) break;
+        v = key_id(ks);
+        nk = (ks & 0xFFFFFFFF00000000ull) | vs;
+        ++attempts;
+        at = try_neighbour<NR>(keys, flags, T, v, k);
+        if (at.ok) break;
+      }
+    }
+    const bool single = attempts == 0 || (attempts == 1 && at.ok);
+    uint32_t ev = kNone;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (at.ok && at.drop >= 0 && r == at.drop / 64) ev = key_id(readlane64(at.lk[r], at.drop % 64));
+    if (lane_id() == 0) {
+      s_list[w] = at.ok ? v : kNone;
+      s_evict[w] = ev;
+    }
+    __syncthreads();
+    bool stop = !active;
+    if (active && w > 0) {
+      if (!single) {
+        stop = true;
+      } else if (attempts == 1) {
+        for (int j = 0; j < w; ++j) {
+          if (s_list[j] == v) stop = true;
+          const uint32_t ev = s_evict[j];
+          bool hit = false;
+#pragma unroll
+          for (int r = 0; r < NR; ++r) hit |= ev != kNone && at.lk[r] != kSentinel && key_id(at.lk[r]) == ev;
+          if (ballot(hit)) stop = true;
+        }
+      }
+    }
+    if (lane_id() == 0) s_stop[w] = stop ? 1u : 0u;
+    __syncthreads();
+    uint32_t pend = kRepairWaves;
+    for (int j = 0; j < kRepairWaves; ++j)
+      if (s_stop[j]) {
+        pend = j;
+        break;
+      }
+    if (static_cast<uint32_t>(w) < pend && at.ok) {
+      commit_attempt<NR>(keys, flags, T, at, v, vs, nk, k);
+      ++fixed;
+    }
+    __threadfence_block();
+    __syncthreads();
+    base += pend;
+  }
+  if (lane_id() == 0 && fixed) atomicAdd(nrep, fixed);
 }
 
 // ---------------------------------------------------------------------------
@@ -580,10 +728,10 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   if ((e = exclusive_scan(b.zmask, b.zoff, N, b.scan_tmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(zero_compact_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.zmask, b.zoff, N, b.zero);
   if (rp.nr == 1)
-    hipLaunchKernelGGL(repair_kernel<1>, dim3(1), dim3(64), 0, s, b.keys, b.flags, b.T, b.zero, b.zoff + N, rp.k,
+    hipLaunchKernelGGL(repair_kernel<1>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.zero, b.zoff + N, rp.k,
                        b.hdr + 2);
   else
-    hipLaunchKernelGGL(repair_kernel<2>, dim3(1), dim3(64), 0, s, b.keys, b.flags, b.T, b.zero, b.zoff + N, rp.k,
+    hipLaunchKernelGGL(repair_kernel<2>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.zero, b.zoff + N, rp.k,
                        b.hdr + 2);
   return hipGetLastError();
 }
@@ -612,8 +760,8 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   const uint32_t P = std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, Nch), Nch / 4));
   const uint32_t M = Nch / P;
   const uint32_t ccap = 2 * (p->k + k_rev);
-  const size_t base_smem = static_cast<size_t>(ccap) * (4 * 4 + 8) + 8 * 4;
-  const size_t rows_smem = static_cast<size_t>(ccap) * dim * 4;
+  const size_t base_smem = static_cast<size_t>(ccap) * (4 * 4 + 8) + 8 * 4 + kPropStage * 12;
+  const size_t rows_smem = static_cast<size_t>(ccap) * (dim + 4) * 4;
   const bool stage_rows = base_smem + rows_smem <= 96 * 1024;
 
   uint64_t cap = std::max<uint64_t>(N * std::max<uint32_t>(4 * p->k, 64), 1 << 16);

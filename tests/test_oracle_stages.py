@@ -280,3 +280,20 @@ def test_merge_end_to_end_quality():
     assert reach_fraction(pg, ent) >= 0.99
     Q = make_queries(cfg, 100)
     assert oracle.search_recall(X, pg, ent, Q, 64, cfg.metric) >= 0.9
+
+
+def test_evaluation_ground_truth_matches_oracle():
+    # The benchmark's FP64 ground truth (torch, Gram form) agrees with the
+    # oracle's direct FP64 brute force, and tie-aware recall of the truth is 1.
+    from workloads.evaluate import exact_knn_fp64, tie_recall
+    rng = np.random.default_rng(8)
+    X = rng.integers(0, 256, (3000, 32)).astype(np.float32)
+    Q = rng.integers(0, 256, (50, 32)).astype(np.float32)
+    for metric in ("l2", "ip"):
+        gi, gd = exact_knn_fp64(X, Q, 10, metric)
+        oi, od = oracle.bruteforce(X, Q, 10, metric)
+        assert np.array_equal(gd, od)
+        assert tie_recall(X, Q, oi, od[:, -1], 10, metric) == 1.0
+        assert tie_recall(X, Q, gi.astype(np.uint32), od[:, -1], 10, metric) == 1.0
+    wrong = np.full((50, 10), 0xFFFFFFFF, np.uint32)
+    assert tie_recall(X, Q, wrong, od[:, -1], 10, "ip") == 0.0
