@@ -144,3 +144,28 @@ def test_quantize_matches_oracle(prec):
         oc, osc, od = oracle.quantize_fp8(X)
         assert (scales.cpu().numpy() == osc).all()
         assert (codes.cpu().numpy() == oc).all()
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("name,sizes", [("cfg4", (1200, 1000)), ("cfg2", (2500, 2000)),
+                                        ("cfg3", (300, 500, 700, 150, 900, 400, 1200, 650))])
+def test_precision_form_stage1_matches_oracle(prec, name, sizes):
+    # The low-precision beam scores the FP32 query against decoded rows
+    # (BF16 exactly, FP8 as scale * decode in one FP32 rounding) in the
+    # canonical order, so the oracle reproduces it by searching the decoded
+    # copy and re-scoring each search's first `rerank` results on FP32 rows.
+    cfg, X, graphs, _ = workload(name, sizes)
+    if prec == "bf16":
+        _, deq = oracle.quantize_bf16(X)
+    else:
+        _, _, deq = oracle.quantize_fp8(X)
+    rerank = min(cfg.L, 2 * cfg.k)
+    m = to_gpu(X, graphs, cfg.metric)
+    ids, dist, _ = fg.cross_query(m, fg.params(k=cfg.k, L=cfg.L, precision=prec))
+    oi, od, _ = oracle.cross_query(X, graphs, cfg.k, cfg.L, cfg.metric, Xs=deq, rerank=rerank)
+    _cmp(ids, dist, oi, od, f"{name} {prec}")
+    # the same with a caller-provided copy from fgim_quantize
+    codes, scales = fg.quantize(m.X, prec)
+    m2 = to_gpu(X, graphs, cfg.metric, codes, scales)
+    ids2, dist2, _ = fg.cross_query(m2, fg.params(k=cfg.k, L=cfg.L, precision=prec))
+    assert torch.equal(ids, ids2) and torch.equal(dist, dist2)
