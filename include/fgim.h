@@ -117,6 +117,8 @@ typedef struct {
 
 #define FGIM_FLAG_NO_REPAIR 1u     /* refinement without indegree repair (test hook) */
 #define FGIM_FLAG_NO_GRAPH_CAPTURE 2u /* run refinement rounds eagerly, not as a hipGraph */
+#define FGIM_FLAG_NO_MFMA_JOIN 4u   /* score every join pair in FP32 instead of screening the
+                                       tile on MFMA first (same result; test hook) */
 
 /* Per-call counters; passing a non-NULL stats pointer synchronises the
  * stream at the end of the call. */
@@ -128,7 +130,7 @@ typedef struct {
     uint64_t searches;        /* beam searches run */
     uint64_t proposals;       /* join proposals that passed the worst-entry screen */
     uint64_t repaired;        /* zero-indegree vertices given an in-edge */
-    uint64_t rechecked;       /* join pairs re-scored after the MFMA screen */
+    uint64_t rechecked;       /* join pairs re-scored in FP32 after the MFMA screen */
     uint32_t L_used;          /* beam width actually used */
     uint32_t lanes_per_dist;  /* launch shape actually used */
     uint32_t waves_per_cu;

@@ -190,6 +190,15 @@ struct JoinArgs {
   uint32_t P, M;
   uint32_t ccap;             // max |Cn| + |Co| = 2 (k + k_rev)
   int stage_rows;            // candidate rows copied to LDS
+  // MFMA join
+  const float* nrm2;         // squared FP32 norm of every base row
+  const float* qerr2;        // squared norm of each row's BF16 rounding residual
+  int stage_f32;             // FP32 candidate rows fit in LDS (re-scoring reads LDS)
+  const uint16_t* xb;        // BF16 copy (dense rows of dim) or null: convert X
+  uint32_t dim;
+  uint32_t dpad;             // dim rounded up to 32 (MFMA K)
+  uint32_t slice;            // dimensions staged in LDS at a time (multiple of 32)
+  uint32_t* rechecked;       // pairs re-scored in FP32 after the screen
 };
 
 // top-k_rev of a reverse segment by key, appended to list (ids) via counter
@@ -366,6 +375,420 @@ __global__ void __launch_bounds__(256) join_kernel(JoinArgs a) {
       }
     }
     // flush the stage with one global atomic
+    __syncthreads();
+    const uint32_t ns = min(counters[4], kPropStage);
+    if (threadIdx.x == 0 && ns) counters[5] = atomicAdd(a.ptotal, ns);
+    __syncthreads();
+    const uint32_t base = counters[5];
+    for (uint32_t t = threadIdx.x; t < ns; t += 256) {
+      const uint32_t pos = base + t;
+      if (pos < a.cap) {
+        a.ptgt[pos] = stgt[t];
+        a.pkey[pos] = skey[t];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Update on MFMA: the neighbour x neighbour tile of each vertex is scored
+// with v_mfma_f32_16x16x32_bf16 on BF16 copies of the candidate rows staged
+// in LDS, every cross-sub-index pair is screened with a rigorous error
+// margin, and the pairs that could still be a proposal are re-scored in
+// canonical FP32.  The screen only skips pairs that provably cannot beat
+// either end's worst entry, so the proposals are exactly those of the
+// plain join.
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef short shortx8_t __attribute__((ext_vector_type(8)));
+typedef float floatx4_t __attribute__((ext_vector_type(4)));
+
+FGIM_DEV float bf16_value(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return __uint_as_float(u & 0xFFFF0000u);
+}
+
+// per row: squared FP32 norm and squared norm of the BF16 rounding residual
+// x - bf16(x) (one wavefront per row)
+__global__ void __launch_bounds__(256) row_norms_kernel(const float* X, uint64_t n, uint32_t dim, uint64_t ld,
+                                                        float* out, float* qerr) {
+  const uint32_t wave = threadIdx.x / 64;
+  for (uint64_t row = blockIdx.x * 4ull + wave; row < n; row += gridDim.x * 4ull) {
+    float s = 0.0f, q = 0.0f;
+    for (uint32_t t = lane_id(); t < dim; t += 64) {
+      const float x = X[row * ld + t];
+      const float r = x - bf16_value(x);
+      s = __builtin_fmaf(x, x, s);
+      q = __builtin_fmaf(r, r, q);
+    }
+    for (int st = 32; st >= 1; st /= 2) {
+      s += shfl_xor_f(s, st);
+      q += shfl_xor_f(q, st);
+    }
+    if (lane_id() == 0) {
+      out[row] = s;
+      qerr[row] = q;
+    }
+  }
+}
+
+FGIM_DEV uint16_t bf16_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+
+// bitonic sort of up to 128 uint32 values held two per lane (element
+// e = r * 64 + lane), ascending
+FGIM_DEV void wave_sort128(uint32_t& v0, uint32_t& v1) {
+  const uint32_t lane = static_cast<uint32_t>(lane_id());
+#pragma unroll
+  for (uint32_t k = 2; k <= 128; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      if (j == 64) {
+        const uint32_t lo = min(v0, v1), hi = max(v0, v1);
+        v0 = lo;
+        v1 = hi;
+      } else {
+        const uint32_t o0 = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v0), static_cast<int>(j), 64));
+        const uint32_t o1 = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v1), static_cast<int>(j), 64));
+        const bool lower = (lane & j) == 0;
+        const bool asc0 = (lane & k) == 0;
+        const bool asc1 = ((64u + lane) & k) == 0;
+        v0 = (lower == asc0) ? min(v0, o0) : max(v0, o0);
+        v1 = (lower == asc1) ? min(v1, o1) : max(v1, o1);
+      }
+    }
+  }
+}
+
+// unique non-NONE values of the sorted pair (v0, v1) appended to out in
+// order; returns the count (wave-uniform)
+FGIM_DEV uint32_t wave_unique128(uint32_t v0, uint32_t v1, uint32_t* out) {
+  const uint32_t prev0 = static_cast<uint32_t>(__shfl(static_cast<int>(v0), lane_id() == 0 ? 0 : lane_id() - 1, 64));
+  const uint32_t last0 = readlane(v0, 63);
+  const uint32_t prev1 = static_cast<uint32_t>(__shfl(static_cast<int>(v1), lane_id() == 0 ? 0 : lane_id() - 1, 64));
+  const bool k0 = v0 != kNone && (lane_id() == 0 || v0 != prev0);
+  const bool k1 = v1 != kNone && v1 != (lane_id() == 0 ? last0 : prev1);
+  const uint64_t m0 = ballot(k0), m1 = ballot(k1);
+  const uint32_t n0 = static_cast<uint32_t>(popc64(m0));
+  if (k0) out[mbcnt(m0)] = v0;
+  if (k1) out[n0 + mbcnt(m1)] = v1;
+  return n0 + static_cast<uint32_t>(popc64(m1));
+}
+
+FGIM_DEV void emit_proposal(const JoinArgs& a, bool emit, uint32_t tgt, uint64_t key) {
+  const uint64_t m = ballot(emit);
+  if (!m) return;
+  const int leader = ffs64(m);
+  uint32_t base = 0;
+  if (lane_id() == leader) base = atomicAdd(a.ptotal, static_cast<uint32_t>(popc64(m)));
+  base = readlane(base, leader);
+  if (emit) {
+    const uint32_t pos = base + static_cast<uint32_t>(mbcnt(m));
+    if (pos < a.cap) {
+      a.ptgt[pos] = tgt;
+      a.pkey[pos] = key;
+    }
+  }
+}
+
+constexpr uint32_t kMfmaMaxC = 128;       // candidates per vertex on the MFMA path
+constexpr uint32_t kMfmaMaxCn = 64;       // |Cn| bound on the MFMA path (k + k_rev <= 64)
+constexpr uint32_t kMfmaTilesPerWave = 7; // ceil(26 tile pairs / 4 waves) for |Cn| <= 64, c <= 128
+
+// position of the r-th set bit (r < popcount) of the 128-bit mask (m0, m1)
+FGIM_DEV uint32_t select_bit(uint64_t m0, uint64_t m1, uint32_t r) {
+  uint32_t pos = 0;
+  uint64_t m = m0;
+  const uint32_t c0 = static_cast<uint32_t>(__popcll(m0));
+  if (r >= c0) {
+    r -= c0;
+    m = m1;
+    pos = 64;
+  }
+#pragma unroll
+  for (uint32_t w = 32; w >= 1; w >>= 1) {
+    const uint64_t low = m & ((1ull << w) - 1ull);
+    const uint32_t c = static_cast<uint32_t>(__popcll(low));
+    if (r >= c) {
+      r -= c;
+      m >>= w;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+template <int MMAX>
+__global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint32_t* arr_n = reinterpret_cast<uint32_t*>(smem);          // 128
+  uint32_t* arr_o = arr_n + kMfmaMaxC;                          // 128
+  uint32_t* cid = arr_o + kMfmaMaxC;                            // 128: Cn then Co, ascending id
+  uint32_t* cg = cid + kMfmaMaxC;                               // sub-index
+  float* cnrm = reinterpret_cast<float*>(cg + kMfmaMaxC);       // squared norms
+  float* cqe = cnrm + kMfmaMaxC;                                // BF16 residual norms
+  uint64_t* cw = reinterpret_cast<uint64_t*>(cqe + kMfmaMaxC);  // worst key of the list
+  uint64_t* pmask = cw + kMfmaMaxC;                             // 64 x 2 words: passing partners of Cn row i
+  uint32_t* rowoff = reinterpret_cast<uint32_t*>(pmask + 2 * kMfmaMaxCn);  // 65 prefix counts
+  uint32_t* counters = rowoff + 68;                             // 8
+  uint64_t* skey = reinterpret_cast<uint64_t*>(counters + 8);   // kPropStage staged proposals
+  uint32_t* stgt = reinterpret_cast<uint32_t*>(skey + kPropStage);
+  float* frows = reinterpret_cast<float*>(stgt + kPropStage);   // FP32 rows, 128 x (dim + 4), or
+  uint16_t* brows = reinterpret_cast<uint16_t*>(frows);         // BF16 slices, 128 x (slice + 8)
+  const uint32_t fstride = a.dim + 4;
+  const uint32_t srow = a.slice + 8;
+  const int wave = threadIdx.x / 64;
+  const int lane = lane_id();
+  const int P = static_cast<int>(a.P), M = static_cast<int>(a.M);
+  const int l = threadIdx.x % P, gid = threadIdx.x / P, ngroups = 256 / P;
+  const float u32 = 5.9604645e-8f;  // 2^-24
+  const float gam = (a.dim + 4) * u32 / (1.0f - (a.dim + 4) * u32);
+
+  for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
+    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+    if (threadIdx.x < kMfmaMaxC) {
+      arr_n[threadIdx.x] = kNone;
+      arr_o[threadIdx.x] = kNone;
+      pmask[threadIdx.x] = 0;
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < a.k; t += 256) {
+      const uint64_t kk = a.keys[u * a.k + t];
+      if (kk == kSentinel) continue;
+      if (a.flags[u * a.k + t] & kFlagNew) arr_n[atomicAdd(&counters[0], 1u)] = key_id(kk);
+      else arr_o[atomicAdd(&counters[1], 1u)] = key_id(kk);
+    }
+    if (wave < 2) {
+      const uint32_t seg = 2u * static_cast<uint32_t>(u) + wave;
+      const uint32_t b0 = a.rev_off[seg], b1 = a.rev_off[seg + 1];
+      rev_top<1>(a.rev + b0, b1 - b0, a.k_rev, wave == 0 ? arr_n : arr_o, &counters[wave]);
+    }
+    __syncthreads();
+    // Cn = unique(arr_n) and the unique ids of arr_o, both ascending (ids
+    // ascending are grouped by sub-index: sub-index ranges are contiguous)
+    if (wave < 2) {
+      uint32_t* src = wave == 0 ? arr_n : arr_o;
+      uint32_t v0 = src[lane], v1 = src[64 + lane];
+      wave_sort128(v0, v1);
+      const uint32_t n = wave_unique128(v0, v1, wave == 0 ? cid : arr_o);
+      if (lane == 0) counters[2 + wave] = n;
+    }
+    __syncthreads();
+    const uint32_t nn = counters[2], no0 = counters[3];
+    // Co: unique old ids not in Cn (binary search in the sorted Cn)
+    if (wave == 1) {
+      const uint32_t v0 = static_cast<uint32_t>(lane) < no0 ? arr_o[lane] : kNone;
+      const uint32_t v1 = 64u + lane < no0 ? arr_o[64 + lane] : kNone;
+      bool k0 = v0 != kNone, k1 = v1 != kNone;
+#pragma unroll
+      for (int r = 0; r < 2; ++r) {
+        const uint32_t v = r ? v1 : v0;
+        uint32_t lo = 0, hi = nn;
+        while (lo < hi) {
+          const uint32_t mid = (lo + hi) / 2;
+          if (cid[mid] < v) lo = mid + 1;
+          else hi = mid;
+        }
+        const bool in_cn = lo < nn && cid[lo] == v;
+        if (r) k1 = k1 && !in_cn;
+        else k0 = k0 && !in_cn;
+      }
+      const uint64_t m0 = ballot(k0), m1 = ballot(k1);
+      const uint32_t n0 = static_cast<uint32_t>(popc64(m0));
+      if (k0) cid[nn + mbcnt(m0)] = v0;
+      if (k1) cid[nn + n0 + mbcnt(m1)] = v1;
+      if (lane == 0) counters[3] = n0 + static_cast<uint32_t>(popc64(m1));
+    }
+    __syncthreads();
+    const uint32_t no = counters[3];
+    const uint32_t c = nn + no;
+    for (uint32_t i = threadIdx.x; i < c; i += 256) {
+      const uint32_t v = cid[i];
+      cg[i] = sub_of(a.sub_off, a.h, v);
+      cw[i] = a.keys[static_cast<uint64_t>(v) * a.k + a.k - 1];
+      cnrm[i] = a.nrm2[v];
+      cqe[i] = sqrtf(a.qerr2[v]) * (1.0f + gam) * 1.0001f;
+    }
+    const uint32_t nI = (nn + 15) / 16, nC = (c + 15) / 16;
+    uint32_t T = 0;
+    for (uint32_t I = 0; I < nI; ++I) T += nC - I;
+    floatx4_t acc[kMfmaTilesPerWave];
+#pragma unroll
+    for (uint32_t t = 0; t < kMfmaTilesPerWave; ++t) acc[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    if (a.stage_f32) {
+      // FP32 rows in LDS; MFMA operands converted to BF16 on the fly
+      for (uint32_t idx = threadIdx.x; idx < nC * 16 * a.nc; idx += 256) {
+        const uint32_t e = idx / a.nc, ch = idx - e * a.nc;
+        *reinterpret_cast<float4*>(frows + e * fstride + 4 * ch) =
+            e < c ? *reinterpret_cast<const float4*>(a.X + static_cast<uint64_t>(cid[e]) * a.ld + 4 * ch)
+                  : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+      __syncthreads();
+#pragma unroll
+      for (uint32_t sl = 0; sl < kMfmaTilesPerWave; ++sl) {
+        uint32_t tp = static_cast<uint32_t>(wave) + 4u * sl;
+        if (tp >= T) break;
+        uint32_t I = 0;
+        while (tp >= nC - I) {
+          tp -= nC - I;
+          ++I;
+        }
+        const uint32_t J = I + tp;
+        const float* ra = frows + (16 * I + lane % 16) * fstride + 8 * (lane / 16);
+        const float* rb = frows + (16 * J + lane % 16) * fstride + 8 * (lane / 16);
+        for (uint32_t kb = 0; kb < a.dpad; kb += 32) {
+          shortx8_t va, vb;
+#pragma unroll
+          for (int e = 0; e < 8; ++e) {
+            const bool in = kb + 8 * (lane / 16) + e < a.dim;
+            va[e] = in ? bf16_rne(ra[kb + e]) : 0;
+            vb[e] = in ? bf16_rne(rb[kb + e]) : 0;
+          }
+          acc[sl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, va),
+                                                            __builtin_bit_cast(bf16x8_t, vb), acc[sl], 0, 0, 0);
+        }
+      }
+    } else {
+      // BF16 slices of the dimensions through LDS
+      for (uint32_t s0 = 0; s0 < a.dpad; s0 += a.slice) {
+        const uint32_t sw = min(a.slice, a.dpad - s0);   // multiple of 32
+        __syncthreads();
+        const uint32_t per_row = sw / 8;
+        for (uint32_t idx = threadIdx.x; idx < nC * 16 * per_row; idx += 256) {
+          const uint32_t e = idx / per_row, q = idx - e * per_row;
+          const uint32_t t0 = s0 + 8 * q;
+          shortx8_t v8;
+          if (e < c && t0 < a.dim) {
+            const uint64_t v = cid[e];
+            if (a.xb) {
+              v8 = *reinterpret_cast<const shortx8_t*>(a.xb + v * a.dim + t0);
+            } else {
+              const float4 f0 = *reinterpret_cast<const float4*>(a.X + v * a.ld + t0);
+              const float4 f1 = t0 + 4 < a.dim ? *reinterpret_cast<const float4*>(a.X + v * a.ld + t0 + 4)
+                                               : make_float4(0.f, 0.f, 0.f, 0.f);
+              v8[0] = bf16_rne(f0.x); v8[1] = bf16_rne(f0.y); v8[2] = bf16_rne(f0.z); v8[3] = bf16_rne(f0.w);
+              v8[4] = bf16_rne(f1.x); v8[5] = bf16_rne(f1.y); v8[6] = bf16_rne(f1.z); v8[7] = bf16_rne(f1.w);
+            }
+          } else {
+            v8 = shortx8_t{0, 0, 0, 0, 0, 0, 0, 0};
+          }
+          *reinterpret_cast<shortx8_t*>(brows + e * srow + 8 * q) = v8;
+        }
+        __syncthreads();
+#pragma unroll
+        for (uint32_t sl = 0; sl < kMfmaTilesPerWave; ++sl) {
+          uint32_t tp = static_cast<uint32_t>(wave) + 4u * sl;
+          if (tp >= T) break;
+          uint32_t I = 0;
+          while (tp >= nC - I) {
+            tp -= nC - I;
+            ++I;
+          }
+          const uint32_t J = I + tp;
+          for (uint32_t kb = 0; kb < sw; kb += 32) {
+            const shortx8_t ra = *reinterpret_cast<const shortx8_t*>(brows + (16 * I + lane % 16) * srow + kb + 8 * (lane / 16));
+            const shortx8_t rb = *reinterpret_cast<const shortx8_t*>(brows + (16 * J + lane % 16) * srow + kb + 8 * (lane / 16));
+            acc[sl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ra),
+                                                              __builtin_bit_cast(bf16x8_t, rb), acc[sl], 0, 0, 0);
+          }
+        }
+      }
+    }
+    // Screen.  With a^, b^ the BF16 operands, e_a = |a - a^| (FP32 residual
+    // norm, inflated by its own rounding bound) and gamma = (d+4)u/(1-(d+4)u):
+    //   |<a^,b^>_mfma - <a,b>| <= e_a (|b| + e_b) + |a| e_b + gamma (|a| + e_a)(|b| + e_b)
+    // (Cauchy-Schwarz on the residuals plus any-order FP32 accumulation);
+    // the L2 estimate adds the FP32 norms' own error.  The canonical FP32
+    // distance of the oracle is within gamma of the true value.  The bound is
+    // doubled; a pair passes when its estimate minus the bound could still
+    // beat the worst entry of either end.
+#pragma unroll
+    for (uint32_t sl = 0; sl < kMfmaTilesPerWave; ++sl) {
+      uint32_t tp = static_cast<uint32_t>(wave) + 4u * sl;
+      if (tp >= T) break;
+      uint32_t I = 0;
+      while (tp >= nC - I) {
+        tp -= nC - I;
+        ++I;
+      }
+      const uint32_t J = I + tp;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const uint32_t i = 16 * I + 4 * (lane / 16) + r, j = 16 * J + lane % 16;
+        const bool valid = i < nn && j < c && j > i && cg[i] != cg[j];
+        if (!valid) continue;
+        const float G = acc[sl][r];
+        const float na2 = cnrm[i], nb2 = cnrm[j];
+        const float na = sqrtf(na2) * (1.0f + gam) * 1.0001f, nb = sqrtf(nb2) * (1.0f + gam) * 1.0001f;
+        const float ea = cqe[i], eb = cqe[j];
+        const float eg = ea * (nb + eb) + na * eb + gam * (na + ea) * (nb + eb) + 1e-30f;
+        float dt, err;
+        if (a.metric == kL2) {
+          dt = na2 + nb2 - 2.0f * G;
+          err = gam * (na2 + nb2) + 2.0f * eg + 4.0f * u32 * (na2 + nb2 + 2.0f * fabsf(G));
+          err += gam * (fabsf(dt) + err);
+        } else if (a.metric == kIP) {
+          dt = -G;
+          err = eg + gam * na * nb;
+        } else {
+          dt = 1.0f - G;
+          err = eg + gam * na * nb + u32 * (1.0f + fabsf(G));
+        }
+        err *= 2.0f;
+        const float thr = fmaxf(key_dist(cw[i]), key_dist(cw[j]));
+        if (dt - err <= thr)
+          atomicOr(reinterpret_cast<unsigned long long*>(&pmask[2 * i + j / 64]), 1ull << (j % 64));
+      }
+    }
+    __syncthreads();
+    // prefix counts of passing partners per Cn row (one wave, nn <= 64)
+    if (wave == 0) {
+      const uint32_t cnt = static_cast<uint32_t>(lane) < nn
+                               ? static_cast<uint32_t>(__popcll(pmask[2 * lane]) + __popcll(pmask[2 * lane + 1]))
+                               : 0u;
+      uint32_t incl = cnt;
+#pragma unroll
+      for (int st = 1; st < 64; st <<= 1) {
+        const uint32_t o = static_cast<uint32_t>(__shfl_up(static_cast<int>(incl), st, 64));
+        if (lane >= st) incl += o;
+      }
+      rowoff[lane + 1] = incl;
+      if (lane == 0) rowoff[0] = 0;
+    }
+    __syncthreads();
+    const uint32_t np = rowoff[nn];
+    if (threadIdx.x == 0 && np) atomicAdd(a.rechecked, np);
+    // exact re-scoring of the passing pairs, enumerated flat over all rows;
+    // proposals are staged in LDS and flushed once per vertex
+    for (uint32_t b = 0; b < np; b += ngroups) {
+      const uint32_t idx = b + gid;
+      const bool act = idx < np;
+      uint32_t i = 0, j = 0;
+      if (act) {
+        uint32_t lo = 0, hi = nn;  // the row holding idx: last row with rowoff <= idx
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) / 2;
+          if (rowoff[mid] <= idx) lo = mid;
+          else hi = mid;
+        }
+        i = lo;
+        j = select_bit(pmask[2 * i], pmask[2 * i + 1], idx - rowoff[i]);
+      }
+      const uint32_t vi = cid[i], vj = cid[j];
+      const float* ri = a.stage_f32 ? frows + i * fstride : a.X + static_cast<uint64_t>(vi) * a.ld;
+      const float* rj = a.stage_f32 ? frows + j * fstride : a.X + static_cast<uint64_t>(vj) * a.ld;
+      const float dd = pair_distance<MMAX>(ri, rj, a.metric, a.nc, P, M, l, act);
+      if (act && l == 0) {
+        const uint64_t to_i = make_key(dd, vj), to_j = make_key(dd, vi);
+        if (to_i < cw[i]) stage_proposal(a, vi, to_i, &counters[4], stgt, skey);
+        if (to_j < cw[j]) stage_proposal(a, vj, to_j, &counters[4], stgt, skey);
+      }
+    }
     __syncthreads();
     const uint32_t ns = min(counters[4], kPropStage);
     if (threadIdx.x == 0 && ns) counters[5] = atomicAdd(a.ptotal, ns);
@@ -691,6 +1114,7 @@ struct RoundPlan {
   int nr, mmax;
   uint32_t join_grid;
   size_t join_smem;
+  bool use_mfma;
 };
 
 // one refinement round; only kernel launches (graph-capturable)
@@ -706,7 +1130,15 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
                      b.rev);
   // Update
   if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
-  if ((e = launch_join(rp.ja, rp.nr, rp.mmax, rp.join_grid, rp.join_smem, s)) != hipSuccess) return e;
+  if (rp.use_mfma) {
+    if (rp.mmax == 4)
+      hipLaunchKernelGGL(join_mfma_kernel<4>, dim3(rp.join_grid), dim3(256), rp.join_smem, s, rp.ja);
+    else
+      hipLaunchKernelGGL(join_mfma_kernel<16>, dim3(rp.join_grid), dim3(256), rp.join_smem, s, rp.ja);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  } else if ((e = launch_join(rp.ja, rp.nr, rp.mmax, rp.join_grid, rp.join_smem, s)) != hipSuccess) {
+    return e;
+  }
   if ((e = fill_u32(b.pcnt, 0u, N, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(prop_count_kernel, dim3(4096), dim3(256), 0, s, b.ptgt, b.hdr, rp.cap, b.pcnt);
   if ((e = exclusive_scan(b.pcnt, b.poff, N, b.scan_tmp, s)) != hipSuccess) return e;
@@ -764,6 +1196,15 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   const size_t rows_smem = static_cast<size_t>(ccap) * (dim + 4) * 4;
   const bool stage_rows = base_smem + rows_smem <= 96 * 1024;
 
+  // MFMA join when the candidate set fits its tile layout (|Cn| + |Co| <= 128)
+  const bool use_mfma = ccap <= kMfmaMaxC && !(p->flags & FGIM_FLAG_NO_MFMA_JOIN);
+  const uint32_t dpad = (dim + 31) / 32 * 32;
+  const uint32_t slice = std::min<uint32_t>(dpad, 128);
+  const size_t mfma_head = kMfmaMaxC * (4 * 4 + 4 + 4 + 8) + 2 * kMfmaMaxCn * 8 + 68 * 4 + 8 * 4 + kPropStage * 12;
+  const size_t f32_rows = static_cast<size_t>(kMfmaMaxC) * (dim + 4) * 4;
+  const bool stage_f32 = mfma_head + f32_rows <= 80 * 1024;
+  const size_t mfma_smem = mfma_head + (stage_f32 ? f32_rows : static_cast<size_t>(kMfmaMaxC) * (slice + 8) * 2);
+
   uint64_t cap = std::max<uint64_t>(N * std::max<uint32_t>(4 * p->k, 64), 1 << 16);
   cap = std::min<uint64_t>(cap, 0xF0000000ull);
 
@@ -786,13 +1227,20 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     FGIM_TRY(scr.get(&b.zmask, N + 1));
     FGIM_TRY(scr.get(&b.zoff, N + 1));
     FGIM_TRY(scr.get(&b.zero, N + 1));
-    FGIM_TRY(scr.get(&b.hdr, 4));
+    FGIM_TRY(scr.get(&b.hdr, 8));
+    float *nrm2 = nullptr, *qerr2 = nullptr;
+    if (use_mfma) {
+      FGIM_TRY(scr.get(&nrm2, N));
+      FGIM_TRY(scr.get(&qerr2, N));
+      hipLaunchKernelGGL(row_norms_kernel, dim3(grid_for(N, 4)), dim3(256), 0, s, d->base, N, dim, d->ld, nrm2, qerr2);
+      HIP_TRY(hipGetLastError());
+    }
     FGIM_TRY(scr.get(&b.scan_tmp, scan_tmp_words(2 * N + 1) + 16));
     FGIM_TRY(scr.get(&b.sub_off, d->h));
     std::vector<uint64_t> hoff(d->h);
     for (uint32_t i = 0; i < d->h; ++i) hoff[i] = d->subs[i].row_offset;
     HIP_TRY(hipMemcpyAsync(b.sub_off, hoff.data(), 8 * d->h, hipMemcpyHostToDevice, s));
-    HIP_TRY(fill_u32(b.hdr, 0u, 4, s));
+    HIP_TRY(fill_u32(b.hdr, 0u, 8, s));
     hipLaunchKernelGGL(to_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, ids, dist, nk, b.keys, b.flags);
     HIP_TRY(hipGetLastError());
 
@@ -826,9 +1274,21 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     ja.M = M;
     ja.ccap = ccap;
     ja.stage_rows = stage_rows;
-    rp.join_smem = base_smem + (stage_rows ? rows_smem : 0);
+    ja.nrm2 = nrm2;
+    ja.qerr2 = qerr2;
+    ja.stage_f32 = stage_f32;
+    ja.xb = (p->precision == FGIM_BF16 && d->base_lp && dim % 8 == 0) ? static_cast<const uint16_t*>(d->base_lp) : nullptr;
+    ja.dim = dim;
+    ja.dpad = dpad;
+    ja.slice = slice;
+    ja.rechecked = b.hdr + 4;
+    rp.use_mfma = use_mfma;
+    rp.join_smem = use_mfma ? mfma_smem : base_smem + (stage_rows ? rows_smem : 0);
     rp.join_grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));
-    if (rp.join_smem > 64 * 1024)
+    if (use_mfma && rp.join_smem > 64 * 1024)
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(rp.mmax == 4 ? join_mfma_kernel<4> : join_mfma_kernel<16>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(rp.join_smem)));
+    if (!use_mfma && rp.join_smem > 64 * 1024)
       HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(rp.nr == 1 ? (rp.mmax == 4 ? join_kernel<1, 4> : join_kernel<1, 16>)
                                                                            : (rp.mmax == 4 ? join_kernel<2, 4> : join_kernel<2, 16>)),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(rp.join_smem)));
@@ -878,7 +1338,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
       hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, b.T);
       HIP_TRY(hipGetLastError());
     }
-    uint32_t hh[4] = {0, 0, 0, 0};
+    uint32_t hh[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     HIP_TRY(hipMemcpyAsync(hh, b.hdr, sizeof(hh), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
     if (hh[1] > cap) {
@@ -896,6 +1356,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
       stats->ms_stage[1] = ms;
       stats->repaired = hh[2];
       stats->proposals = hh[3];
+      stats->rechecked = hh[4];
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
     }

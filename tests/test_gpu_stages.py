@@ -36,16 +36,20 @@ def _stage1(name, sizes):
 
 
 @pytest.mark.parametrize("name,sizes", CASES, ids=IDS)
-@pytest.mark.parametrize("rounds,repair", [(1, True), (2, False), (None, True)])
-def test_refine_matches_oracle(name, sizes, rounds, repair):
+@pytest.mark.parametrize("rounds,repair,join", [(1, True, "mfma"), (2, False, "mfma"), (None, True, "mfma"),
+                                                (None, True, "fp32")])
+def test_refine_matches_oracle(name, sizes, rounds, repair, join):
     cfg, X, graphs, m, ids, dist = _stage1(name, sizes)
     rounds = cfg.rounds if rounds is None else rounds
     print(f"case {name} rounds={rounds} repair={repair}", flush=True)
     oi, od, of, oT, ost = oracle.refine(X, graphs, _u32(ids), dist.cpu().numpy(), rounds,
                                         cfg.metric, do_repair=repair)
-    flags = 0 if repair else fg.FGIM_FLAG_NO_REPAIR
+    flags = (0 if repair else fg.FGIM_FLAG_NO_REPAIR) | (fg.FGIM_FLAG_NO_MFMA_JOIN if join == "fp32" else 0)
     T, st = fg.refine(m, fg.params(k=cfg.k, L=cfg.L, rounds=rounds, flags=flags), ids, dist,
                       stats=True)
+    if join == "mfma":
+        # the screen re-scores a fraction of the pairs and never misses a proposal
+        assert 0 < st["rechecked"]
     gi = _u32(ids)
     bad = np.argwhere(gi != oi)
     assert bad.size == 0, f"{len(bad)} id mismatches, first {bad[:3].tolist()}"
