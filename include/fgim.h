@@ -135,6 +135,7 @@ typedef struct {
     uint32_t lanes_per_dist;  /* launch shape actually used */
     uint32_t waves_per_cu;
     uint32_t visited_slots;
+    double ms_tune;           /* time spent on tuner trial launches (autotune=1; 0 on a cache hit) */
 } fgim_stats;
 
 /*

@@ -69,7 +69,8 @@ class Stats(ctypes.Structure):
                 ("searches", ctypes.c_uint64), ("proposals", ctypes.c_uint64),
                 ("repaired", ctypes.c_uint64), ("rechecked", ctypes.c_uint64),
                 ("L_used", ctypes.c_uint32), ("lanes_per_dist", ctypes.c_uint32),
-                ("waves_per_cu", ctypes.c_uint32), ("visited_slots", ctypes.c_uint32)]
+                ("waves_per_cu", ctypes.c_uint32), ("visited_slots", ctypes.c_uint32),
+                ("ms_tune", ctypes.c_double)]
 
     def to_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "ms_stage"}

@@ -70,14 +70,19 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
 }
 
 // One wavefront per adjacency row: every id must be FGIM_NONE or < n, not
-// the row's own id, and unique within the row.  Sets *err on a violation.
+// the row's own id, and unique within the row.  Sets *err on a violation and,
+// when min_deg is given, lowers *min_deg to the smallest out-degree seen.
 __global__ void __launch_bounds__(256) validate_graph_kernel(const uint32_t* adj, uint32_t n,
-                                                             uint32_t stride, uint32_t* err) {
+                                                             uint32_t stride, uint32_t* err,
+                                                             uint32_t* min_deg) {
   const uint32_t wave = threadIdx.x / 64;
   const int lane = lane_id();
+  uint32_t mdeg = 0xFFFFFFFFu;
   for (uint64_t row = blockIdx.x * 4ull + wave; row < n; row += gridDim.x * 4ull) {
     const uint32_t v0 = lane < static_cast<int>(stride) ? adj[row * stride + lane] : kNone;
     const uint32_t v1 = lane + 64 < static_cast<int>(stride) ? adj[row * stride + 64 + lane] : kNone;
+    const uint32_t deg = static_cast<uint32_t>(popc64(ballot(v0 != kNone)) + popc64(ballot(v1 != kNone)));
+    mdeg = deg < mdeg ? deg : mdeg;
     bool bad = (v0 != kNone && (v0 >= n || v0 == row)) || (v1 != kNone && (v1 >= n || v1 == row));
     for (int s = 1; s < 64; ++s) {
       const uint32_t w0 = __shfl_xor(v0, s, 64);
@@ -95,12 +100,13 @@ __global__ void __launch_bounds__(256) validate_graph_kernel(const uint32_t* adj
     }
     if (ballot(bad) != 0 && lane == 0) atomicOr(err, 1u);
   }
+  if (min_deg && lane == 0 && mdeg != 0xFFFFFFFFu) atomicMin(min_deg, mdeg);
 }
 
 hipError_t validate_graph(const uint32_t* adj, uint32_t n, uint32_t stride, uint32_t* err,
-                          hipStream_t s) {
+                          hipStream_t s, uint32_t* min_deg = nullptr) {
   uint32_t blocks = std::min<uint32_t>((n + 3) / 4, 8192);
-  hipLaunchKernelGGL(validate_graph_kernel, dim3(blocks), dim3(256), 0, s, adj, n, stride, err);
+  hipLaunchKernelGGL(validate_graph_kernel, dim3(blocks), dim3(256), 0, s, adj, n, stride, err, min_deg);
   return hipGetLastError();
 }
 
@@ -219,25 +225,23 @@ fgim_status check_dataset(const fgim_dataset* d, bool need_cross) {
   return FGIM_OK;
 }
 
-// Launch shape of the beam kernel.
-struct BeamShape {
-  uint32_t P, M, mmax, nr, vis_log2, waves;
-};
-
 fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* p, BeamShape* out) {
   const uint32_t nc = dim / 4;
   const uint32_t N = ceil_pow2(nc);
-  uint32_t P = p && p->lanes_per_dist ? p->lanes_per_dist : std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, N), N / 4));
+  // defaults measured on 2 x 500k rows, d=128, L=64: two chunks per lane, 32
+  // waves per CU and a 1024-slot visited cache keep ~28 waves resident per CU
+  // (VGPR- and LDS-limited) and beat the 4-chunk/16-wave shape by 23 %
+  uint32_t P = p && p->lanes_per_dist ? p->lanes_per_dist : std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, N), N / 2));
   if (!is_pow2(P) || P > 64 || P > N) return fail(FGIM_ERR_INVALID_ARG, "lanes_per_dist %u must be a power of 2 <= min(64, %u)", P, N);
   const uint32_t M = N / P;
   if (M > 16) return fail(FGIM_ERR_INVALID_ARG, "lanes_per_dist %u too small for dim %u", P, dim);
   const uint32_t cap = std::max(L, k);
   uint32_t nr = cap <= 64 ? 1 : (cap <= 128 ? 2 : 4);
-  uint32_t slots = p && p->visited_slots ? p->visited_slots : std::min<uint32_t>(8192, std::max<uint32_t>(1024, ceil_pow2(32 * L)));
+  uint32_t slots = p && p->visited_slots ? p->visited_slots : std::min<uint32_t>(8192, std::max<uint32_t>(1024, ceil_pow2(16 * L)));
   if (!is_pow2(slots) || slots < 64 || slots > 16384) return fail(FGIM_ERR_INVALID_ARG, "visited_slots %u must be a power of 2 in 64..16384", slots);
-  uint32_t waves = p && p->waves_per_cu ? p->waves_per_cu : 16;
+  uint32_t waves = p && p->waves_per_cu ? p->waves_per_cu : 32;
   if (waves > 64) return fail(FGIM_ERR_INVALID_ARG, "waves_per_cu %u > 64", waves);
-  *out = BeamShape{P, M, M <= 4 ? 4u : 16u, nr, ilog2(slots), waves};
+  *out = BeamShape{P, M, M <= 2 ? 2u : (M <= 4 ? 4u : 16u), nr, ilog2(slots), waves};
   return FGIM_OK;
 }
 
@@ -251,9 +255,14 @@ hipError_t launch_beam(const BeamArgs& a, bool l2, int fmt, const BeamShape& s, 
   return launch_beam_fp8(a, l2, s.nr, s.mmax, grid, smem, st);
 }
 
-uint32_t tuned_beam_width(const fgim_dataset* d, const fgim_params* p, uint32_t lo) {
-  (void)d;
-  return std::max(lo, p->L);
+fgim_status rerank_for(const fgim_params* p, uint32_t L, uint32_t* out) {
+  uint32_t rerank = p->rerank ? p->rerank : std::min<uint32_t>(L, 2 * p->k);
+  if (p->precision != FGIM_FP32 && (rerank < p->k || rerank > L)) {
+    if (p->rerank) return fail(FGIM_ERR_INVALID_ARG, "rerank %u must be in k..L", p->rerank);
+    rerank = std::min(L, std::max(rerank, p->k));
+  }
+  *out = rerank;
+  return FGIM_OK;
 }
 
 fgim_status quantize_into(const float* base, uint64_t n, uint32_t dim, uint64_t ld, fgim_precision prec,
@@ -283,22 +292,14 @@ fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32
   if (p->L == 0 || p->L > FGIM_MAX_L) return fail(FGIM_ERR_INVALID_ARG, "L = %u out of 1..%u", p->L, FGIM_MAX_L);
   if (p->precision != FGIM_FP32 && p->precision != FGIM_BF16 && p->precision != FGIM_FP8_E4M3)
     return fail(FGIM_ERR_INVALID_ARG, "unknown precision %d", (int)p->precision);
-  uint32_t L = p->L;
-  if (p->autotune) {
-    uint32_t min_local = 0;  // worst case: a vertex without local neighbours
-    uint32_t lo = fgim_min_beam_width(p->k, min_local, d->h);
-    L = tuned_beam_width(d, p, lo);
+  {  // argument errors before anything is enqueued
+    uint32_t rr = 0;
+    BeamShape sh;
+    FGIM_TRY(rerank_for(p, p->L, &rr));
+    FGIM_TRY(beam_shape(d->dim, p->L, p->k, p, &sh));
   }
-  uint32_t rerank = p->rerank ? p->rerank : std::min<uint32_t>(L, 2 * p->k);
-  if (p->precision != FGIM_FP32 && (rerank < p->k || rerank > L)) {
-    if (p->rerank) return fail(FGIM_ERR_INVALID_ARG, "rerank %u must be in k..L", p->rerank);
-    rerank = std::min(L, std::max(rerank, p->k));
-  }
-  BeamShape shape;
-  FGIM_TRY(beam_shape(d->dim, L, p->k, p, &shape));
-
   Scratch scr(s);
-  uint32_t* hdr = nullptr;  // [0] queue head, [1] error flag
+  uint32_t* hdr = nullptr;  // [0] queue head, [1] error flag, [2] smallest input out-degree
   unsigned long long* cnt = nullptr;
   SubDev* subs = nullptr;
   FGIM_TRY(scr.get(&hdr, 4));
@@ -308,9 +309,12 @@ fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32
   for (uint32_t i = 0; i < d->h; ++i)
     hs[i] = SubDev{d->subs[i].row_offset, d->subs[i].adj, d->subs[i].n, d->subs[i].adj_stride, d->subs[i].entry, 0};
   HIP_TRY(hipMemcpyAsync(subs, hs.data(), sizeof(SubDev) * d->h, hipMemcpyHostToDevice, s));
-  HIP_TRY(fill_u32(hdr, 0u, 4, s));
+  HIP_TRY(fill_u32(hdr, 0u, 2, s));
+  HIP_TRY(fill_u32(hdr + 2, 0xFFFFFFFFu, 2, s));
   HIP_TRY(fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, 8, s));
-  for (uint32_t i = 0; i < d->h; ++i) HIP_TRY(validate_graph(d->subs[i].adj, d->subs[i].n, d->subs[i].adj_stride, hdr + 1, s));
+  for (uint32_t i = 0; i < d->h; ++i)
+    HIP_TRY(validate_graph(d->subs[i].adj, d->subs[i].n, d->subs[i].adj_stride, hdr + 1, s,
+                           p->autotune ? hdr + 2 : nullptr));
 
   const void* lp = d->base_lp;
   const float* lps = d->base_lp_scale;
@@ -343,19 +347,41 @@ fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32
   a.dim = d->dim;
   a.subs = subs;
   a.h = d->h;
-  a.L = L;
   a.k = p->k;
-  a.rerank = rerank;
   a.n_items = d->n_total;
+  a.item_stride = 1;
+  a.compact_out = 0;
   a.out_ids = ids;
   a.out_dist = dist;
   a.counter = hdr;
   a.err = hdr + 1;
+  a.search_mode = 0;
+  const int fmt = p->precision == FGIM_FP32 ? kF32 : (p->precision == FGIM_BF16 ? kBF16 : kFP8);
+  const bool l2 = d->metric == FGIM_L2;
+
+  uint32_t L = p->L;
+  BeamShape shape;
+  double ms_tune = 0.0;
+  if (p->autotune) {
+    // trial launches mean nothing on a malformed graph: check it first
+    uint32_t hv[2] = {0, 0};
+    HIP_TRY(hipMemcpyAsync(hv, hdr + 1, sizeof(hv), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hv[0]) return fail(FGIM_ERR_GRAPH, "an adjacency list holds an out-of-range id, a self-loop or a duplicate");
+    uint32_t lo = fgim_min_beam_width(p->k, hv[1], d->h);
+    if (p->precision != FGIM_FP32 && p->rerank) lo = std::max(lo, p->rerank);
+    FGIM_TRY(tune_stage1(a, d, p, fmt, l2, lo, &L, &shape, &ms_tune, s));
+  } else {
+    FGIM_TRY(beam_shape(d->dim, L, p->k, p, &shape));
+  }
+  uint32_t rerank = 0;
+  FGIM_TRY(rerank_for(p, L, &rerank));
+  a.L = L;
+  a.rerank = rerank;
   a.stats = cnt;
   a.vis_log2 = shape.vis_log2;
   a.P = shape.P;
   a.M = shape.M;
-  a.search_mode = 0;
 
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (stats) {
@@ -363,8 +389,7 @@ fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32
     HIP_TRY(hipEventCreate(&e1));
     HIP_TRY(hipEventRecord(e0, s));
   }
-  int fmt = p->precision == FGIM_FP32 ? kF32 : (p->precision == FGIM_BF16 ? kBF16 : kFP8);
-  HIP_TRY(launch_beam(a, d->metric == FGIM_L2, fmt, shape, s));
+  HIP_TRY(launch_beam(a, l2, fmt, shape, s));
   if (stats) HIP_TRY(hipEventRecord(e1, s));
 
   uint32_t herr = 0;
@@ -383,6 +408,7 @@ fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32
     stats->lanes_per_dist = shape.P;
     stats->waves_per_cu = shape.waves;
     stats->visited_slots = 1u << shape.vis_log2;
+    stats->ms_tune = ms_tune;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
   }
@@ -471,6 +497,7 @@ fgim_status fgim_search(const float* base, uint64_t n, uint32_t dim, uint64_t ld
   HIP_TRY(fill_u32(hdr, 0u, 4, s));
   HIP_TRY(validate_graph(adj, static_cast<uint32_t>(n), stride, hdr + 1, s));
   BeamArgs a{};
+  a.item_stride = 1;
   a.X = base;
   a.ld = ld;
   a.nc = dim / 4;

@@ -54,6 +54,8 @@ struct BeamArgs {
   uint32_t k;              // top-k of stage 1 / results kept by a search
   uint32_t rerank;         // entries per search re-scored in FP32 (low precision)
   uint64_t n_items;
+  uint64_t item_stride;    // stage-1 item t is vertex t * item_stride (1: every vertex)
+  int compact_out;         // 1: stage-1 item t writes output row t instead of row u
   uint32_t* out_ids;
   float* out_dist;
   uint32_t* counter;       // work-queue head, zero at launch
@@ -325,7 +327,8 @@ __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
     }
 
     // ---- stage 1 item: global vertex u ----
-    const uint64_t u = item;
+    const uint64_t u = static_cast<uint64_t>(item) * a.item_stride;
+    const uint64_t orow = a.compact_out ? item : u;
     uint32_t gi = 0;
     for (uint32_t i = 0; i < a.h; ++i)
       if (u >= a.subs[i].off) gi = i;
@@ -401,8 +404,8 @@ __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
       const uint32_t e = r * 64 + lane_id();
       if (e < a.k) {
         const uint64_t kk = topk.key[r];
-        a.out_ids[u * a.k + e] = kk == kSentinel ? kNone : key_id(kk);
-        a.out_dist[u * a.k + e] = key_dist(kk);
+        a.out_ids[orow * a.k + e] = kk == kSentinel ? kNone : key_id(kk);
+        a.out_dist[orow * a.k + e] = key_dist(kk);
       }
     }
   }

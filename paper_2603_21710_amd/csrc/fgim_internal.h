@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include "beam_impl.h"
+#include "fgim.h"
 
 namespace fgim {
 
@@ -16,6 +17,29 @@ hipError_t launch_beam_bf16(const BeamArgs& a, bool l2, int nr, int mmax, dim3 g
 hipError_t launch_beam_fp8(const BeamArgs& a, bool l2, int nr, int mmax, dim3 grid, size_t smem,
                            hipStream_t s);
 
+// Launch shape of the beam kernel: P lanes per distance, M = padded chunks /
+// P chunks per lane (kernel instance mmax >= M), nr pool registers per lane,
+// 2^vis_log2 visited-cache slots, `waves` workgroups (one wave each) per CU.
+struct BeamShape {
+  uint32_t P, M, mmax, nr, vis_log2, waves;
+};
+
+// api.hip: the shape for (dim, L, k), taking every non-zero launch field of
+// p as given and the measured defaults for the rest
+fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* p, BeamShape* out);
+size_t beam_smem(const BeamShape& s);
+hipError_t launch_beam(const BeamArgs& a, bool l2, int fmt, const BeamShape& s, hipStream_t st);
+// entries of each search re-scored in FP32 in the low-precision forms
+fgim_status rerank_for(const fgim_params* p, uint32_t L, uint32_t* out);
+
+// tune.hip: with a.counter pointing at a zeroed-by-the-callee queue head, a
+// graph already validated, and lo the minimum-querying bound on L, choose
+// the beam width (*L, lowered only in the batched or low-precision forms) and
+// the launch shape; ms_tune gets the time spent on trial launches (0 when
+// both came from the cache)
+fgim_status tune_stage1(const BeamArgs& a, const fgim_dataset* d, const fgim_params* p, int fmt, bool l2,
+                        uint32_t lo, uint32_t* L, BeamShape* shape, double* ms_tune, hipStream_t s);
+
 template <bool L2, int FMT>
 hipError_t launch_beam_dispatch(const BeamArgs& a, int nr, int mmax, dim3 grid, size_t smem,
                                 hipStream_t s) {
@@ -24,6 +48,9 @@ hipError_t launch_beam_dispatch(const BeamArgs& a, int nr, int mmax, dim3 grid, 
     hipLaunchKernelGGL((beam_kernel<L2, FMT, NR_, MM_>), grid, dim3(64), smem, s, a); \
     return hipGetLastError();                                                           \
   }
+  FGIM_BEAM_CASE(1, 2)
+  FGIM_BEAM_CASE(2, 2)
+  FGIM_BEAM_CASE(4, 2)
   FGIM_BEAM_CASE(1, 4)
   FGIM_BEAM_CASE(2, 4)
   FGIM_BEAM_CASE(4, 4)

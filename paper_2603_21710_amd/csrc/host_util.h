@@ -17,7 +17,6 @@ fgim_status fail(fgim_status s, const char* fmt, ...);
 int device_cus();
 hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 fgim_status check_dataset(const fgim_dataset* d, bool need_cross);
-uint32_t tuned_beam_width(const fgim_dataset* d, const fgim_params* p, uint32_t lo);
 // a non-blocking, default-priority stream owned by the library (one per
 // device), used where work has to be captured into a hipGraph
 hipError_t library_stream(hipStream_t* out);
