@@ -136,6 +136,8 @@ typedef struct {
     uint32_t waves_per_cu;
     uint32_t visited_slots;
     double ms_tune;           /* time spent on tuner trial launches (autotune=1; 0 on a cache hit) */
+    uint64_t repair_batches;  /* speculative batches of the indegree-repair passes */
+    uint64_t repair_alone;    /* repair steps that needed more than one attempt (run alone) */
 } fgim_stats;
 
 /*
@@ -166,6 +168,23 @@ fgim_status fgim_cross_query(const fgim_dataset* data, const fgim_params* params
 fgim_status fgim_refine(const fgim_dataset* data, const fgim_params* params,
                         uint32_t* knn_ids, float* knn_dist, uint32_t* indegree,
                         fgim_stats* stats, void* stream);
+
+/*
+ * Indegree repair alone (Section 4.2.2, Algorithm 4) on a k-NNG whose rows
+ * are sorted by (distance, id) with FGIM_NONE padding at the end: T is the
+ * indegree histogram of the lists; every v* with T(v*) = 0, in ascending id,
+ * tries its neighbours v from the closest and enters N(v) in place of the
+ * farthest entry that is not already a repair edge and whose indegree
+ * exceeds 1 (or takes a free slot), flagged as a repair edge.  The same pass
+ * ends every refinement round of fgim_refine.
+ * In/out (device, n x k): knn_ids, knn_dist.  indegree (device, n,
+ * nullable) receives T after the pass; *repaired (host, nullable) the number
+ * of vertices that gained an in-edge (the call then synchronises).
+ * Errors: FGIM_ERR_INVALID_ARG (arguments), FGIM_ERR_GRAPH (an id >= n,
+ * checked before any list changes; the call synchronises for it).
+ */
+fgim_status fgim_repair(uint32_t* knn_ids, float* knn_dist, uint64_t n, uint32_t k,
+                        uint32_t* indegree, uint64_t* repaired, void* stream);
 
 /*
  * Stage 3, k-NNG -> PG (Section 4.3, Algorithm 5).  Neighbour selection

@@ -30,7 +30,7 @@ PRECISIONS = {"fp32": FGIM_FP32, "bf16": FGIM_BF16, "fp8": FGIM_FP8_E4M3}
 STATUS = {0: "FGIM_OK", 1: "FGIM_ERR_INVALID_ARG", 2: "FGIM_ERR_GRAPH",
           3: "FGIM_ERR_OUT_OF_MEMORY", 4: "FGIM_ERR_DEVICE", 5: "FGIM_ERR_UNSUPPORTED"}
 
-EXPORTS = ["fgim_cross_query", "fgim_refine", "fgim_prune", "fgim_merge", "fgim_search",
+EXPORTS = ["fgim_cross_query", "fgim_refine", "fgim_repair", "fgim_prune", "fgim_merge", "fgim_search",
            "fgim_quantize", "fgim_min_beam_width", "fgim_status_string", "fgim_last_error"]
 
 
@@ -70,7 +70,8 @@ class Stats(ctypes.Structure):
                 ("repaired", ctypes.c_uint64), ("rechecked", ctypes.c_uint64),
                 ("L_used", ctypes.c_uint32), ("lanes_per_dist", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("visited_slots", ctypes.c_uint32),
-                ("ms_tune", ctypes.c_double)]
+                ("ms_tune", ctypes.c_double), ("repair_batches", ctypes.c_uint64),
+                ("repair_alone", ctypes.c_uint64)]
 
     def to_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "ms_stage"}
@@ -98,6 +99,7 @@ def lib() -> ctypes.CDLL:
             "fgim_search": [vp, u64, u32, u64, i32, vp, u32, u32, vp, u64, u64, u32, u32, vp,
                             vp, vp],
             "fgim_quantize": [vp, u64, u32, u64, i32, vp, vp, vp],
+            "fgim_repair": [vp, vp, u64, u32, vp, vp, vp],
         }.items():
             fn = getattr(L, name)
             fn.restype = ctypes.c_int
@@ -193,6 +195,20 @@ def refine(m: Merge, p: Params, ids: torch.Tensor, dist: torch.Tensor, stats: bo
                              dist.data_ptr(), T.data_ptr(), ctypes.byref(st) if st else None,
                              _stream()))
     return T, (st.to_dict() if st else None)
+
+
+def repair(ids: torch.Tensor, dist: torch.Tensor):
+    """Algorithm 4 alone, in place on (ids, dist) [N, k]; returns (indegree
+    int32 [N], number of repaired vertices)."""
+    _need_cuda(ids, "ids", torch.int32)
+    _need_cuda(dist, "dist", torch.float32)
+    if ids.dim() != 2 or ids.shape != dist.shape or not ids.is_contiguous() or not dist.is_contiguous():
+        raise ValueError("ids and dist must be contiguous [N, k] tensors of one shape")
+    T = torch.empty(ids.shape[0], dtype=torch.int32, device=ids.device)
+    n = ctypes.c_uint64()
+    _check(lib().fgim_repair(ids.data_ptr(), dist.data_ptr(), ids.shape[0], ids.shape[1], T.data_ptr(),
+                             ctypes.byref(n), _stream()))
+    return T, n.value
 
 
 def prune(m: Merge, p: Params, ids: torch.Tensor, dist: torch.Tensor, T: torch.Tensor):

@@ -312,6 +312,8 @@ fgim_status fgim_merge(const fgim_dataset* data, const fgim_params* params, uint
     stats->proposals = st2.proposals;
     stats->repaired = st2.repaired;
     stats->rechecked = st2.rechecked;
+    stats->repair_batches = st2.repair_batches;
+    stats->repair_alone = st2.repair_alone;
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   return FGIM_OK;

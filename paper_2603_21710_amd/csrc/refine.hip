@@ -874,10 +874,17 @@ __global__ void zero_mask_kernel(const uint32_t* T, uint64_t N, uint32_t* mask) 
     mask[i] = T[i] == 0u ? 1u : 0u;
 }
 
-__global__ void zero_compact_kernel(const uint32_t* mask, const uint32_t* off, uint64_t N, uint32_t* zero) {
+// list of the zero-indegree vertices in ascending id, with the first key of
+// each one's list (its closest neighbour; these lists never change during
+// the repair pass)
+__global__ void zero_compact_kernel(const uint32_t* mask, const uint32_t* off, uint64_t N, const uint64_t* keys,
+                                    uint32_t k, uint32_t* zero, uint64_t* zkey) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < N;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-    if (mask[i]) zero[off[i]] = static_cast<uint32_t>(i);
+    if (mask[i]) {
+      zero[off[i]] = static_cast<uint32_t>(i);
+      zkey[off[i]] = keys[i * k];
+    }
 }
 
 // The repair runs in a single workgroup, so workgroup-scope coherence is
@@ -897,15 +904,17 @@ FGIM_DEV uint32_t ld_wg32(const uint32_t* p) {
 // replaced.  Lists of the v* themselves never change during the pass (no
 // list holds a zero-indegree vertex before its own turn).
 //
-// The pass keeps this sequential order but runs speculatively: each of the
-// W wavefronts of the one workgroup computes the next step of the order
-// against the current state, then the batch commits its longest prefix in
-// which no step read a list or an indegree that an earlier step of the batch
-// writes (a step writes N(v), T(v') and T(v*); it read N(v) and T of N(v)'s
-// entries).  Steps that needed more than one attempt commit only as the
-// first step of a batch.  Committed steps therefore see exactly the state of
-// the sequential loop, and the next batch starts at the first uncommitted
-// step.
+// The pass keeps this sequential order but runs speculatively, in batches of
+// kRepairBatch consecutive steps: every step makes its first attempt (the
+// closest neighbour v) against the current state, all at once; then the
+// batch commits its longest prefix in which no step read a list or an
+// indegree that an earlier step of the batch writes.  A step writes N(v),
+// T(v') of the entry v' it evicts and T(v*); it read N(v) and T of N(v)'s
+// entries (and v*'s own list, which no step changes).  Earlier writes are
+// looked up in two LDS hash tables that map a vertex to the first step of
+// the batch writing its list or lowering its indegree.  A step whose first
+// attempt fails continues alone, as the first step of a batch.  Committed
+// steps therefore see exactly the state of the sequential loop.
 
 // state read by one attempt (v = the neighbour of v* tried)
 template <int NR>
@@ -913,19 +922,14 @@ struct Attempt {
   uint64_t lk[NR];
   uint32_t lf[NR];
   int drop;      // entry to evict, -1 for a free slot
+  uint32_t tdrop;  // indegree of the evicted entry as read
   bool ok;       // v* can enter N(v)
 };
 
+// decide an attempt from N(v) (keys lk, flags lf) and the entries'
+// indegrees tv
 template <int NR>
-FGIM_DEV Attempt<NR> try_neighbour(const uint64_t* keys, const uint32_t* flags, const uint32_t* T, uint32_t v,
-                                   uint32_t k) {
-  Attempt<NR> at;
-#pragma unroll
-  for (int r = 0; r < NR; ++r) {
-    const uint32_t e = r * 64 + lane_id();
-    at.lk[r] = e < k ? ld_wg64(&keys[static_cast<uint64_t>(v) * k + e]) : kSentinel;
-    at.lf[r] = e < k ? ld_wg32(&flags[static_cast<uint64_t>(v) * k + e]) : 0u;
-  }
+FGIM_DEV void decide_attempt(Attempt<NR>& at, const uint32_t (&tv)[NR], uint32_t k) {
   uint64_t lastk = kSentinel;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
@@ -937,7 +941,7 @@ FGIM_DEV Attempt<NR> try_neighbour(const uint64_t* keys, const uint32_t* flags, 
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
       const uint32_t e = r * 64 + lane_id();
-      cand[r] = e < k && !(at.lf[r] & kFlagReplaced) && ld_wg32(&T[key_id(at.lk[r])]) > 1u;
+      cand[r] = e < k && !(at.lf[r] & kFlagReplaced) && tv[r] > 1u;
     }
 #pragma unroll
     for (int r = NR - 1; r >= 0; --r) {
@@ -945,12 +949,32 @@ FGIM_DEV Attempt<NR> try_neighbour(const uint64_t* keys, const uint32_t* flags, 
       if (at.drop < 0 && m) at.drop = r * 64 + 63 - __clzll(static_cast<long long>(m));
     }
     at.ok = at.drop >= 0;
+#pragma unroll
+    for (int r = 0; r < NR; ++r)
+      if (at.drop >= 0 && r == at.drop / 64) at.tdrop = __builtin_amdgcn_readlane(tv[r], at.drop % 64);
   }
+}
+
+template <int NR>
+FGIM_DEV Attempt<NR> try_neighbour(const uint64_t* keys, const uint32_t* flags, const uint32_t* T, uint32_t v,
+                                   uint32_t k) {
+  Attempt<NR> at;
+  uint32_t tv[NR];
+#pragma unroll
+  for (int r = 0; r < NR; ++r) {
+    const uint32_t e = r * 64 + lane_id();
+    at.lk[r] = e < k ? ld_wg64(&keys[static_cast<uint64_t>(v) * k + e]) : kSentinel;
+    at.lf[r] = e < k ? ld_wg32(&flags[static_cast<uint64_t>(v) * k + e]) : 0u;
+  }
+#pragma unroll
+  for (int r = 0; r < NR; ++r) tv[r] = at.lk[r] != kSentinel ? ld_wg32(&T[key_id(at.lk[r])]) : 0u;
+  decide_attempt<NR>(at, tv, k);
   return at;
 }
 
 // write N(v) with entry `drop` removed (if any) and key nk inserted, and
-// update the indegrees
+// update the indegrees (no other step of a committed prefix touches T of
+// the evicted entry, so its indegree as read is still current)
 template <int NR>
 FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, const Attempt<NR>& at, uint32_t v,
                              uint32_t vs, uint64_t nk, uint32_t k) {
@@ -964,10 +988,8 @@ FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, const
 #pragma unroll
   for (int r = 0; r < NR; ++r)
     if (at.drop >= 0 && r == at.drop / 64) dk = readlane64(at.lk[r], at.drop % 64);
-  if (at.drop >= 0 && lane_id() == 0) {
-    const uint32_t vp = key_id(dk);
-    __hip_atomic_store(&T[vp], ld_wg32(&T[vp]) - 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  }
+  if (at.drop >= 0 && lane_id() == 0)
+    __hip_atomic_store(&T[key_id(dk)], at.tdrop - 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int e = r * 64 + lane_id();
@@ -987,79 +1009,203 @@ FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, const
 }
 
 constexpr int kRepairWaves = 16;
+constexpr int kRepairHash = 2048;  // slots per table (a batch notes at most 128 ids in each)
+constexpr uint32_t kTail = 4;      // list entries whose indegree a first attempt reads
+
+template <int NR>
+struct RepairShape {
+  static constexpr int kSteps = NR == 1 ? 8 : 4;  // steps per wave and batch
+  static constexpr int kBatch = kSteps * kRepairWaves;
+};
+
+FGIM_DEV uint32_t repair_slot(uint32_t id) { return (id * 0x9E3779B1u) >> 21; }
+
+// record that step i writes id (keeps the smallest step per id)
+FGIM_DEV void note_write(uint32_t* hid, uint32_t* hstep, uint32_t id, uint32_t i) {
+  uint32_t s = repair_slot(id);
+  for (;;) {
+    const uint32_t prev = atomicCAS(&hid[s], kNone, id);
+    if (prev == kNone || prev == id) break;
+    s = (s + 1) & (kRepairHash - 1);
+  }
+  atomicMin(&hstep[s], i);
+}
+
+// first step of the batch that writes id (kNone: none)
+FGIM_DEV uint32_t first_write(const uint32_t* hid, const uint32_t* hstep, uint32_t id) {
+  uint32_t s = repair_slot(id);
+  for (;;) {
+    const uint32_t cur = hid[s];
+    if (cur == id) return hstep[s];
+    if (cur == kNone) return kNone;
+    s = (s + 1) & (kRepairHash - 1);
+  }
+}
 
 template <int NR>
 __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* keys, uint32_t* flags, uint32_t* T,
-                                                                   const uint32_t* zero, const uint32_t* zcount,
-                                                                   uint32_t k, uint32_t* nrep) {
-  __shared__ uint32_t s_list[kRepairWaves];   // N(v) written by step w (kNone: none)
-  __shared__ uint32_t s_evict[kRepairWaves];  // v' whose indegree step w lowers (kNone: none)
-  __shared__ uint32_t s_stop[kRepairWaves];   // step w cannot commit in this batch
+                                                                   const uint32_t* zero, const uint64_t* zkey,
+                                                                   const uint32_t* zcount, uint32_t k, uint32_t* nrep) {
+  // nrep[0]: vertices repaired, nrep[3]: batches, nrep[4]: steps run alone
+  constexpr int S = RepairShape<NR>::kSteps;
+  constexpr uint32_t B = RepairShape<NR>::kBatch;
+  __shared__ uint32_t h_lid[kRepairHash], h_lstep[kRepairHash];  // lists written
+  __shared__ uint32_t h_eid[kRepairHash], h_estep[kRepairHash];  // indegrees lowered
+  __shared__ uint32_t s_stop[2];  // first step of the batch that cannot commit
   const int w = threadIdx.x / 64;
+  const int lane = lane_id();
+  for (int t = threadIdx.x; t < kRepairHash; t += blockDim.x) {
+    h_lid[t] = kNone;
+    h_lstep[t] = kNone;
+    h_eid[t] = kNone;
+    h_estep[t] = kNone;
+  }
+  if (threadIdx.x < 2) s_stop[threadIdx.x] = kNone;
+  __syncthreads();
   const uint32_t Z = *zcount;
-  uint32_t fixed = 0;
-  for (uint32_t base = 0; base < Z;) {
-    const uint32_t zi = base + w;
-    const bool active = zi < Z;
-    const uint32_t vs = active ? zero[zi] : 0u;
-    Attempt<NR> at{};
-    at.ok = false;
-    uint32_t v = kNone;
-    uint64_t nk = 0;
-    int attempts = 0;
-    if (active) {
-      for (uint32_t s = 0; s < k; ++s) {
-        const uint64_t ks = keys[static_cast<uint64_t>(vs) * k + s];
-        if (ks == kSentinel) break;
-        v = key_id(ks);
-        nk = (ks & 0xFFFFFFFF00000000ull) | vs;
-        ++attempts;
-        at = try_neighbour<NR>(keys, flags, T, v, k);
-        if (at.ok) break;
+  uint32_t fixed = 0, batches = 0, alone = 0;
+  uint32_t parity = 0;
+  // step i = s * kRepairWaves + w of a batch belongs to slot s of wave w;
+  // the zero list and first keys of the next batch load during the commits
+  uint32_t vs[S];
+  uint64_t zk[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    const uint32_t zi = s * kRepairWaves + w;
+    vs[s] = zi < Z ? zero[zi] : kNone;
+    zk[s] = zi < Z ? zkey[zi] : kSentinel;
+  }
+  for (uint32_t base = 0; base < Z; parity ^= 1u) {
+    uint32_t v[S];
+    uint64_t nk[S];
+    bool has[S];
+    Attempt<NR> at[S];
+    uint32_t tv[S][NR];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint64_t ks = zk[s];
+      has[s] = ks != kSentinel;
+      v[s] = has[s] ? key_id(ks) : kNone;
+      nk[s] = (ks & 0xFFFFFFFF00000000ull) | vs[s];
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const uint32_t e = r * 64 + lane;
+        const bool in = has[s] && e < k;
+        at[s].lk[r] = in ? ld_wg64(&keys[static_cast<uint64_t>(v[s]) * k + e]) : kSentinel;
+        at[s].lf[r] = in ? ld_wg32(&flags[static_cast<uint64_t>(v[s]) * k + e]) : 0u;
+      }
+    // indegrees of the farthest kTail entries first: the farthest entry
+    // usually qualifies, and one qualifying entry among them is the answer
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        const uint32_t e = r * 64 + lane;
+        tv[s][r] = at[s].lk[r] != kSentinel && e + kTail >= k ? ld_wg32(&T[key_id(at[s].lk[r])]) : 0u;
+      }
+    uint32_t my_list = kNone, my_evict = kNone, my_step = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      decide_attempt<NR>(at[s], tv[s], k);
+      if (has[s] && !at[s].ok) {
+        // none of the tail qualifies: read every entry's indegree
+#pragma unroll
+        for (int r = 0; r < NR; ++r)
+          tv[s][r] = at[s].lk[r] != kSentinel ? ld_wg32(&T[key_id(at[s].lk[r])]) : 0u;
+        decide_attempt<NR>(at[s], tv[s], k);
+      }
+      if (!has[s]) at[s].ok = false;
+      uint32_t ev = kNone;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (at[s].ok && at[s].drop >= 0 && r == at[s].drop / 64) ev = key_id(readlane64(at[s].lk[r], at[s].drop % 64));
+      if (lane == s) {
+        my_step = s * kRepairWaves + w;
+        my_list = at[s].ok ? v[s] : kNone;
+        my_evict = ev;
       }
     }
-    const bool single = attempts == 0 || (attempts == 1 && at.ok);
-    uint32_t ev = kNone;
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-      if (at.ok && at.drop >= 0 && r == at.drop / 64) ev = key_id(readlane64(at.lk[r], at.drop % 64));
-    if (lane_id() == 0) {
-      s_list[w] = at.ok ? v : kNone;
-      s_evict[w] = ev;
-    }
+    if (my_list != kNone) note_write(h_lid, h_lstep, my_list, my_step);
+    if (my_evict != kNone) note_write(h_eid, h_estep, my_evict, my_step);
     __syncthreads();
-    bool stop = !active;
-    if (active && w > 0) {
-      if (!single) {
-        stop = true;
-      } else if (attempts == 1) {
-        for (int j = 0; j < w; ++j) {
-          if (s_list[j] == v) stop = true;
-          const uint32_t ev = s_evict[j];
-          bool hit = false;
+    if (threadIdx.x == 0) s_stop[parity ^ 1u] = kNone;
+    uint32_t my_stop = kNone;
 #pragma unroll
-          for (int r = 0; r < NR; ++r) hit |= ev != kNone && at.lk[r] != kSentinel && key_id(at.lk[r]) == ev;
-          if (ballot(hit)) stop = true;
+    for (int s = 0; s < S; ++s) {
+      const uint32_t i = s * kRepairWaves + w;
+      bool stop = has[s] && !at[s].ok;
+      if (at[s].ok && first_write(h_lid, h_lstep, v[s]) < i) stop = true;
+      bool hit = false;
+#pragma unroll
+      for (int r = 0; r < NR; ++r)
+        if (at[s].ok && at[s].lk[r] != kSentinel) hit |= first_write(h_eid, h_estep, key_id(at[s].lk[r])) < i;
+      if (ballot(hit)) stop = true;
+      if (stop && i < my_stop) my_stop = i;
+    }
+    if (lane == 0 && my_stop != kNone) atomicMin(&s_stop[parity], my_stop);
+    __syncthreads();
+    const uint32_t nb = Z - base < B ? Z - base : B;
+    uint32_t pend = s_stop[parity] < nb ? s_stop[parity] : nb;
+    const uint32_t next = base + (pend ? pend : 1u);
+    uint32_t nvs[S];
+    uint64_t nzk[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t zi = next + s * kRepairWaves + w;
+      nvs[s] = zi < Z ? zero[zi] : kNone;
+      nzk[s] = zi < Z ? zkey[zi] : kSentinel;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t i = s * kRepairWaves + w;
+      if (i < pend && at[s].ok) {
+        commit_attempt<NR>(keys, flags, T, at[s], v[s], vs[s], nk[s], k);
+        ++fixed;
+      }
+    }
+    ++batches;
+    if (pend == 0) {
+      // the batch's first step found no slot in its closest neighbour's list:
+      // it tries the next neighbours alone (wave 0 owns step 0)
+      ++alone;
+      if (w == 0) {
+        for (uint32_t t = 1; t < k; ++t) {
+          const uint64_t ks = keys[static_cast<uint64_t>(vs[0]) * k + t];
+          if (ks == kSentinel) break;
+          const uint32_t vt = key_id(ks);
+          const Attempt<NR> a1 = try_neighbour<NR>(keys, flags, T, vt, k);
+          if (a1.ok) {
+            commit_attempt<NR>(keys, flags, T, a1, vt, vs[0], (ks & 0xFFFFFFFF00000000ull) | vs[0], k);
+            ++fixed;
+            break;
+          }
         }
       }
+      pend = 1;
     }
-    if (lane_id() == 0) s_stop[w] = stop ? 1u : 0u;
-    __syncthreads();
-    uint32_t pend = kRepairWaves;
-    for (int j = 0; j < kRepairWaves; ++j)
-      if (s_stop[j]) {
-        pend = j;
-        break;
-      }
-    if (static_cast<uint32_t>(w) < pend && at.ok) {
-      commit_attempt<NR>(keys, flags, T, at, v, vs, nk, k);
-      ++fixed;
+    for (int t = threadIdx.x; t < kRepairHash; t += blockDim.x) {
+      h_lid[t] = kNone;
+      h_lstep[t] = kNone;
+      h_eid[t] = kNone;
+      h_estep[t] = kNone;
     }
     __threadfence_block();
     __syncthreads();
-    base += pend;
+    base = next;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      vs[s] = nvs[s];
+      zk[s] = nzk[s];
+    }
   }
   if (lane_id() == 0 && fixed) atomicAdd(nrep, fixed);
+  if (threadIdx.x == 0) {
+    atomicAdd(nrep + 3, batches);
+    atomicAdd(nrep + 4, alone);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1082,6 +1228,7 @@ struct RefineBufs {
   uint32_t* zmask;
   uint32_t* zoff;
   uint32_t* zero;
+  uint64_t* zkey;
   uint32_t* hdr;  // [0] proposals this round, [1] max per round, [2] repaired, [3] sum
   uint32_t* scan_tmp;
   uint64_t* sub_off;
@@ -1118,6 +1265,26 @@ struct RoundPlan {
 };
 
 // one refinement round; only kernel launches (graph-capturable)
+// indegrees T of the lists in b.keys, then Algorithm 4 (count of repaired
+// vertices added to b.hdr[2])
+hipError_t launch_repair(const RefineBufs& b, uint64_t N, uint32_t k, hipStream_t s) {
+  const uint64_t nk = N * k;
+  hipError_t e;
+  if ((e = fill_u32(b.T, 0u, N, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, b.T);
+  hipLaunchKernelGGL(zero_mask_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, N, b.zmask);
+  if ((e = exclusive_scan(b.zmask, b.zoff, N, b.scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(zero_compact_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.zmask, b.zoff, N, b.keys, k, b.zero,
+                     b.zkey);
+  if (k <= 64)
+    hipLaunchKernelGGL(repair_kernel<1>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.zero, b.zkey,
+                       b.zoff + N, k, b.hdr + 2);
+  else
+    hipLaunchKernelGGL(repair_kernel<2>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.zero, b.zkey,
+                       b.zoff + N, k, b.hdr + 2);
+  return hipGetLastError();
+}
+
 hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   const uint64_t N = rp.N, nk = N * rp.k;
   hipError_t e;
@@ -1153,19 +1320,7 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
                        b.psorted, b.hdr + 1, b.hdr);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!rp.repair) return hipSuccess;
-  // indegree repair
-  if ((e = fill_u32(b.T, 0u, N, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, b.T);
-  hipLaunchKernelGGL(zero_mask_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, N, b.zmask);
-  if ((e = exclusive_scan(b.zmask, b.zoff, N, b.scan_tmp, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(zero_compact_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.zmask, b.zoff, N, b.zero);
-  if (rp.nr == 1)
-    hipLaunchKernelGGL(repair_kernel<1>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.zero, b.zoff + N, rp.k,
-                       b.hdr + 2);
-  else
-    hipLaunchKernelGGL(repair_kernel<2>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.zero, b.zoff + N, rp.k,
-                       b.hdr + 2);
-  return hipGetLastError();
+  return launch_repair(b, N, rp.k, s);
 }
 
 uint32_t ceil_pow2_u(uint32_t x) {
@@ -1227,6 +1382,8 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     FGIM_TRY(scr.get(&b.zmask, N + 1));
     FGIM_TRY(scr.get(&b.zoff, N + 1));
     FGIM_TRY(scr.get(&b.zero, N + 1));
+  FGIM_TRY(scr.get(&b.zkey, N + 1));
+    FGIM_TRY(scr.get(&b.zkey, N + 1));
     FGIM_TRY(scr.get(&b.hdr, 8));
     float *nrm2 = nullptr, *qerr2 = nullptr;
     if (use_mfma) {
@@ -1357,6 +1514,8 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
       stats->repaired = hh[2];
       stats->proposals = hh[3];
       stats->rechecked = hh[4];
+      stats->repair_batches = hh[5];
+      stats->repair_alone = hh[6];
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
     }
@@ -1365,7 +1524,59 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   return fail(FGIM_ERR_OUT_OF_MEMORY, "join proposals keep overflowing the buffer");
 }
 
+__global__ void check_ids_kernel(const uint32_t* ids, uint64_t nk, uint64_t N, uint32_t* err) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    if (ids[i] != kNone && ids[i] >= N) atomicOr(err, 1u);
+}
+
+fgim_status repair_impl(uint32_t* ids, float* dist, uint64_t N, uint32_t k, uint32_t* T_out, uint64_t* repaired,
+                        hipStream_t s) {
+  if (!ids || !dist) return fail(FGIM_ERR_INVALID_ARG, "NULL buffer");
+  if (N == 0 || N >= 0xFFFFFFFFull) return fail(FGIM_ERR_INVALID_ARG, "n = %llu out of range", (unsigned long long)N);
+  if (k == 0 || k > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "k = %u out of 1..%u", k, FGIM_MAX_K);
+  const uint64_t nk = N * k;
+  Scratch scr(s);
+  RefineBufs b{};
+  FGIM_TRY(scr.get(&b.keys, nk));
+  FGIM_TRY(scr.get(&b.flags, nk));
+  FGIM_TRY(scr.get(&b.T, N));
+  FGIM_TRY(scr.get(&b.zmask, N + 1));
+  FGIM_TRY(scr.get(&b.zoff, N + 1));
+  FGIM_TRY(scr.get(&b.zero, N + 1));
+  FGIM_TRY(scr.get(&b.zkey, N + 1));
+  FGIM_TRY(scr.get(&b.scan_tmp, scan_tmp_words(N + 1) + 16));
+  FGIM_TRY(scr.get(&b.hdr, 8));
+  HIP_TRY(fill_u32(b.hdr, 0u, 8, s));
+  // an id >= n would index T out of bounds: reject the lists first
+  hipLaunchKernelGGL(check_ids_kernel, dim3(grid_for(nk)), dim3(256), 0, s, ids, nk, N, b.hdr + 1);
+  HIP_TRY(hipGetLastError());
+  uint32_t herr = 0;
+  HIP_TRY(hipMemcpyAsync(&herr, b.hdr + 1, 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipStreamSynchronize(s));
+  if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n");
+  hipLaunchKernelGGL(to_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, ids, dist, nk, b.keys, b.flags);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_repair(b, N, k, s));
+  hipLaunchKernelGGL(from_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, ids, dist);
+  HIP_TRY(hipGetLastError());
+  if (T_out) HIP_TRY(hipMemcpyAsync(T_out, b.T, 4 * N, hipMemcpyDeviceToDevice, s));
+  if (repaired) {
+    uint32_t hh[4] = {0, 0, 0, 0};
+    HIP_TRY(hipMemcpyAsync(hh, b.hdr, sizeof(hh), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    *repaired = hh[2];
+  }
+  return FGIM_OK;
+}
+
 }  // namespace fgim
+
+extern "C" fgim_status fgim_repair(uint32_t* knn_ids, float* knn_dist, uint64_t n, uint32_t k, uint32_t* indegree,
+                                   uint64_t* repaired, void* stream) {
+  fgim::fail(FGIM_OK, "");
+  return fgim::repair_impl(knn_ids, knn_dist, n, k, indegree, repaired, static_cast<hipStream_t>(stream));
+}
 
 extern "C" fgim_status fgim_refine(const fgim_dataset* data, const fgim_params* params, uint32_t* knn_ids,
                                    float* knn_dist, uint32_t* indegree, fgim_stats* stats, void* stream) {

@@ -74,3 +74,15 @@ def test_null_outputs_rejected():
     p = fg.params(k=8, L=16)
     assert fg.lib().fgim_cross_query(ctypes.byref(d), ctypes.byref(p), None, 0x50000, None, None) == 1
     assert fg.lib().fgim_cross_query(None, ctypes.byref(p), 0x40000, 0x50000, None, None) == 1
+
+
+@pytest.mark.parametrize("ids,dist,n,k", [
+    (None, 0x50000, 100, 8),
+    (0x40000, None, 100, 8),
+    (0x40000, 0x50000, 0, 8),
+    (0x40000, 0x50000, 100, 0),
+    (0x40000, 0x50000, 100, 200),
+])
+def test_repair_bad_arguments_rejected_on_host(ids, dist, n, k):
+    assert fg.lib().fgim_repair(ids, dist, n, k, None, None, None) == 1
+    assert fg.lib().fgim_last_error()
