@@ -83,7 +83,7 @@ typedef struct {
  * ascending row_offset order and tile [0, n_total) without gaps. */
 typedef struct {
     const float* base;          /* device, n_total rows of ld floats; 16-byte aligned */
-    uint64_t n_total;           /* sum of n_i, < 2^32 - 1 */
+    uint64_t n_total;           /* sum of n_i, < 0xFFF00000 */
     uint32_t dim;               /* d: multiple of 4, 4..FGIM_MAX_DIM */
     uint64_t ld;                /* row stride in floats: multiple of 4, >= dim */
     fgim_metric metric;

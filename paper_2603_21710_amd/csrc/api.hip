@@ -188,7 +188,9 @@ uint32_t ilog2(uint32_t x) {
 
 fgim_status check_rows(const float* base, uint64_t n, uint32_t dim, uint64_t ld) {
   if (!base) return fail(FGIM_ERR_INVALID_ARG, "base is NULL");
-  if (n == 0 || n >= 0xFFFFFFFFull) return fail(FGIM_ERR_INVALID_ARG, "row count %llu out of range", (unsigned long long)n);
+  // ids are 32-bit with 0xFFFFFFFF reserved, and the work queue's 32-bit
+  // counter may run up to 2^20 past the item count
+  if (n == 0 || n >= 0xFFF00000ull) return fail(FGIM_ERR_INVALID_ARG, "row count %llu out of range", (unsigned long long)n);
   if (dim < 4 || dim > FGIM_MAX_DIM || dim % 4)
     return fail(dim % 4 ? FGIM_ERR_UNSUPPORTED : FGIM_ERR_INVALID_ARG, "dim %u must be a multiple of 4 in 4..%u", dim, FGIM_MAX_DIM);
   if (ld < dim || ld % 4) return fail(FGIM_ERR_INVALID_ARG, "ld %llu must be a multiple of 4 and >= dim", (unsigned long long)ld);
@@ -482,7 +484,7 @@ fgim_status fgim_search(const float* base, uint64_t n, uint32_t dim, uint64_t ld
   if (nq == 0) return FGIM_OK;
   if (!queries || ldq < dim || ldq % 4 || reinterpret_cast<uintptr_t>(queries) % 16)
     return fail(FGIM_ERR_INVALID_ARG, "bad query matrix");
-  if (nq >= 0xFFFFFFFFull) return fail(FGIM_ERR_INVALID_ARG, "too many queries");
+  if (nq >= 0xFFF00000ull) return fail(FGIM_ERR_INVALID_ARG, "too many queries");
   if (L == 0 || L > FGIM_MAX_L || topk == 0 || topk > L) return fail(FGIM_ERR_INVALID_ARG, "need 1 <= topk <= L <= %u", FGIM_MAX_L);
   if (!out_ids || !out_dist) return fail(FGIM_ERR_INVALID_ARG, "output is NULL");
   BeamShape shape;

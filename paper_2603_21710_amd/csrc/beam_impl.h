@@ -280,6 +280,8 @@ FGIM_DEV void load_query(float4 (&q)[MMAX], const float* row, const BeamArgs& a)
   }
 }
 
+constexpr uint32_t kItemsPerPop = 1;
+
 template <bool L2, int FMT, int NR, int MMAX>
 __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -295,10 +297,18 @@ __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
   Pool<NR> topk;
   float4 q[MMAX];
 
+  // items are popped kItemsPerPop at a time (more than one per pop measured
+  // slower on 2 x 500k rows: the tail imbalance outweighs the atomics saved)
+  uint32_t next = 0, left = 0;
   for (;;) {
-    uint32_t item = 0;
-    if (lane_id() == 0) item = atomicAdd(a.counter, 1u);
-    item = uniform(shfl_u(item, 0));
+    if (left == 0) {
+      uint32_t b = 0;
+      if (lane_id() == 0) b = atomicAdd(a.counter, kItemsPerPop);
+      next = uniform(shfl_u(b, 0));
+      left = kItemsPerPop;
+    }
+    const uint32_t item = next++;
+    --left;
     if (item >= a.n_items) break;
 
     if (a.search_mode) {

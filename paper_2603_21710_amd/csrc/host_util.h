@@ -20,6 +20,9 @@ fgim_status check_dataset(const fgim_dataset* d, bool need_cross);
 // a non-blocking, default-priority stream owned by the library (one per
 // device), used where work has to be captured into a hipGraph
 hipError_t library_stream(hipStream_t* out);
+// BF16 (round to nearest even) or FP8 E4M3 (per-row scale) copy of n rows
+fgim_status quantize_into(const float* base, uint64_t n, uint32_t dim, uint64_t ld, fgim_precision prec,
+                          void* codes, float* scales, hipStream_t s);
 
 // Stream-ordered scratch, released (stream-ordered) at scope exit.
 struct Scratch {

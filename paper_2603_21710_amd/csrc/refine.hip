@@ -193,12 +193,26 @@ struct JoinArgs {
   // MFMA join
   const float* nrm2;         // squared FP32 norm of every base row
   const float* qerr2;        // squared norm of each row's BF16 rounding residual
-  int stage_f32;             // FP32 candidate rows fit in LDS (re-scoring reads LDS)
   const uint16_t* xb;        // BF16 copy (dense rows of dim) or null: convert X
   uint32_t dim;
   uint32_t dpad;             // dim rounded up to 32 (MFMA K)
   uint32_t slice;            // dimensions staged in LDS at a time (multiple of 32)
   uint32_t* rechecked;       // pairs re-scored in FP32 after the screen
+  // candidate sets of the MFMA join, built by cand_kernel
+  uint32_t* cand;            // N x kMfmaMaxC: Cn then Co, each ascending
+  uint32_t* ccnt;            // 2N: |Cn|, |Co|
+  struct CandAux* aux;       // N: per-vertex screen data
+  uint64_t* pairs;           // pairs passing the screen: (Cn id) | (partner id) << 32
+  uint32_t* npairs;          // pairs emitted this round (may exceed pair_cap)
+  uint32_t* npairs_max;      // largest npairs over the rounds
+  uint32_t pair_cap;
+};
+
+// per-vertex data the MFMA screen reads for every candidate
+struct CandAux {
+  uint64_t worst;  // key of the list's last entry (kSentinel while the list has a free slot)
+  float nrm2;      // squared FP32 norm of the row
+  float qerr;      // norm of the row's BF16 rounding residual, inflated by its own rounding bound
 };
 
 // top-k_rev of a reverse segment by key, appended to list (ids) via counter
@@ -499,6 +513,8 @@ FGIM_DEV void emit_proposal(const JoinArgs& a, bool emit, uint32_t tgt, uint64_t
 constexpr uint32_t kMfmaMaxC = 128;       // candidates per vertex on the MFMA path
 constexpr uint32_t kMfmaMaxCn = 64;       // |Cn| bound on the MFMA path (k + k_rev <= 64)
 constexpr uint32_t kMfmaTilesPerWave = 7; // ceil(26 tile pairs / 4 waves) for |Cn| <= 64, c <= 128
+constexpr uint32_t kPairChunk = 1024;     // pair-buffer slots a join workgroup claims at a time
+constexpr uint64_t kNoPair = ~0ull;       // an unused pair-buffer slot
 
 // position of the r-th set bit (r < popcount) of the 128-bit mask (m0, m1)
 FGIM_DEV uint32_t select_bit(uint64_t m0, uint64_t m1, uint32_t r) {
@@ -523,55 +539,42 @@ FGIM_DEV uint32_t select_bit(uint64_t m0, uint64_t m1, uint32_t r) {
   return pos;
 }
 
-template <int MMAX>
-__global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  uint32_t* arr_n = reinterpret_cast<uint32_t*>(smem);          // 128
-  uint32_t* arr_o = arr_n + kMfmaMaxC;                          // 128
-  uint32_t* cid = arr_o + kMfmaMaxC;                            // 128: Cn then Co, ascending id
-  uint32_t* cg = cid + kMfmaMaxC;                               // sub-index
-  float* cnrm = reinterpret_cast<float*>(cg + kMfmaMaxC);       // squared norms
-  float* cqe = cnrm + kMfmaMaxC;                                // BF16 residual norms
-  uint64_t* cw = reinterpret_cast<uint64_t*>(cqe + kMfmaMaxC);  // worst key of the list
-  uint64_t* pmask = cw + kMfmaMaxC;                             // 64 x 2 words: passing partners of Cn row i
-  uint32_t* rowoff = reinterpret_cast<uint32_t*>(pmask + 2 * kMfmaMaxCn);  // 65 prefix counts
-  uint32_t* counters = rowoff + 68;                             // 8
-  uint64_t* skey = reinterpret_cast<uint64_t*>(counters + 8);   // kPropStage staged proposals
-  uint32_t* stgt = reinterpret_cast<uint32_t*>(skey + kPropStage);
-  float* frows = reinterpret_cast<float*>(stgt + kPropStage);   // FP32 rows, 128 x (dim + 4), or
-  uint16_t* brows = reinterpret_cast<uint16_t*>(frows);         // BF16 slices, 128 x (slice + 8)
-  const uint32_t fstride = a.dim + 4;
-  const uint32_t srow = a.slice + 8;
+// Visit for the MFMA join, one vertex u per two-wave workgroup: Cn(u) =
+// the new forward entries and the k_rev closest new reverse entries, Co(u)
+// = the old ones not in Cn, each unique and ascending (ascending ids group
+// by sub-index); written to a.cand / a.ccnt with u's own screen data.
+__global__ void __launch_bounds__(128) cand_kernel(JoinArgs a) {
+  __shared__ uint32_t arr_n[kMfmaMaxC], arr_o[kMfmaMaxC], cid[kMfmaMaxC];
+  __shared__ uint32_t counters[4];
   const int wave = threadIdx.x / 64;
   const int lane = lane_id();
-  const int P = static_cast<int>(a.P), M = static_cast<int>(a.M);
-  const int l = threadIdx.x % P, gid = threadIdx.x / P, ngroups = 256 / P;
   const float u32 = 5.9604645e-8f;  // 2^-24
   const float gam = (a.dim + 4) * u32 / (1.0f - (a.dim + 4) * u32);
-
   for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
-    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
-    if (threadIdx.x < kMfmaMaxC) {
-      arr_n[threadIdx.x] = kNone;
-      arr_o[threadIdx.x] = kNone;
-      pmask[threadIdx.x] = 0;
+    if (threadIdx.x < 4) counters[threadIdx.x] = 0;
+    arr_n[threadIdx.x] = kNone;
+    arr_o[threadIdx.x] = kNone;
+    if (threadIdx.x == 0) {
+      CandAux x;
+      x.worst = a.keys[u * a.k + a.k - 1];
+      x.nrm2 = a.nrm2[u];
+      x.qerr = sqrtf(a.qerr2[u]) * (1.0f + gam) * 1.0001f;
+      a.aux[u] = x;
     }
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < a.k; t += 256) {
+    for (uint32_t t = threadIdx.x; t < a.k; t += 128) {
       const uint64_t kk = a.keys[u * a.k + t];
       if (kk == kSentinel) continue;
       if (a.flags[u * a.k + t] & kFlagNew) arr_n[atomicAdd(&counters[0], 1u)] = key_id(kk);
       else arr_o[atomicAdd(&counters[1], 1u)] = key_id(kk);
     }
-    if (wave < 2) {
-      const uint32_t seg = 2u * static_cast<uint32_t>(u) + wave;
+    {
+      const uint64_t seg = 2u * u + static_cast<uint64_t>(wave);
       const uint32_t b0 = a.rev_off[seg], b1 = a.rev_off[seg + 1];
       rev_top<1>(a.rev + b0, b1 - b0, a.k_rev, wave == 0 ? arr_n : arr_o, &counters[wave]);
     }
     __syncthreads();
-    // Cn = unique(arr_n) and the unique ids of arr_o, both ascending (ids
-    // ascending are grouped by sub-index: sub-index ranges are contiguous)
-    if (wave < 2) {
+    {
       uint32_t* src = wave == 0 ? arr_n : arr_o;
       uint32_t v0 = src[lane], v1 = src[64 + lane];
       wave_sort128(v0, v1);
@@ -605,28 +608,80 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
       if (lane == 0) counters[3] = n0 + static_cast<uint32_t>(popc64(m1));
     }
     __syncthreads();
-    const uint32_t no = counters[3];
+    const uint32_t c = nn + counters[3];
+    for (uint32_t i = threadIdx.x; i < c; i += 128) a.cand[u * kMfmaMaxC + i] = cid[i];
+    if (threadIdx.x == 0) {
+      a.ccnt[2 * u] = nn;
+      a.ccnt[2 * u + 1] = counters[3];
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  uint64_t* cw = reinterpret_cast<uint64_t*>(smem);              // worst key of each candidate's list
+  uint64_t* pmask = cw + kMfmaMaxC;                               // 64 x 2 words: passing partners of Cn row i
+  uint32_t* cid = reinterpret_cast<uint32_t*>(pmask + 2 * kMfmaMaxCn); // 128: Cn then Co, ascending id
+  uint32_t* cg = cid + kMfmaMaxC;                                 // sub-index
+  float* cnrm = reinterpret_cast<float*>(cg + kMfmaMaxC);         // squared norms
+  float* cqe = cnrm + kMfmaMaxC;                                  // BF16 residual norms
+  uint32_t* rowoff = reinterpret_cast<uint32_t*>(cqe + kMfmaMaxC); // 65 prefix counts
+  uint32_t* counters = rowoff + 68;  // 16: [0..7] per vertex; [8..10] pair chunk base, used, size
+  uint16_t* brows = reinterpret_cast<uint16_t*>(counters + 16);   // BF16 slices, 128 x (slice + 8)
+  const uint32_t srow = a.slice + 8;
+  const int wave = threadIdx.x / 64;
+  const int lane = lane_id();
+  const float u32 = 5.9604645e-8f;  // 2^-24
+  const float gam = (a.dim + 4) * u32 / (1.0f - (a.dim + 4) * u32);
+  uint32_t nrech = 0;  // pairs passing the screen (thread 0)
+  if (threadIdx.x >= 8 && threadIdx.x < 16) counters[threadIdx.x] = 0;
+
+  for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
+    if (threadIdx.x < 8) counters[threadIdx.x] = 0;
+    if (threadIdx.x < kMfmaMaxC) pmask[threadIdx.x] = 0;
+    const uint32_t nn = a.ccnt[2 * u], no = a.ccnt[2 * u + 1];
     const uint32_t c = nn + no;
     for (uint32_t i = threadIdx.x; i < c; i += 256) {
-      const uint32_t v = cid[i];
+      const uint32_t v = a.cand[u * kMfmaMaxC + i];
+      const CandAux x = a.aux[v];
+      cid[i] = v;
       cg[i] = sub_of(a.sub_off, a.h, v);
-      cw[i] = a.keys[static_cast<uint64_t>(v) * a.k + a.k - 1];
-      cnrm[i] = a.nrm2[v];
-      cqe[i] = sqrtf(a.qerr2[v]) * (1.0f + gam) * 1.0001f;
+      cw[i] = x.worst;
+      cnrm[i] = x.nrm2;
+      cqe[i] = x.qerr;
     }
+    __syncthreads();
     const uint32_t nI = (nn + 15) / 16, nC = (c + 15) / 16;
     uint32_t T = 0;
     for (uint32_t I = 0; I < nI; ++I) T += nC - I;
     floatx4_t acc[kMfmaTilesPerWave];
 #pragma unroll
     for (uint32_t t = 0; t < kMfmaTilesPerWave; ++t) acc[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    if (a.stage_f32) {
-      // FP32 rows in LDS; MFMA operands converted to BF16 on the fly
-      for (uint32_t idx = threadIdx.x; idx < nC * 16 * a.nc; idx += 256) {
-        const uint32_t e = idx / a.nc, ch = idx - e * a.nc;
-        *reinterpret_cast<float4*>(frows + e * fstride + 4 * ch) =
-            e < c ? *reinterpret_cast<const float4*>(a.X + static_cast<uint64_t>(cid[e]) * a.ld + 4 * ch)
-                  : make_float4(0.f, 0.f, 0.f, 0.f);
+    // BF16 slices of the dimensions through LDS
+    for (uint32_t s0 = 0; s0 < a.dpad; s0 += a.slice) {
+      const uint32_t sw = min(a.slice, a.dpad - s0);   // multiple of 32
+      __syncthreads();
+      const uint32_t per_row = sw / 8;
+      for (uint32_t idx = threadIdx.x; idx < nC * 16 * per_row; idx += 256) {
+        const uint32_t e = idx / per_row, q = idx - e * per_row;
+        const uint32_t t0 = s0 + 8 * q;
+        shortx8_t v8;
+        if (e < c && t0 < a.dim) {
+          const uint64_t v = cid[e];
+          if (a.xb) {
+            v8 = *reinterpret_cast<const shortx8_t*>(a.xb + v * a.dim + t0);
+          } else {
+            const float4 f0 = *reinterpret_cast<const float4*>(a.X + v * a.ld + t0);
+            const float4 f1 = t0 + 4 < a.dim ? *reinterpret_cast<const float4*>(a.X + v * a.ld + t0 + 4)
+                                             : make_float4(0.f, 0.f, 0.f, 0.f);
+            v8[0] = bf16_rne(f0.x); v8[1] = bf16_rne(f0.y); v8[2] = bf16_rne(f0.z); v8[3] = bf16_rne(f0.w);
+            v8[4] = bf16_rne(f1.x); v8[5] = bf16_rne(f1.y); v8[6] = bf16_rne(f1.z); v8[7] = bf16_rne(f1.w);
+          }
+        } else {
+          v8 = shortx8_t{0, 0, 0, 0, 0, 0, 0, 0};
+        }
+        *reinterpret_cast<shortx8_t*>(brows + e * srow + 8 * q) = v8;
       }
       __syncthreads();
 #pragma unroll
@@ -639,63 +694,11 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
           ++I;
         }
         const uint32_t J = I + tp;
-        const float* ra = frows + (16 * I + lane % 16) * fstride + 8 * (lane / 16);
-        const float* rb = frows + (16 * J + lane % 16) * fstride + 8 * (lane / 16);
-        for (uint32_t kb = 0; kb < a.dpad; kb += 32) {
-          shortx8_t va, vb;
-#pragma unroll
-          for (int e = 0; e < 8; ++e) {
-            const bool in = kb + 8 * (lane / 16) + e < a.dim;
-            va[e] = in ? bf16_rne(ra[kb + e]) : 0;
-            vb[e] = in ? bf16_rne(rb[kb + e]) : 0;
-          }
-          acc[sl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, va),
-                                                            __builtin_bit_cast(bf16x8_t, vb), acc[sl], 0, 0, 0);
-        }
-      }
-    } else {
-      // BF16 slices of the dimensions through LDS
-      for (uint32_t s0 = 0; s0 < a.dpad; s0 += a.slice) {
-        const uint32_t sw = min(a.slice, a.dpad - s0);   // multiple of 32
-        __syncthreads();
-        const uint32_t per_row = sw / 8;
-        for (uint32_t idx = threadIdx.x; idx < nC * 16 * per_row; idx += 256) {
-          const uint32_t e = idx / per_row, q = idx - e * per_row;
-          const uint32_t t0 = s0 + 8 * q;
-          shortx8_t v8;
-          if (e < c && t0 < a.dim) {
-            const uint64_t v = cid[e];
-            if (a.xb) {
-              v8 = *reinterpret_cast<const shortx8_t*>(a.xb + v * a.dim + t0);
-            } else {
-              const float4 f0 = *reinterpret_cast<const float4*>(a.X + v * a.ld + t0);
-              const float4 f1 = t0 + 4 < a.dim ? *reinterpret_cast<const float4*>(a.X + v * a.ld + t0 + 4)
-                                               : make_float4(0.f, 0.f, 0.f, 0.f);
-              v8[0] = bf16_rne(f0.x); v8[1] = bf16_rne(f0.y); v8[2] = bf16_rne(f0.z); v8[3] = bf16_rne(f0.w);
-              v8[4] = bf16_rne(f1.x); v8[5] = bf16_rne(f1.y); v8[6] = bf16_rne(f1.z); v8[7] = bf16_rne(f1.w);
-            }
-          } else {
-            v8 = shortx8_t{0, 0, 0, 0, 0, 0, 0, 0};
-          }
-          *reinterpret_cast<shortx8_t*>(brows + e * srow + 8 * q) = v8;
-        }
-        __syncthreads();
-#pragma unroll
-        for (uint32_t sl = 0; sl < kMfmaTilesPerWave; ++sl) {
-          uint32_t tp = static_cast<uint32_t>(wave) + 4u * sl;
-          if (tp >= T) break;
-          uint32_t I = 0;
-          while (tp >= nC - I) {
-            tp -= nC - I;
-            ++I;
-          }
-          const uint32_t J = I + tp;
-          for (uint32_t kb = 0; kb < sw; kb += 32) {
-            const shortx8_t ra = *reinterpret_cast<const shortx8_t*>(brows + (16 * I + lane % 16) * srow + kb + 8 * (lane / 16));
-            const shortx8_t rb = *reinterpret_cast<const shortx8_t*>(brows + (16 * J + lane % 16) * srow + kb + 8 * (lane / 16));
-            acc[sl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ra),
-                                                              __builtin_bit_cast(bf16x8_t, rb), acc[sl], 0, 0, 0);
-          }
+        for (uint32_t kb = 0; kb < sw; kb += 32) {
+          const shortx8_t ra = *reinterpret_cast<const shortx8_t*>(brows + (16 * I + lane % 16) * srow + kb + 8 * (lane / 16));
+          const shortx8_t rb = *reinterpret_cast<const shortx8_t*>(brows + (16 * J + lane % 16) * srow + kb + 8 * (lane / 16));
+          acc[sl] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ra),
+                                                            __builtin_bit_cast(bf16x8_t, rb), acc[sl], 0, 0, 0);
         }
       }
     }
@@ -762,47 +765,109 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
     }
     __syncthreads();
     const uint32_t np = rowoff[nn];
-    if (threadIdx.x == 0 && np) atomicAdd(a.rechecked, np);
-    // exact re-scoring of the passing pairs, enumerated flat over all rows;
-    // proposals are staged in LDS and flushed once per vertex
-    for (uint32_t b = 0; b < np; b += ngroups) {
-      const uint32_t idx = b + gid;
-      const bool act = idx < np;
-      uint32_t i = 0, j = 0;
-      if (act) {
-        uint32_t lo = 0, hi = nn;  // the row holding idx: last row with rowoff <= idx
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) / 2;
-          if (rowoff[mid] <= idx) lo = mid;
-          else hi = mid;
-        }
-        i = lo;
-        j = select_bit(pmask[2 * i], pmask[2 * i + 1], idx - rowoff[i]);
-      }
-      const uint32_t vi = cid[i], vj = cid[j];
-      const float* ri = a.stage_f32 ? frows + i * fstride : a.X + static_cast<uint64_t>(vi) * a.ld;
-      const float* rj = a.stage_f32 ? frows + j * fstride : a.X + static_cast<uint64_t>(vj) * a.ld;
-      const float dd = pair_distance<MMAX>(ri, rj, a.metric, a.nc, P, M, l, act);
-      if (act && l == 0) {
-        const uint64_t to_i = make_key(dd, vj), to_j = make_key(dd, vi);
-        if (to_i < cw[i]) stage_proposal(a, vi, to_i, &counters[4], stgt, skey);
-        if (to_j < cw[j]) stage_proposal(a, vj, to_j, &counters[4], stgt, skey);
+    // the passing pairs go to the pair buffer, enumerated flat over all rows,
+    // into chunks of it this workgroup claims (one global atomic per chunk,
+    // not per vertex); recheck_kernel scores them exactly
+    if (threadIdx.x == 0) {
+      nrech += np;
+      const uint32_t used = counters[9], size = counters[10];
+      const uint32_t rem = size - used;
+      counters[4] = counters[8] + used;  // first part: the current chunk's tail
+      counters[5] = min(np, rem);
+      if (np > rem) {  // second part: a new chunk
+        const uint32_t need = np - rem;
+        const uint32_t sz = max(kPairChunk, need);
+        counters[8] = atomicAdd(a.npairs, sz);
+        counters[9] = need;
+        counters[10] = sz;
+        counters[6] = counters[8];
+      } else {
+        counters[9] = used + np;
       }
     }
     __syncthreads();
-    const uint32_t ns = min(counters[4], kPropStage);
-    if (threadIdx.x == 0 && ns) counters[5] = atomicAdd(a.ptotal, ns);
+    const uint32_t p0 = counters[4], n0 = counters[5], p1 = counters[6];
+    for (uint32_t idx = threadIdx.x; idx < np; idx += 256) {
+      uint32_t lo = 0, hi = nn;  // the row holding idx: last row with rowoff <= idx
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (rowoff[mid] <= idx) lo = mid;
+        else hi = mid;
+      }
+      const uint32_t jj = select_bit(pmask[2 * lo], pmask[2 * lo + 1], idx - rowoff[lo]);
+      const uint64_t pos = idx < n0 ? static_cast<uint64_t>(p0) + idx : static_cast<uint64_t>(p1) + (idx - n0);
+      if (pos < a.pair_cap) a.pairs[pos] = (static_cast<uint64_t>(cid[jj]) << 32) | cid[lo];
+    }
     __syncthreads();
-    const uint32_t base = counters[5];
+  }
+  // the unused tail of the last chunk holds no pair
+  const uint64_t t0 = static_cast<uint64_t>(counters[8]) + counters[9];
+  const uint64_t t1 = static_cast<uint64_t>(counters[8]) + counters[10];
+  for (uint64_t t = t0 + threadIdx.x; t < t1; t += 256)
+    if (t < a.pair_cap) a.pairs[t] = kNoPair;
+  if (threadIdx.x == 0 && nrech) atomicAdd(a.rechecked, nrech);
+}
+
+// Exact re-scoring of the pairs that passed the MFMA screen: one pair per
+// group of P lanes, the canonical FP32 distance from the base rows, and a
+// proposal to each end whose list's worst entry it beats.
+constexpr uint32_t kRecheckStage = 2048;  // proposals staged in LDS per flush
+
+template <int MMAX>
+__global__ void __launch_bounds__(256) recheck_kernel(JoinArgs a) {
+  __shared__ uint64_t skey[kRecheckStage];
+  __shared__ uint32_t stgt[kRecheckStage];
+  __shared__ uint32_t scount, sbase;
+  const int P = static_cast<int>(a.P), M = static_cast<int>(a.M);
+  const int l = threadIdx.x % P;
+  const uint32_t per_block = 256 / P;
+  const uint64_t n = min(*a.npairs, a.pair_cap);
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(a.npairs_max, *a.npairs);
+  if (threadIdx.x == 0) scount = 0;
+  __syncthreads();
+  // proposals are staged in LDS and flushed with one global atomic per
+  // flush (a single shared counter would serialise on contention)
+  auto flush = [&]() {
+    const uint32_t ns = scount;
+    if (threadIdx.x == 0 && ns) sbase = atomicAdd(a.ptotal, ns);
+    __syncthreads();
     for (uint32_t t = threadIdx.x; t < ns; t += 256) {
-      const uint32_t pos = base + t;
+      const uint32_t pos = sbase + t;
       if (pos < a.cap) {
         a.ptgt[pos] = stgt[t];
         a.pkey[pos] = skey[t];
       }
     }
     __syncthreads();
+    if (threadIdx.x == 0) scount = 0;
+    __syncthreads();
+  };
+  for (uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * per_block; b0 < n;
+       b0 += static_cast<uint64_t>(gridDim.x) * per_block) {
+    const uint64_t idx = b0 + threadIdx.x / P;
+    uint64_t pr = idx < n ? a.pairs[idx] : kNoPair;
+    const bool act = pr != kNoPair;
+    if (!act) pr = 0;
+    const uint32_t vi = static_cast<uint32_t>(pr), vj = static_cast<uint32_t>(pr >> 32);
+    const float dd = pair_distance<MMAX>(a.X + static_cast<uint64_t>(vi) * a.ld, a.X + static_cast<uint64_t>(vj) * a.ld,
+                                         a.metric, a.nc, P, M, l, act);
+    if (act && l == 0) {
+      const uint64_t ki = make_key(dd, vj), kj = make_key(dd, vi);
+      if (ki < a.aux[vi].worst) {
+        const uint32_t pos = atomicAdd(&scount, 1u);
+        stgt[pos] = vi;
+        skey[pos] = ki;
+      }
+      if (kj < a.aux[vj].worst) {
+        const uint32_t pos = atomicAdd(&scount, 1u);
+        stgt[pos] = vj;
+        skey[pos] = kj;
+      }
+    }
+    __syncthreads();
+    if (scount + 2 * per_block > kRecheckStage) flush();
   }
+  flush();
 }
 
 // ---------------------------------------------------------------------------
@@ -1259,12 +1324,11 @@ struct RoundPlan {
   bool repair;
   JoinArgs ja;
   int nr, mmax;
-  uint32_t join_grid;
+  uint32_t join_grid, cand_grid, recheck_grid;
   size_t join_smem;
   bool use_mfma;
 };
 
-// one refinement round; only kernel launches (graph-capturable)
 // indegrees T of the lists in b.keys, then Algorithm 4 (count of repaired
 // vertices added to b.hdr[2])
 hipError_t launch_repair(const RefineBufs& b, uint64_t N, uint32_t k, hipStream_t s) {
@@ -1285,6 +1349,7 @@ hipError_t launch_repair(const RefineBufs& b, uint64_t N, uint32_t k, hipStream_
   return hipGetLastError();
 }
 
+// one refinement round; only kernel launches (graph-capturable)
 hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   const uint64_t N = rp.N, nk = N * rp.k;
   hipError_t e;
@@ -1298,10 +1363,13 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   // Update
   if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
   if (rp.use_mfma) {
+    if ((e = fill_u32(rp.ja.npairs, 0u, 1, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(cand_kernel, dim3(rp.cand_grid), dim3(128), 0, s, rp.ja);
+    hipLaunchKernelGGL(join_mfma_kernel, dim3(rp.join_grid), dim3(256), rp.join_smem, s, rp.ja);
     if (rp.mmax == 4)
-      hipLaunchKernelGGL(join_mfma_kernel<4>, dim3(rp.join_grid), dim3(256), rp.join_smem, s, rp.ja);
+      hipLaunchKernelGGL(recheck_kernel<4>, dim3(rp.recheck_grid), dim3(256), 0, s, rp.ja);
     else
-      hipLaunchKernelGGL(join_mfma_kernel<16>, dim3(rp.join_grid), dim3(256), rp.join_smem, s, rp.ja);
+      hipLaunchKernelGGL(recheck_kernel<16>, dim3(rp.recheck_grid), dim3(256), 0, s, rp.ja);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   } else if ((e = launch_join(rp.ja, rp.nr, rp.mmax, rp.join_grid, rp.join_smem, s)) != hipSuccess) {
     return e;
@@ -1355,13 +1423,18 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   const bool use_mfma = ccap <= kMfmaMaxC && !(p->flags & FGIM_FLAG_NO_MFMA_JOIN);
   const uint32_t dpad = (dim + 31) / 32 * 32;
   const uint32_t slice = std::min<uint32_t>(dpad, 128);
-  const size_t mfma_head = kMfmaMaxC * (4 * 4 + 4 + 4 + 8) + 2 * kMfmaMaxCn * 8 + 68 * 4 + 8 * 4 + kPropStage * 12;
-  const size_t f32_rows = static_cast<size_t>(kMfmaMaxC) * (dim + 4) * 4;
-  const bool stage_f32 = mfma_head + f32_rows <= 80 * 1024;
-  const size_t mfma_smem = mfma_head + (stage_f32 ? f32_rows : static_cast<size_t>(kMfmaMaxC) * (slice + 8) * 2);
+  const size_t mfma_head = kMfmaMaxC * (8 + 4 * 4) + 2 * kMfmaMaxCn * 8 + 68 * 4 + 16 * 4;
+  // BF16 slices of the candidate rows in LDS (FP32 rows there cost occupancy
+  // and measured slower); the exact re-scoring reads FP32 rows from memory
+  const size_t mfma_smem = mfma_head + static_cast<size_t>(kMfmaMaxC) * (slice + 8) * 2;
 
   uint64_t cap = std::max<uint64_t>(N * std::max<uint32_t>(4 * p->k, 64), 1 << 16);
   cap = std::min<uint64_t>(cap, 0xF0000000ull);
+  // pairs passing the screen: about k per vertex in the first round at
+  // k = 32; an overflow re-runs with a larger buffer
+  uint64_t pair_cap = std::min<uint64_t>(std::max<uint64_t>(N * 3 * p->k, 1 << 16) +
+                                             static_cast<uint64_t>(device_cus()) * 8 * kPairChunk,
+                                         0xF0000000ull);
 
   for (int attempt = 0; attempt < 3; ++attempt) {
     Scratch scr(s);
@@ -1384,11 +1457,25 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     FGIM_TRY(scr.get(&b.zero, N + 1));
   FGIM_TRY(scr.get(&b.zkey, N + 1));
     FGIM_TRY(scr.get(&b.zkey, N + 1));
-    FGIM_TRY(scr.get(&b.hdr, 8));
+    FGIM_TRY(scr.get(&b.hdr, 16));
     float *nrm2 = nullptr, *qerr2 = nullptr;
+    uint32_t *cand = nullptr, *ccnt = nullptr;
+    uint16_t* xb = nullptr;
+    uint64_t* pairs = nullptr;
+    CandAux* aux = nullptr;
     if (use_mfma) {
       FGIM_TRY(scr.get(&nrm2, N));
       FGIM_TRY(scr.get(&qerr2, N));
+      FGIM_TRY(scr.get(&cand, N * kMfmaMaxC));
+      FGIM_TRY(scr.get(&ccnt, 2 * N));
+      FGIM_TRY(scr.get(&aux, N));
+      FGIM_TRY(scr.get(&pairs, pair_cap));
+      // the screen's error bound is derived for round-to-nearest-even BF16
+      // operands, so the join stages its own copy (never a caller's)
+      if (dim % 8 == 0) {
+        FGIM_TRY(scr.get(&xb, N * dim));
+        FGIM_TRY(quantize_into(d->base, N, dim, d->ld, FGIM_BF16, xb, nullptr, s));
+      }
       hipLaunchKernelGGL(row_norms_kernel, dim3(grid_for(N, 4)), dim3(256), 0, s, d->base, N, dim, d->ld, nrm2, qerr2);
       HIP_TRY(hipGetLastError());
     }
@@ -1397,7 +1484,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     std::vector<uint64_t> hoff(d->h);
     for (uint32_t i = 0; i < d->h; ++i) hoff[i] = d->subs[i].row_offset;
     HIP_TRY(hipMemcpyAsync(b.sub_off, hoff.data(), 8 * d->h, hipMemcpyHostToDevice, s));
-    HIP_TRY(fill_u32(b.hdr, 0u, 8, s));
+    HIP_TRY(fill_u32(b.hdr, 0u, 16, s));
     hipLaunchKernelGGL(to_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, ids, dist, nk, b.keys, b.flags);
     HIP_TRY(hipGetLastError());
 
@@ -1433,17 +1520,25 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     ja.stage_rows = stage_rows;
     ja.nrm2 = nrm2;
     ja.qerr2 = qerr2;
-    ja.stage_f32 = stage_f32;
-    ja.xb = (p->precision == FGIM_BF16 && d->base_lp && dim % 8 == 0) ? static_cast<const uint16_t*>(d->base_lp) : nullptr;
+    ja.xb = xb;
     ja.dim = dim;
     ja.dpad = dpad;
     ja.slice = slice;
     ja.rechecked = b.hdr + 4;
+    ja.cand = cand;
+    ja.ccnt = ccnt;
+    ja.aux = aux;
+    ja.pairs = pairs;
+    ja.npairs = b.hdr + 8;
+    ja.npairs_max = b.hdr + 9;
+    ja.pair_cap = static_cast<uint32_t>(pair_cap);
     rp.use_mfma = use_mfma;
     rp.join_smem = use_mfma ? mfma_smem : base_smem + (stage_rows ? rows_smem : 0);
     rp.join_grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));
+    rp.cand_grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 16));
+    rp.recheck_grid = static_cast<uint32_t>(device_cus()) * 8;
     if (use_mfma && rp.join_smem > 64 * 1024)
-      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(rp.mmax == 4 ? join_mfma_kernel<4> : join_mfma_kernel<16>),
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(join_mfma_kernel),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(rp.join_smem)));
     if (!use_mfma && rp.join_smem > 64 * 1024)
       HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(rp.nr == 1 ? (rp.mmax == 4 ? join_kernel<1, 4> : join_kernel<1, 16>)
@@ -1495,12 +1590,14 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
       hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, b.T);
       HIP_TRY(hipGetLastError());
     }
-    uint32_t hh[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    uint32_t hh[16] = {};
     HIP_TRY(hipMemcpyAsync(hh, b.hdr, sizeof(hh), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (hh[1] > cap) {
-      cap = std::min<uint64_t>(static_cast<uint64_t>(hh[1]) * 5 / 4 + 1024, 0xF0000000ull);
-      continue;  // proposals overflowed: run again with a larger buffer (same result)
+    if (hh[1] > cap || hh[9] > pair_cap) {
+      // a buffer overflowed: run again with larger ones (same result)
+      if (hh[1] > cap) cap = std::min<uint64_t>(static_cast<uint64_t>(hh[1]) * 5 / 4 + 1024, 0xF0000000ull);
+      if (hh[9] > pair_cap) pair_cap = std::min<uint64_t>(static_cast<uint64_t>(hh[9]) * 5 / 4 + 1024, 0xF0000000ull);
+      continue;
     }
     hipLaunchKernelGGL(from_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, ids, dist);
     HIP_TRY(hipGetLastError());
