@@ -117,8 +117,9 @@ typedef struct {
 
 #define FGIM_FLAG_NO_REPAIR 1u     /* refinement without indegree repair (test hook) */
 #define FGIM_FLAG_NO_GRAPH_CAPTURE 2u /* run refinement rounds eagerly, not as a hipGraph */
-#define FGIM_FLAG_NO_MFMA_JOIN 4u   /* score every join pair in FP32 instead of screening the
-                                       tile on MFMA first (same result; test hook) */
+#define FGIM_FLAG_NO_MFMA_SCREEN 4u /* score every join pair and every occlusion pair of the
+                                       neighbour selection in FP32 instead of screening the
+                                       tiles on MFMA first (same result; test hook) */
 
 /* Per-call counters; passing a non-NULL stats pointer synchronises the
  * stream at the end of the call. */

@@ -230,10 +230,11 @@ fgim_status check_dataset(const fgim_dataset* d, bool need_cross) {
 fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* p, BeamShape* out) {
   const uint32_t nc = dim / 4;
   const uint32_t N = ceil_pow2(nc);
-  // defaults measured on 2 x 500k rows, d=128, L=64: two chunks per lane, 32
-  // waves per CU and a 1024-slot visited cache keep ~28 waves resident per CU
-  // (VGPR- and LDS-limited) and beat the 4-chunk/16-wave shape by 23 %
-  uint32_t P = p && p->lanes_per_dist ? p->lanes_per_dist : std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, N), N / 2));
+  // defaults measured on 2 x 500k rows, d=128, L=64: four chunks per lane
+  // (P = 8) with two candidate batches in flight per wave, 32 workgroups per
+  // CU (VGPR-limited to 16 resident) and a 1024-slot visited cache: 95 ms,
+  // against 100 ms for two chunks per lane and 129 ms for the first shape
+  uint32_t P = p && p->lanes_per_dist ? p->lanes_per_dist : std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, N), N / 4));
   if (!is_pow2(P) || P > 64 || P > N) return fail(FGIM_ERR_INVALID_ARG, "lanes_per_dist %u must be a power of 2 <= min(64, %u)", P, N);
   const uint32_t M = N / P;
   if (M > 16) return fail(FGIM_ERR_INVALID_ARG, "lanes_per_dist %u too small for dim %u", P, dim);

@@ -173,42 +173,60 @@ struct Pool {
 
 // Score candidates cand[0..m) (row ids relative to `goff`) against the query
 // held in q; key = (delta, key_off + id).  Group g of P lanes scores
-// candidates g, g+G, ... (G = 64/P).  All lanes must call this.
+// candidates g, g+G, ... (G = 64/P).  The rows of U consecutive group
+// batches are loaded before any is reduced, so their memory latencies
+// overlap.  All lanes must call this.
 template <bool L2, int MMAX, class Row>
 FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, const float4 (&q)[MMAX],
                           const BeamArgs& a, const WaveLds& lds, int m) {
+  constexpr int U = MMAX <= 4 ? 2 : 1;
   const int P = static_cast<int>(a.P);
   const int M = static_cast<int>(a.M);
   const int G = 64 / P;
   const int g = lane_id() / P;
   const int l = lane_id() % P;
-  for (int base = 0; base < m; base += G) {
-    const int c = base + g;
-    const bool act = c < m;
-    const uint32_t rid = lds.cand[act ? c : 0];
-    float s[MMAX];
+  for (int base = 0; base < m; base += G * U) {
+    float4 rv[U][MMAX];
+    uint32_t rid[U];
 #pragma unroll
-    for (int mi = 0; mi < MMAX; ++mi) {
-      s[mi] = 0.0f;
-      const uint32_t ch = static_cast<uint32_t>(l + mi * P);
-      if (mi < M && act && ch < a.nc) s[mi] = chunk_sum<L2 ? kL2 : kIP>(q[mi], rows.chunk(goff + rid, ch));
-    }
+    for (int u = 0; u < U; ++u) {
+      const int c = base + u * G + g;
+      const bool act = c < m;
+      rid[u] = lds.cand[act ? c : 0];
 #pragma unroll
-    for (int st = MMAX / 2; st >= 1; st /= 2) {
-      if (2 * st <= M) {
-#pragma unroll
-        for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
+      for (int mi = 0; mi < MMAX; ++mi) {
+        const uint32_t ch = static_cast<uint32_t>(l + mi * P);
+        rv[u][mi] = (mi < M && act && ch < a.nc) ? rows.chunk(goff + rid[u], ch) : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
-    float r = s[0];
 #pragma unroll
-    for (int st = 32; st >= 1; st /= 2)
-      if (st < P) r = r + shfl_xor_f(r, st);
-    float d;
-    if (a.metric == kL2) d = finish<kL2>(r);
-    else if (a.metric == kIP) d = finish<kIP>(r);
-    else d = finish<kCos>(r);
-    if (act && l == 0) lds.ckey[c] = make_key(d, key_off + rid);
+    for (int u = 0; u < U; ++u) {
+      const int c = base + u * G + g;
+      const bool act = c < m;
+      float s[MMAX];
+#pragma unroll
+      for (int mi = 0; mi < MMAX; ++mi) {
+        s[mi] = 0.0f;
+        const uint32_t ch = static_cast<uint32_t>(l + mi * P);
+        if (mi < M && act && ch < a.nc) s[mi] = chunk_sum<L2 ? kL2 : kIP>(q[mi], rv[u][mi]);
+      }
+#pragma unroll
+      for (int st = MMAX / 2; st >= 1; st /= 2) {
+        if (2 * st <= M) {
+#pragma unroll
+          for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
+        }
+      }
+      float r = s[0];
+#pragma unroll
+      for (int st = 32; st >= 1; st /= 2)
+        if (st < P) r = r + shfl_xor_f(r, st);
+      float d;
+      if (a.metric == kL2) d = finish<kL2>(r);
+      else if (a.metric == kIP) d = finish<kIP>(r);
+      else d = finish<kCos>(r);
+      if (act && l == 0) lds.ckey[c] = make_key(d, key_off + rid[u]);
+    }
   }
 }
 

@@ -10,6 +10,11 @@ namespace fgim {
 constexpr uint8_t kFlagNew = 1;
 constexpr uint8_t kFlagReplaced = 2;
 
+// per row of X: squared FP32 norm and squared norm of its BF16 rounding
+// residual (round to nearest even)
+hipError_t launch_row_norms(const float* X, uint64_t n, uint32_t dim, uint64_t ld, float* nrm2, float* qerr2,
+                            hipStream_t s);
+
 // Exclusive scan of n uint32 counts into out[0..n] (out[n] = total).
 hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t n, uint32_t* block_tmp,
                           hipStream_t s);

@@ -1,11 +1,14 @@
 // Stage 3 of FGIM: k-NNG -> PG (Section 4.3, Algorithm 5), and the
 // three-stage merge entry point.
 //
-//   select   one workgroup per vertex u: the k x k occlusion tile of u's list
-//            (delta(w, v) for every earlier w, canonical FP32, candidate rows
-//            staged in LDS), then the sequential scan of Algorithm 5 over
-//            64-bit masks: v is kept when T(v) = 1 or no kept w has
-//            delta(w, v) <= delta(u, v); at most R are kept.
+//   select   per vertex u: the k x k occlusion tile of u's list (whether
+//            delta(w, v) <= delta(u, v) for every earlier entry w), then the
+//            sequential scan of Algorithm 5 over 64-bit masks: v is kept
+//            when T(v) = 1 or no kept w occludes it; at most R are kept.
+//            For k <= 64 one wavefront per vertex screens the tile on MFMA
+//            (BF16 rows in LDS, rigorous error bound) and re-scores only the
+//            undecided pairs in canonical FP32; otherwise one workgroup per
+//            vertex scores every pair in FP32 from rows staged in LDS.
 //   reverse  CSR of the selected edges by head (count / scan / scatter).
 //   fill     per vertex: first R of its selected neighbours and the vertices
 //            that selected it, (delta, id)-sorted and id-unique.
@@ -14,6 +17,7 @@
 #include "fgim_internal.h"
 #include "graph_util.h"
 #include "host_util.h"
+#include "mfma_util.h"
 
 namespace fgim {
 
@@ -32,6 +36,11 @@ struct SelectArgs {
   uint32_t* sel_n;
   uint32_t P, M;
   int stage_rows;
+  // MFMA screen
+  const float* nrm2;   // squared FP32 norm of every row
+  const float* qerr2;  // squared norm of every row's BF16 rounding residual
+  uint32_t dpad;       // dim rounded up to 32
+  uint32_t wave_smem;  // LDS bytes per wavefront
 };
 
 template <int MMAX>
@@ -123,6 +132,163 @@ __global__ void __launch_bounds__(256) select_kernel(SelectArgs a) {
   }
 }
 
+constexpr uint32_t kSelMfmaMaxK = 64;
+constexpr uint32_t kSelMfmaMaxDpad = 256;
+constexpr size_t kSelMfmaHead = 64 * 8 * 2 + 64 * 4 * 2 + 68 * 4 + 64 * 4 * 3;
+
+FGIM_DEV void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
+FGIM_DEV uint32_t select_bit64(uint64_t m, uint32_t r) {
+  uint32_t pos = 0;
+#pragma unroll
+  for (uint32_t w = 32; w >= 1; w >>= 1) {
+    const uint32_t c = static_cast<uint32_t>(__popcll(m & ((1ull << w) - 1ull)));
+    if (r >= c) {
+      r -= c;
+      m >>= w;
+      pos += w;
+    }
+  }
+  return pos;
+}
+
+// Neighbour selection with the occlusion tile screened on MFMA, one
+// wavefront per vertex (k <= 64 list entries, dim padded to <= 256).  The
+// list's rows are staged in LDS as BF16; every pair (w_q, v_p), q < p, gets
+// the estimate of delta(w_q, v_p) and its bound (screen_estimate): the
+// occlusion bit is set when the estimate plus the bound is below
+// delta(u, v_p), left clear when the estimate minus the bound exceeds it,
+// and otherwise decided by the canonical FP32 distance.  The bits are those
+// of the plain computation.
+template <int MMAX>
+__global__ void __launch_bounds__(128) select_mfma_kernel(SelectArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int wave = threadIdx.x / 64;
+  const int lane = lane_id();
+  unsigned char* wbase = smem + static_cast<size_t>(wave) * a.wave_smem;
+  uint64_t* occl = reinterpret_cast<uint64_t*>(wbase);   // bit q of row p: w_q occludes v_p
+  uint64_t* unc = occl + 64;                             // bit q of row p: undecided by the screen
+  uint32_t* vid = reinterpret_cast<uint32_t*>(unc + 64);
+  uint32_t* tv = vid + 64;
+  uint32_t* rowoff = tv + 64;                            // 65 prefix counts of undecided pairs
+  float* vd = reinterpret_cast<float*>(rowoff + 68);
+  float* nrm = vd + 64;
+  float* qe = nrm + 64;
+  uint16_t* rows = reinterpret_cast<uint16_t*>(qe + 64);  // BF16 rows, stride dpad + 8
+  const uint32_t srow = a.dpad + 8;
+  const uint32_t dim = a.nc * 4;
+  const float gam = fp32_gamma(dim);
+  const int P = static_cast<int>(a.P), M = static_cast<int>(a.M);
+  const int l = lane % P, g = lane / P, G = 64 / P;
+
+  for (uint64_t u = blockIdx.x * 2ull + wave; u < a.N; u += gridDim.x * 2ull) {
+    const bool in = static_cast<uint32_t>(lane) < a.k;
+    const uint32_t v = in ? a.ids[u * a.k + lane] : kNone;
+    // the list's entries up to its first free slot
+    const uint64_t invalid = ballot(v == kNone);
+    const uint32_t cnt = invalid ? static_cast<uint32_t>(ffs64(invalid)) : 64u;
+    const bool valid = static_cast<uint32_t>(lane) < cnt;
+    vid[lane] = valid ? v : kNone;
+    vd[lane] = valid ? a.dist[u * a.k + lane] : 0.0f;
+    tv[lane] = valid ? a.T[v] : 0u;
+    nrm[lane] = valid ? a.nrm2[v] : 0.0f;
+    qe[lane] = valid ? sqrtf(a.qerr2[v]) * (1.0f + gam) * 1.0001f : 0.0f;
+    occl[lane] = 0;
+    unc[lane] = 0;
+    wave_lds_sync();
+    const uint32_t kpad = (cnt + 15) & ~15u;
+    const uint32_t per_row = a.dpad / 8;
+    for (uint32_t idx = lane; idx < kpad * per_row; idx += 64) {
+      const uint32_t e = idx / per_row, t0 = 8 * (idx - e * per_row);
+      shortx8_t v8 = shortx8_t{0, 0, 0, 0, 0, 0, 0, 0};
+      if (e < cnt && t0 < dim) {
+        const float* xr = a.X + static_cast<uint64_t>(vid[e]) * a.ld + t0;
+        const float4 f0 = *reinterpret_cast<const float4*>(xr);
+        const float4 f1 = t0 + 4 < dim ? *reinterpret_cast<const float4*>(xr + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+        v8[0] = bf16_rne(f0.x); v8[1] = bf16_rne(f0.y); v8[2] = bf16_rne(f0.z); v8[3] = bf16_rne(f0.w);
+        v8[4] = bf16_rne(f1.x); v8[5] = bf16_rne(f1.y); v8[6] = bf16_rne(f1.z); v8[7] = bf16_rne(f1.w);
+      }
+      *reinterpret_cast<shortx8_t*>(rows + e * srow + t0) = v8;
+    }
+    wave_lds_sync();
+    // tiles (I, J), J <= I, of the Gram matrix; D[i][j] = <row i, row j>
+    const uint32_t nt = kpad / 16;
+    for (uint32_t I = 0; I < nt; ++I) {
+      for (uint32_t J = 0; J <= I; ++J) {
+        floatx4_t acc = floatx4_t{0.f, 0.f, 0.f, 0.f};
+        for (uint32_t kb = 0; kb < a.dpad; kb += 32) {
+          const shortx8_t ra = *reinterpret_cast<const shortx8_t*>(rows + (16 * I + lane % 16) * srow + kb + 8 * (lane / 16));
+          const shortx8_t rb = *reinterpret_cast<const shortx8_t*>(rows + (16 * J + lane % 16) * srow + kb + 8 * (lane / 16));
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ra), __builtin_bit_cast(bf16x8_t, rb),
+                                                        acc, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const uint32_t i = 16 * I + 4 * (lane / 16) + r, j = 16 * J + lane % 16;
+          if (i < cnt && j < i && tv[i] != 1u) {
+            float dt, err;
+            screen_estimate(acc[r], nrm[i], nrm[j], qe[i], qe[j], gam, a.metric, &dt, &err);
+            const float dup = vd[i];
+            if (dt + err < dup) atomicOr(reinterpret_cast<unsigned long long*>(&occl[i]), 1ull << j);
+            else if (!(dt - err > dup)) atomicOr(reinterpret_cast<unsigned long long*>(&unc[i]), 1ull << j);
+          }
+        }
+      }
+    }
+    wave_lds_sync();
+    // exact re-scoring of the undecided pairs, enumerated flat over rows
+    {
+      const uint32_t c0 = static_cast<uint32_t>(lane) < cnt ? static_cast<uint32_t>(__popcll(unc[lane])) : 0u;
+      uint32_t incl = c0;
+#pragma unroll
+      for (int st = 1; st < 64; st <<= 1) {
+        const uint32_t o = static_cast<uint32_t>(__shfl_up(static_cast<int>(incl), st, 64));
+        if (lane >= st) incl += o;
+      }
+      rowoff[lane + 1] = incl;
+      if (lane == 0) rowoff[0] = 0;
+    }
+    wave_lds_sync();
+    const uint32_t nu = rowoff[cnt];
+    for (uint32_t b = 0; b < nu; b += static_cast<uint32_t>(G)) {
+      const uint32_t idx = b + static_cast<uint32_t>(g);
+      const bool act = idx < nu;
+      uint32_t i = 0, j = 0;
+      if (act) {
+        uint32_t lo = 0, hi = cnt;  // the row holding idx: last row with rowoff <= idx
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) / 2;
+          if (rowoff[mid] <= idx) lo = mid;
+          else hi = mid;
+        }
+        i = lo;
+        j = select_bit64(unc[i], idx - rowoff[i]);
+      }
+      const float dd = pair_distance<MMAX>(a.X + static_cast<uint64_t>(vid[i]) * a.ld,
+                                           a.X + static_cast<uint64_t>(vid[j]) * a.ld, a.metric, a.nc, P, M, l, act);
+      if (act && l == 0 && !(vd[i] < dd)) atomicOr(reinterpret_cast<unsigned long long*>(&occl[i]), 1ull << j);
+    }
+    wave_lds_sync();
+    if (lane == 0) {
+      uint64_t kept = 0;
+      uint32_t ns = 0;
+      for (uint32_t p = 0; p < cnt && ns < a.R; ++p) {
+        if (tv[p] == 1u || (occl[p] & kept) == 0) {
+          kept |= 1ull << p;
+          a.sel_ids[u * a.R + ns] = vid[p];
+          a.sel_dist[u * a.R + ns] = vd[p];
+          ++ns;
+        }
+      }
+      a.sel_n[u] = ns;
+    }
+    wave_lds_sync();
+  }
+}
+
 __global__ void sel_count_kernel(const uint32_t* sel_ids, const uint32_t* sel_n, uint64_t N, uint32_t R, uint32_t* cnt) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < N * R;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
@@ -169,10 +335,15 @@ __global__ void __launch_bounds__(256) fill_kernel(const uint32_t* sel_ids, cons
   }
 }
 
-__global__ void validate_lists_kernel(const uint32_t* ids, uint64_t nk, uint64_t N, uint32_t* err) {
+// every id < N or FGIM_NONE, and FGIM_NONE only as padding after a list's
+// entries (k ids per list)
+__global__ void validate_lists_kernel(const uint32_t* ids, uint64_t nk, uint64_t N, uint32_t k, uint32_t* err) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-    if (ids[i] != kNone && ids[i] >= N) atomicOr(err, 1u);
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t v = ids[i];
+    if (v == kNone) continue;
+    if (v >= N || (i % k != 0 && ids[i - 1] == kNone)) atomicOr(err, 1u);
+  }
 }
 
 static uint32_t grid_n(uint64_t n, uint32_t per_block = 256) {
@@ -218,15 +389,35 @@ fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32
   FGIM_TRY(scr.get(&tmp, scan_tmp_words(N) + 16));
   FGIM_TRY(scr.get(&err, 4));
   HIP_TRY(fill_u32(err, 0u, 1, s));
-  hipLaunchKernelGGL(validate_lists_kernel, dim3(grid_n(N * k)), dim3(256), 0, s, ids, N * k, N, err);
+  hipLaunchKernelGGL(validate_lists_kernel, dim3(grid_n(N * k)), dim3(256), 0, s, ids, N * k, N, p->k, err);
   uint32_t herr = 0;
   HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
-  if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n_total");
+  if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n_total or an entry after a free slot");
 
-  SelectArgs sa{d->base, d->ld, nc, d->metric, N, p->k, p->R, ids, dist, T, sel_ids, sel_dist, sel_n, P, M, stage};
+  SelectArgs sa{d->base, d->ld, nc, d->metric, N, p->k, p->R, ids, dist, T, sel_ids, sel_dist, sel_n, P, M, stage,
+                nullptr, nullptr, 0, 0};
   const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));
-  if (M <= 4) {
+  const uint32_t dpad = (d->dim + 31) / 32 * 32;
+  const bool use_mfma = k <= kSelMfmaMaxK && dpad <= kSelMfmaMaxDpad && !(p->flags & FGIM_FLAG_NO_MFMA_SCREEN);
+  if (use_mfma) {
+    float *nrm2 = nullptr, *qerr2 = nullptr;
+    FGIM_TRY(scr.get(&nrm2, N));
+    FGIM_TRY(scr.get(&qerr2, N));
+    HIP_TRY(launch_row_norms(d->base, N, d->dim, d->ld, nrm2, qerr2, s));
+    sa.nrm2 = nrm2;
+    sa.qerr2 = qerr2;
+    sa.dpad = dpad;
+    const uint32_t kpad = (static_cast<uint32_t>(k) + 15) & ~15u;
+    sa.wave_smem = static_cast<uint32_t>(kSelMfmaHead + static_cast<size_t>(kpad) * (dpad + 8) * 2);
+    const size_t msmem = 2 * static_cast<size_t>(sa.wave_smem);
+    const uint32_t mgrid = static_cast<uint32_t>(std::min<uint64_t>((N + 1) / 2, static_cast<uint64_t>(device_cus()) * 16));
+    auto kern = M <= 4 ? select_mfma_kernel<4> : select_mfma_kernel<16>;
+    if (msmem > 64 * 1024)
+      HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(kern), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  static_cast<int>(msmem)));
+    hipLaunchKernelGGL(kern, dim3(mgrid), dim3(128), msmem, s, sa);
+  } else if (M <= 4) {
     if (smem > 64 * 1024)
       HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(select_kernel<4>), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   static_cast<int>(smem)));

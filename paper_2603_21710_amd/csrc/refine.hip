@@ -25,6 +25,7 @@
 
 #include "fgim_internal.h"
 #include "graph_util.h"
+#include "mfma_util.h"
 #include "host_util.h"
 
 namespace fgim {
@@ -414,16 +415,6 @@ __global__ void __launch_bounds__(256) join_kernel(JoinArgs a) {
 // either end's worst entry, so the proposals are exactly those of the
 // plain join.
 
-typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
-typedef short shortx8_t __attribute__((ext_vector_type(8)));
-typedef float floatx4_t __attribute__((ext_vector_type(4)));
-
-FGIM_DEV float bf16_value(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return __uint_as_float(u & 0xFFFF0000u);
-}
-
 // per row: squared FP32 norm and squared norm of the BF16 rounding residual
 // x - bf16(x) (one wavefront per row)
 __global__ void __launch_bounds__(256) row_norms_kernel(const float* X, uint64_t n, uint32_t dim, uint64_t ld,
@@ -448,10 +439,12 @@ __global__ void __launch_bounds__(256) row_norms_kernel(const float* X, uint64_t
   }
 }
 
-FGIM_DEV uint16_t bf16_rne(float x) {
-  uint32_t u = __float_as_uint(x);
-  u += 0x7FFFu + ((u >> 16) & 1u);
-  return static_cast<uint16_t>(u >> 16);
+hipError_t launch_row_norms(const float* X, uint64_t n, uint32_t dim, uint64_t ld, float* nrm2, float* qerr2,
+                            hipStream_t s) {
+  const uint64_t b = (n + 3) / 4;
+  hipLaunchKernelGGL(row_norms_kernel, dim3(static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(b, 1), 65536))),
+                     dim3(256), 0, s, X, n, dim, ld, nrm2, qerr2);
+  return hipGetLastError();
 }
 
 // bitonic sort of up to 128 uint32 values held two per lane (element
@@ -548,8 +541,7 @@ __global__ void __launch_bounds__(128) cand_kernel(JoinArgs a) {
   __shared__ uint32_t counters[4];
   const int wave = threadIdx.x / 64;
   const int lane = lane_id();
-  const float u32 = 5.9604645e-8f;  // 2^-24
-  const float gam = (a.dim + 4) * u32 / (1.0f - (a.dim + 4) * u32);
+  const float gam = fp32_gamma(a.dim);
   for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
     if (threadIdx.x < 4) counters[threadIdx.x] = 0;
     arr_n[threadIdx.x] = kNone;
@@ -632,8 +624,7 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
   const uint32_t srow = a.slice + 8;
   const int wave = threadIdx.x / 64;
   const int lane = lane_id();
-  const float u32 = 5.9604645e-8f;  // 2^-24
-  const float gam = (a.dim + 4) * u32 / (1.0f - (a.dim + 4) * u32);
+  const float gam = fp32_gamma(a.dim);
   uint32_t nrech = 0;  // pairs passing the screen (thread 0)
   if (threadIdx.x >= 8 && threadIdx.x < 16) counters[threadIdx.x] = 0;
 
@@ -702,14 +693,8 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
         }
       }
     }
-    // Screen.  With a^, b^ the BF16 operands, e_a = |a - a^| (FP32 residual
-    // norm, inflated by its own rounding bound) and gamma = (d+4)u/(1-(d+4)u):
-    //   |<a^,b^>_mfma - <a,b>| <= e_a (|b| + e_b) + |a| e_b + gamma (|a| + e_a)(|b| + e_b)
-    // (Cauchy-Schwarz on the residuals plus any-order FP32 accumulation);
-    // the L2 estimate adds the FP32 norms' own error.  The canonical FP32
-    // distance of the oracle is within gamma of the true value.  The bound is
-    // doubled; a pair passes when its estimate minus the bound could still
-    // beat the worst entry of either end.
+    // Screen (screen_estimate): a pair passes when its estimate minus the
+    // bound could still beat the worst entry of either end.
 #pragma unroll
     for (uint32_t sl = 0; sl < kMfmaTilesPerWave; ++sl) {
       uint32_t tp = static_cast<uint32_t>(wave) + 4u * sl;
@@ -725,24 +710,8 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
         const uint32_t i = 16 * I + 4 * (lane / 16) + r, j = 16 * J + lane % 16;
         const bool valid = i < nn && j < c && j > i && cg[i] != cg[j];
         if (!valid) continue;
-        const float G = acc[sl][r];
-        const float na2 = cnrm[i], nb2 = cnrm[j];
-        const float na = sqrtf(na2) * (1.0f + gam) * 1.0001f, nb = sqrtf(nb2) * (1.0f + gam) * 1.0001f;
-        const float ea = cqe[i], eb = cqe[j];
-        const float eg = ea * (nb + eb) + na * eb + gam * (na + ea) * (nb + eb) + 1e-30f;
         float dt, err;
-        if (a.metric == kL2) {
-          dt = na2 + nb2 - 2.0f * G;
-          err = gam * (na2 + nb2) + 2.0f * eg + 4.0f * u32 * (na2 + nb2 + 2.0f * fabsf(G));
-          err += gam * (fabsf(dt) + err);
-        } else if (a.metric == kIP) {
-          dt = -G;
-          err = eg + gam * na * nb;
-        } else {
-          dt = 1.0f - G;
-          err = eg + gam * na * nb + u32 * (1.0f + fabsf(G));
-        }
-        err *= 2.0f;
+        screen_estimate(acc[sl][r], cnrm[i], cnrm[j], cqe[i], cqe[j], gam, a.metric, &dt, &err);
         const float thr = fmaxf(key_dist(cw[i]), key_dist(cw[j]));
         if (dt - err <= thr)
           atomicOr(reinterpret_cast<unsigned long long*>(&pmask[2 * i + j / 64]), 1ull << (j % 64));
@@ -1085,26 +1054,41 @@ struct RepairShape {
 
 FGIM_DEV uint32_t repair_slot(uint32_t id) { return (id * 0x9E3779B1u) >> 21; }
 
+// A table slot packs (vertex << 32) | step; kEmptySlot is free.
+constexpr uint64_t kEmptySlot = ~0ull;
+
 // record that step i writes id (keeps the smallest step per id)
-FGIM_DEV void note_write(uint32_t* hid, uint32_t* hstep, uint32_t id, uint32_t i) {
+FGIM_DEV void note_write(uint64_t* tab, uint32_t id, uint32_t i) {
   uint32_t s = repair_slot(id);
+  const uint64_t mine = (static_cast<uint64_t>(id) << 32) | i;
   for (;;) {
-    const uint32_t prev = atomicCAS(&hid[s], kNone, id);
-    if (prev == kNone || prev == id) break;
+    const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[s]), kEmptySlot, mine);
+    if (prev == kEmptySlot) return;
+    if (static_cast<uint32_t>(prev >> 32) == id) {
+      atomicMin(reinterpret_cast<unsigned long long*>(&tab[s]), mine);
+      return;
+    }
     s = (s + 1) & (kRepairHash - 1);
   }
-  atomicMin(&hstep[s], i);
 }
 
-// first step of the batch that writes id (kNone: none)
-FGIM_DEV uint32_t first_write(const uint32_t* hid, const uint32_t* hstep, uint32_t id) {
-  uint32_t s = repair_slot(id);
+FGIM_DEV uint32_t first_write_chain(const uint64_t* tab, uint32_t id, uint32_t s) {
   for (;;) {
-    const uint32_t cur = hid[s];
-    if (cur == id) return hstep[s];
-    if (cur == kNone) return kNone;
     s = (s + 1) & (kRepairHash - 1);
+    const uint64_t cur = tab[s];
+    if (static_cast<uint32_t>(cur >> 32) == id) return static_cast<uint32_t>(cur);
+    if (cur == kEmptySlot) return kNone;
   }
+}
+
+// first step of the batch that writes id (kNone: none); one LDS read unless
+// the home slot holds another vertex
+FGIM_DEV uint32_t first_write(const uint64_t* tab, uint32_t id) {
+  const uint32_t s = repair_slot(id);
+  const uint64_t cur = tab[s];
+  if (static_cast<uint32_t>(cur >> 32) == id) return static_cast<uint32_t>(cur);
+  if (cur == kEmptySlot) return kNone;
+  return first_write_chain(tab, id, s);
 }
 
 template <int NR>
@@ -1114,16 +1098,14 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
   // nrep[0]: vertices repaired, nrep[3]: batches, nrep[4]: steps run alone
   constexpr int S = RepairShape<NR>::kSteps;
   constexpr uint32_t B = RepairShape<NR>::kBatch;
-  __shared__ uint32_t h_lid[kRepairHash], h_lstep[kRepairHash];  // lists written
-  __shared__ uint32_t h_eid[kRepairHash], h_estep[kRepairHash];  // indegrees lowered
+  __shared__ uint64_t h_list[kRepairHash];   // lists written
+  __shared__ uint64_t h_evict[kRepairHash];  // indegrees lowered
   __shared__ uint32_t s_stop[2];  // first step of the batch that cannot commit
   const int w = threadIdx.x / 64;
   const int lane = lane_id();
   for (int t = threadIdx.x; t < kRepairHash; t += blockDim.x) {
-    h_lid[t] = kNone;
-    h_lstep[t] = kNone;
-    h_eid[t] = kNone;
-    h_estep[t] = kNone;
+    h_list[t] = kEmptySlot;
+    h_evict[t] = kEmptySlot;
   }
   if (threadIdx.x < 2) s_stop[threadIdx.x] = kNone;
   __syncthreads();
@@ -1193,8 +1175,8 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
         my_evict = ev;
       }
     }
-    if (my_list != kNone) note_write(h_lid, h_lstep, my_list, my_step);
-    if (my_evict != kNone) note_write(h_eid, h_estep, my_evict, my_step);
+    if (my_list != kNone) note_write(h_list, my_list, my_step);
+    if (my_evict != kNone) note_write(h_evict, my_evict, my_step);
     __syncthreads();
     if (threadIdx.x == 0) s_stop[parity ^ 1u] = kNone;
     uint32_t my_stop = kNone;
@@ -1202,11 +1184,11 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
     for (int s = 0; s < S; ++s) {
       const uint32_t i = s * kRepairWaves + w;
       bool stop = has[s] && !at[s].ok;
-      if (at[s].ok && first_write(h_lid, h_lstep, v[s]) < i) stop = true;
+      if (at[s].ok && first_write(h_list, v[s]) < i) stop = true;
       bool hit = false;
 #pragma unroll
       for (int r = 0; r < NR; ++r)
-        if (at[s].ok && at[s].lk[r] != kSentinel) hit |= first_write(h_eid, h_estep, key_id(at[s].lk[r])) < i;
+        if (at[s].ok && at[s].lk[r] != kSentinel) hit |= first_write(h_evict, key_id(at[s].lk[r])) < i;
       if (ballot(hit)) stop = true;
       if (stop && i < my_stop) my_stop = i;
     }
@@ -1252,10 +1234,8 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
       pend = 1;
     }
     for (int t = threadIdx.x; t < kRepairHash; t += blockDim.x) {
-      h_lid[t] = kNone;
-      h_lstep[t] = kNone;
-      h_eid[t] = kNone;
-      h_estep[t] = kNone;
+      h_list[t] = kEmptySlot;
+      h_evict[t] = kEmptySlot;
     }
     __threadfence_block();
     __syncthreads();
@@ -1420,7 +1400,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   const bool stage_rows = base_smem + rows_smem <= 96 * 1024;
 
   // MFMA join when the candidate set fits its tile layout (|Cn| + |Co| <= 128)
-  const bool use_mfma = ccap <= kMfmaMaxC && !(p->flags & FGIM_FLAG_NO_MFMA_JOIN);
+  const bool use_mfma = ccap <= kMfmaMaxC && !(p->flags & FGIM_FLAG_NO_MFMA_SCREEN);
   const uint32_t dpad = (dim + 31) / 32 * 32;
   const uint32_t slice = std::min<uint32_t>(dpad, 128);
   const size_t mfma_head = kMfmaMaxC * (8 + 4 * 4) + 2 * kMfmaMaxCn * 8 + 68 * 4 + 16 * 4;

@@ -44,7 +44,7 @@ def test_refine_matches_oracle(name, sizes, rounds, repair, join):
     print(f"case {name} rounds={rounds} repair={repair}", flush=True)
     oi, od, of, oT, ost = oracle.refine(X, graphs, _u32(ids), dist.cpu().numpy(), rounds,
                                         cfg.metric, do_repair=repair)
-    flags = (0 if repair else fg.FGIM_FLAG_NO_REPAIR) | (fg.FGIM_FLAG_NO_MFMA_JOIN if join == "fp32" else 0)
+    flags = (0 if repair else fg.FGIM_FLAG_NO_REPAIR) | (fg.FGIM_FLAG_NO_MFMA_SCREEN if join == "fp32" else 0)
     T, st = fg.refine(m, fg.params(k=cfg.k, L=cfg.L, rounds=rounds, flags=flags), ids, dist,
                       stats=True)
     if join == "mfma":
@@ -95,9 +95,21 @@ def test_prune_matches_oracle(name, sizes):
     gT = torch.from_numpy(oT.view(np.int32)).to(dev)
     for R in (cfg.R, 8):
         pi, pd, pdeg = oracle.prune(X, oi, od, oT, R, cfg.metric)
-        pg, deg = fg.prune(m, fg.params(k=cfg.k, L=cfg.L, R=R), gids, gd, gT)
-        assert (_u32(pg) == pi).all(), f"R={R}"
-        assert (_u32(deg) == pdeg).all()
+        # the MFMA-screened selection (k <= 64, dim <= 256) and the FP32 one
+        for flags in (0, fg.FGIM_FLAG_NO_MFMA_SCREEN):
+            pg, deg = fg.prune(m, fg.params(k=cfg.k, L=cfg.L, R=R, flags=flags), gids, gd, gT)
+            assert (_u32(pg) == pi).all(), f"R={R} flags={flags}"
+            assert (_u32(deg) == pdeg).all()
+
+
+def test_prune_rejects_list_holes():
+    cfg, X, graphs, m, ids, dist = _stage1("cfg1", None)
+    T, _ = fg.refine(m, fg.params(k=cfg.k, L=cfg.L, rounds=1), ids, dist)
+    bad = ids.clone()
+    bad[3, 2] = -1  # a free slot before occupied ones
+    with pytest.raises(fg.FgimError) as ei:
+        fg.prune(m, fg.params(k=cfg.k, L=cfg.L, R=cfg.R), bad, dist, T)
+    assert ei.value.name == "FGIM_ERR_GRAPH"
 
 
 @pytest.mark.parametrize("name,sizes", CASES, ids=IDS)
