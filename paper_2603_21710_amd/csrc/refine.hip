@@ -1154,10 +1154,12 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
         tv[s][r] = at[s].lk[r] != kSentinel && e + kTail >= k ? ld_wg32(&T[key_id(at[s].lk[r])]) : 0u;
       }
     uint32_t my_list = kNone, my_evict = kNone, my_step = 0;
+    bool full[S];  // the step read every entry's indegree (else only the tail's)
 #pragma unroll
     for (int s = 0; s < S; ++s) {
       decide_attempt<NR>(at[s], tv[s], k);
-      if (has[s] && !at[s].ok) {
+      full[s] = has[s] && !at[s].ok;
+      if (full[s]) {
         // none of the tail qualifies: read every entry's indegree
 #pragma unroll
         for (int r = 0; r < NR; ++r)
@@ -1185,10 +1187,16 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
       const uint32_t i = s * kRepairWaves + w;
       bool stop = has[s] && !at[s].ok;
       if (at[s].ok && first_write(h_list, v[s]) < i) stop = true;
+      // indegrees this step read: none for a free slot, else the tail's, or
+      // every entry's after the fallback
+      const bool reads_t = at[s].ok && at[s].drop >= 0;
       bool hit = false;
 #pragma unroll
-      for (int r = 0; r < NR; ++r)
-        if (at[s].ok && at[s].lk[r] != kSentinel) hit |= first_write(h_evict, key_id(at[s].lk[r])) < i;
+      for (int r = 0; r < NR; ++r) {
+        const uint32_t e = r * 64 + lane;
+        if (reads_t && at[s].lk[r] != kSentinel && (full[s] || e + kTail >= k))
+          hit |= first_write(h_evict, key_id(at[s].lk[r])) < i;
+      }
       if (ballot(hit)) stop = true;
       if (stop && i < my_stop) my_stop = i;
     }
