@@ -179,24 +179,31 @@ struct Pool {
 template <bool L2, int MMAX, class Row>
 FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, const float4 (&q)[MMAX],
                           const BeamArgs& a, const WaveLds& lds, int m) {
-  constexpr int U = MMAX <= 4 ? 2 : 1;
+  // group batches in flight: two for FP32 rows, else as many as about 32
+  // registers of raw (BF16 / FP8) row data per lane hold, at most four
+  // (measured on d = 128 and d = 768)
+  constexpr int kRawRegs = static_cast<int>(sizeof(typename Row::Raw) / 4);
+  constexpr int kLowP = 32 / (MMAX * kRawRegs) < 4 ? 32 / (MMAX * kRawRegs) : 4;
+  constexpr int U = MMAX > 4 ? 1 : (kRawRegs == 4 ? 2 : kLowP);
   const int P = static_cast<int>(a.P);
   const int M = static_cast<int>(a.M);
   const int G = 64 / P;
   const int g = lane_id() / P;
   const int l = lane_id() % P;
   for (int base = 0; base < m; base += G * U) {
-    float4 rv[U][MMAX];
+    typename Row::Raw rv[U][MMAX];
+    float sc[U];
     uint32_t rid[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int c = base + u * G + g;
       const bool act = c < m;
       rid[u] = lds.cand[act ? c : 0];
+      sc[u] = act ? rows.scale(goff + rid[u]) : 1.0f;
 #pragma unroll
       for (int mi = 0; mi < MMAX; ++mi) {
         const uint32_t ch = static_cast<uint32_t>(l + mi * P);
-        rv[u][mi] = (mi < M && act && ch < a.nc) ? rows.chunk(goff + rid[u], ch) : make_float4(0.f, 0.f, 0.f, 0.f);
+        rv[u][mi] = (mi < M && act && ch < a.nc) ? rows.raw(goff + rid[u], ch) : typename Row::Raw{};
       }
     }
 #pragma unroll
@@ -208,7 +215,7 @@ FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, cons
       for (int mi = 0; mi < MMAX; ++mi) {
         s[mi] = 0.0f;
         const uint32_t ch = static_cast<uint32_t>(l + mi * P);
-        if (mi < M && act && ch < a.nc) s[mi] = chunk_sum<L2 ? kL2 : kIP>(q[mi], rv[u][mi]);
+        if (mi < M && act && ch < a.nc) s[mi] = chunk_sum<L2 ? kL2 : kIP>(q[mi], Row::decode(rv[u][mi], sc[u]));
       }
 #pragma unroll
       for (int st = MMAX / 2; st >= 1; st /= 2) {
