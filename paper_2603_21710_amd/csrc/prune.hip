@@ -133,7 +133,8 @@ __global__ void __launch_bounds__(256) select_kernel(SelectArgs a) {
 }
 
 constexpr uint32_t kSelMfmaMaxK = 64;
-constexpr uint32_t kSelMfmaMaxDpad = 256;
+constexpr uint32_t kSelMfmaSlice = 256;  // dimensions staged in LDS at a time
+constexpr int kSelTiles = 10;            // lower-triangle 16 x 16 tiles for 64 rows
 constexpr size_t kSelMfmaHead = 64 * 8 * 2 + 64 * 4 * 2 + 68 * 4 + 64 * 4 * 3;
 
 FGIM_DEV void wave_lds_sync() {
@@ -156,8 +157,9 @@ FGIM_DEV uint32_t select_bit64(uint64_t m, uint32_t r) {
 }
 
 // Neighbour selection with the occlusion tile screened on MFMA, one
-// wavefront per vertex (k <= 64 list entries, dim padded to <= 256).  The
-// list's rows are staged in LDS as BF16; every pair (w_q, v_p), q < p, gets
+// wavefront per vertex (k <= 64 list entries).  The list's rows are staged
+// in LDS as BF16, kSelMfmaSlice dimensions at a time, and the Gram tiles
+// accumulate over the slices; every pair (w_q, v_p), q < p, gets
 // the estimate of delta(w_q, v_p) and its bound (screen_estimate): the
 // occlusion bit is set when the estimate plus the bound is below
 // delta(u, v_p), left clear when the estimate minus the bound exceeds it,
@@ -177,8 +179,9 @@ __global__ void __launch_bounds__(128) select_mfma_kernel(SelectArgs a) {
   float* vd = reinterpret_cast<float*>(rowoff + 68);
   float* nrm = vd + 64;
   float* qe = nrm + 64;
-  uint16_t* rows = reinterpret_cast<uint16_t*>(qe + 64);  // BF16 rows, stride dpad + 8
-  const uint32_t srow = a.dpad + 8;
+  uint16_t* rows = reinterpret_cast<uint16_t*>(qe + 64);  // BF16 rows, stride slice + 8
+  const uint32_t slice = a.dpad < kSelMfmaSlice ? a.dpad : kSelMfmaSlice;
+  const uint32_t srow = slice + 8;
   const uint32_t dim = a.nc * 4;
   const float gam = fp32_gamma(dim);
   const int P = static_cast<int>(a.P), M = static_cast<int>(a.M);
@@ -200,37 +203,54 @@ __global__ void __launch_bounds__(128) select_mfma_kernel(SelectArgs a) {
     unc[lane] = 0;
     wave_lds_sync();
     const uint32_t kpad = (cnt + 15) & ~15u;
-    const uint32_t per_row = a.dpad / 8;
-    for (uint32_t idx = lane; idx < kpad * per_row; idx += 64) {
-      const uint32_t e = idx / per_row, t0 = 8 * (idx - e * per_row);
-      shortx8_t v8 = shortx8_t{0, 0, 0, 0, 0, 0, 0, 0};
-      if (e < cnt && t0 < dim) {
-        const float* xr = a.X + static_cast<uint64_t>(vid[e]) * a.ld + t0;
-        const float4 f0 = *reinterpret_cast<const float4*>(xr);
-        const float4 f1 = t0 + 4 < dim ? *reinterpret_cast<const float4*>(xr + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
-        v8[0] = bf16_rne(f0.x); v8[1] = bf16_rne(f0.y); v8[2] = bf16_rne(f0.z); v8[3] = bf16_rne(f0.w);
-        v8[4] = bf16_rne(f1.x); v8[5] = bf16_rne(f1.y); v8[6] = bf16_rne(f1.z); v8[7] = bf16_rne(f1.w);
-      }
-      *reinterpret_cast<shortx8_t*>(rows + e * srow + t0) = v8;
-    }
-    wave_lds_sync();
-    // tiles (I, J), J <= I, of the Gram matrix; D[i][j] = <row i, row j>
     const uint32_t nt = kpad / 16;
-    for (uint32_t I = 0; I < nt; ++I) {
-      for (uint32_t J = 0; J <= I; ++J) {
-        floatx4_t acc = floatx4_t{0.f, 0.f, 0.f, 0.f};
-        for (uint32_t kb = 0; kb < a.dpad; kb += 32) {
-          const shortx8_t ra = *reinterpret_cast<const shortx8_t*>(rows + (16 * I + lane % 16) * srow + kb + 8 * (lane / 16));
-          const shortx8_t rb = *reinterpret_cast<const shortx8_t*>(rows + (16 * J + lane % 16) * srow + kb + 8 * (lane / 16));
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ra), __builtin_bit_cast(bf16x8_t, rb),
-                                                        acc, 0, 0, 0);
+    const uint32_t ntl = nt * (nt + 1) / 2;  // tiles (I, J), J <= I, in order t = I (I + 1) / 2 + J
+    floatx4_t acc[kSelTiles];
+#pragma unroll
+    for (int t = 0; t < kSelTiles; ++t) acc[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
+    for (uint32_t s0 = 0; s0 < a.dpad; s0 += slice) {
+      const uint32_t sw = a.dpad - s0 < slice ? a.dpad - s0 : slice;  // multiple of 32
+      const uint32_t per_row = sw / 8;
+      for (uint32_t idx = lane; idx < kpad * per_row; idx += 64) {
+        const uint32_t e = idx / per_row, c8 = 8 * (idx - e * per_row), t0 = s0 + c8;
+        shortx8_t v8 = shortx8_t{0, 0, 0, 0, 0, 0, 0, 0};
+        if (e < cnt && t0 < dim) {
+          const float* xr = a.X + static_cast<uint64_t>(vid[e]) * a.ld + t0;
+          const float4 f0 = *reinterpret_cast<const float4*>(xr);
+          const float4 f1 = t0 + 4 < dim ? *reinterpret_cast<const float4*>(xr + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+          v8[0] = bf16_rne(f0.x); v8[1] = bf16_rne(f0.y); v8[2] = bf16_rne(f0.z); v8[3] = bf16_rne(f0.w);
+          v8[4] = bf16_rne(f1.x); v8[5] = bf16_rne(f1.y); v8[6] = bf16_rne(f1.z); v8[7] = bf16_rne(f1.w);
         }
+        *reinterpret_cast<shortx8_t*>(rows + e * srow + c8) = v8;
+      }
+      wave_lds_sync();
+      // D[i][j] = <row i, row j> over this slice, accumulated
+#pragma unroll
+      for (int t = 0; t < kSelTiles; ++t) {
+        if (static_cast<uint32_t>(t) < ntl) {
+          const uint32_t I = t >= 6 ? 3 : (t >= 3 ? 2 : (t >= 1 ? 1 : 0));
+          const uint32_t J = static_cast<uint32_t>(t) - I * (I + 1) / 2;
+          for (uint32_t kb = 0; kb < sw; kb += 32) {
+            const shortx8_t ra = *reinterpret_cast<const shortx8_t*>(rows + (16 * I + lane % 16) * srow + kb + 8 * (lane / 16));
+            const shortx8_t rb = *reinterpret_cast<const shortx8_t*>(rows + (16 * J + lane % 16) * srow + kb + 8 * (lane / 16));
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, ra),
+                                                             __builtin_bit_cast(bf16x8_t, rb), acc[t], 0, 0, 0);
+          }
+        }
+      }
+      wave_lds_sync();
+    }
+#pragma unroll
+    for (int t = 0; t < kSelTiles; ++t) {
+      if (static_cast<uint32_t>(t) < ntl) {
+        const uint32_t I = t >= 6 ? 3 : (t >= 3 ? 2 : (t >= 1 ? 1 : 0));
+        const uint32_t J = static_cast<uint32_t>(t) - I * (I + 1) / 2;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
           const uint32_t i = 16 * I + 4 * (lane / 16) + r, j = 16 * J + lane % 16;
           if (i < cnt && j < i && tv[i] != 1u) {
             float dt, err;
-            screen_estimate(acc[r], nrm[i], nrm[j], qe[i], qe[j], gam, a.metric, &dt, &err);
+            screen_estimate(acc[t][r], nrm[i], nrm[j], qe[i], qe[j], gam, a.metric, &dt, &err);
             const float dup = vd[i];
             if (dt + err < dup) atomicOr(reinterpret_cast<unsigned long long*>(&occl[i]), 1ull << j);
             else if (!(dt - err > dup)) atomicOr(reinterpret_cast<unsigned long long*>(&unc[i]), 1ull << j);
@@ -399,7 +419,7 @@ fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32
                 nullptr, nullptr, 0, 0};
   const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));
   const uint32_t dpad = (d->dim + 31) / 32 * 32;
-  const bool use_mfma = k <= kSelMfmaMaxK && dpad <= kSelMfmaMaxDpad && !(p->flags & FGIM_FLAG_NO_MFMA_SCREEN);
+  const bool use_mfma = k <= kSelMfmaMaxK && !(p->flags & FGIM_FLAG_NO_MFMA_SCREEN);
   if (use_mfma) {
     float *nrm2 = nullptr, *qerr2 = nullptr;
     FGIM_TRY(scr.get(&nrm2, N));
@@ -409,7 +429,8 @@ fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32
     sa.qerr2 = qerr2;
     sa.dpad = dpad;
     const uint32_t kpad = (static_cast<uint32_t>(k) + 15) & ~15u;
-    sa.wave_smem = static_cast<uint32_t>(kSelMfmaHead + static_cast<size_t>(kpad) * (dpad + 8) * 2);
+    const uint32_t slice = std::min(dpad, kSelMfmaSlice);
+    sa.wave_smem = static_cast<uint32_t>(kSelMfmaHead + static_cast<size_t>(kpad) * (slice + 8) * 2);
     const size_t msmem = 2 * static_cast<size_t>(sa.wave_smem);
     const uint32_t mgrid = static_cast<uint32_t>(std::min<uint64_t>((N + 1) / 2, static_cast<uint64_t>(device_cus()) * 16));
     auto kern = M <= 4 ? select_mfma_kernel<4> : select_mfma_kernel<16>;
