@@ -77,6 +77,13 @@ FGIM_DEV uint64_t readlane64(uint64_t v, int l) {
 
 FGIM_DEV uint32_t uniform(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
+// orders this wavefront's LDS writes before its later LDS reads (lanes of
+// one wavefront exchanging data through LDS)
+FGIM_DEV void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 FGIM_DEV float shfl_xor_f(float v, int m) { return __shfl_xor(v, m, kWave); }
 
 FGIM_DEV uint32_t shfl_u(uint32_t v, int src) { return __shfl(v, src, kWave); }

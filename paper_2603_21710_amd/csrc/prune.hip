@@ -137,11 +137,6 @@ constexpr uint32_t kSelMfmaSlice = 256;  // dimensions staged in LDS at a time
 constexpr int kSelTiles = 10;            // lower-triangle 16 x 16 tiles for 64 rows
 constexpr size_t kSelMfmaHead = 64 * 8 * 2 + 64 * 4 * 2 + 68 * 4 + 64 * 4 * 3;
 
-FGIM_DEV void wave_lds_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-}
-
 FGIM_DEV uint32_t select_bit64(uint64_t m, uint32_t r) {
   uint32_t pos = 0;
 #pragma unroll

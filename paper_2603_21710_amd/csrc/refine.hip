@@ -532,81 +532,106 @@ FGIM_DEV uint32_t select_bit(uint64_t m0, uint64_t m1, uint32_t r) {
   return pos;
 }
 
-// Visit for the MFMA join, one vertex u per two-wave workgroup: Cn(u) =
-// the new forward entries and the k_rev closest new reverse entries, Co(u)
-// = the old ones not in Cn, each unique and ascending (ascending ids group
-// by sub-index); written to a.cand / a.ccnt with u's own screen data.
-__global__ void __launch_bounds__(128) cand_kernel(JoinArgs a) {
-  __shared__ uint32_t arr_n[kMfmaMaxC], arr_o[kMfmaMaxC], cid[kMfmaMaxC];
-  __shared__ uint32_t counters[4];
+// bitonic sort of 64 uint32 values, one per lane, ascending
+FGIM_DEV uint32_t wave_sort64(uint32_t v) {
+  const uint32_t lane = static_cast<uint32_t>(lane_id());
+#pragma unroll
+  for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      const uint32_t o = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v), static_cast<int>(j), 64));
+      const bool lower = (lane & j) == 0;
+      const bool asc = (lane & k) == 0;
+      v = (lower == asc) ? min(v, o) : max(v, o);
+    }
+  }
+  return v;
+}
+
+// the unique non-NONE values of the sorted wave (one per lane) written to
+// out in order; returns their count (wave-uniform)
+FGIM_DEV uint32_t wave_unique64(uint32_t v, uint32_t* out) {
+  const uint32_t prev = static_cast<uint32_t>(__shfl(static_cast<int>(v), lane_id() == 0 ? 0 : lane_id() - 1, 64));
+  const bool keep = v != kNone && (lane_id() == 0 || v != prev);
+  const uint64_t m = ballot(keep);
+  if (keep) out[mbcnt(m)] = v;
+  return static_cast<uint32_t>(popc64(m));
+}
+
+// Visit for the MFMA join, one vertex u per wavefront (four independent
+// wavefronts per workgroup): Cn(u) = the new forward entries and the k_rev
+// closest new reverse entries, Co(u) = the old ones not in Cn, each unique
+// and ascending (ascending ids group by sub-index); written to a.cand /
+// a.ccnt with u's own screen data.  k + k_rev <= 64, so each set fits one
+// value per lane.
+__global__ void __launch_bounds__(256) cand_kernel(JoinArgs a) {
+  __shared__ uint32_t s_n[4][kMfmaMaxCn], s_o[4][kMfmaMaxCn], s_c[4][kMfmaMaxC];
+  __shared__ uint32_t s_cnt[4][2];
   const int wave = threadIdx.x / 64;
   const int lane = lane_id();
+  uint32_t* arr_n = s_n[wave];
+  uint32_t* arr_o = s_o[wave];
+  uint32_t* cid = s_c[wave];
+  uint32_t* cnt = s_cnt[wave];
   const float gam = fp32_gamma(a.dim);
-  for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
-    if (threadIdx.x < 4) counters[threadIdx.x] = 0;
-    arr_n[threadIdx.x] = kNone;
-    arr_o[threadIdx.x] = kNone;
-    if (threadIdx.x == 0) {
+  for (uint64_t u = blockIdx.x * 4ull + wave; u < a.N; u += gridDim.x * 4ull) {
+    // forward entries, split by flag
+    const bool in = static_cast<uint32_t>(lane) < a.k;
+    const uint64_t kk = in ? a.keys[u * a.k + lane] : kSentinel;
+    const bool valid = kk != kSentinel;
+    const bool isnew = valid && (a.flags[u * a.k + lane] & kFlagNew);
+    const uint64_t mn = ballot(isnew), mo = ballot(valid && !isnew);
+    if (isnew) arr_n[mbcnt(mn)] = key_id(kk);
+    if (valid && !isnew) arr_o[mbcnt(mo)] = key_id(kk);
+    if (lane == 0) {
+      cnt[0] = static_cast<uint32_t>(popc64(mn));
+      cnt[1] = static_cast<uint32_t>(popc64(mo));
+    }
+    const uint64_t wk = readlane64(kk, static_cast<int>(a.k - 1));
+    if (lane == 0) {
       CandAux x;
-      x.worst = a.keys[u * a.k + a.k - 1];
+      x.worst = wk;
       x.nrm2 = a.nrm2[u];
       x.qerr = sqrtf(a.qerr2[u]) * (1.0f + gam) * 1.0001f;
       a.aux[u] = x;
     }
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < a.k; t += 128) {
-      const uint64_t kk = a.keys[u * a.k + t];
-      if (kk == kSentinel) continue;
-      if (a.flags[u * a.k + t] & kFlagNew) arr_n[atomicAdd(&counters[0], 1u)] = key_id(kk);
-      else arr_o[atomicAdd(&counters[1], 1u)] = key_id(kk);
-    }
-    {
-      const uint64_t seg = 2u * u + static_cast<uint64_t>(wave);
-      const uint32_t b0 = a.rev_off[seg], b1 = a.rev_off[seg + 1];
-      rev_top<1>(a.rev + b0, b1 - b0, a.k_rev, wave == 0 ? arr_n : arr_o, &counters[wave]);
-    }
-    __syncthreads();
-    {
-      uint32_t* src = wave == 0 ? arr_n : arr_o;
-      uint32_t v0 = src[lane], v1 = src[64 + lane];
-      wave_sort128(v0, v1);
-      const uint32_t n = wave_unique128(v0, v1, wave == 0 ? cid : arr_o);
-      if (lane == 0) counters[2 + wave] = n;
-    }
-    __syncthreads();
-    const uint32_t nn = counters[2], no0 = counters[3];
-    // Co: unique old ids not in Cn (binary search in the sorted Cn)
-    if (wave == 1) {
-      const uint32_t v0 = static_cast<uint32_t>(lane) < no0 ? arr_o[lane] : kNone;
-      const uint32_t v1 = 64u + lane < no0 ? arr_o[64 + lane] : kNone;
-      bool k0 = v0 != kNone, k1 = v1 != kNone;
+    wave_lds_sync();
+    // the k_rev closest reverse entries of each kind
 #pragma unroll
-      for (int r = 0; r < 2; ++r) {
-        const uint32_t v = r ? v1 : v0;
-        uint32_t lo = 0, hi = nn;
-        while (lo < hi) {
-          const uint32_t mid = (lo + hi) / 2;
-          if (cid[mid] < v) lo = mid + 1;
-          else hi = mid;
-        }
-        const bool in_cn = lo < nn && cid[lo] == v;
-        if (r) k1 = k1 && !in_cn;
-        else k0 = k0 && !in_cn;
+    for (int kind = 0; kind < 2; ++kind) {
+      const uint64_t seg = 2u * u + static_cast<uint64_t>(kind);
+      const uint32_t b0 = a.rev_off[seg], b1 = a.rev_off[seg + 1];
+      rev_top<1>(a.rev + b0, b1 - b0, a.k_rev, kind == 0 ? arr_n : arr_o, &cnt[kind]);
+      wave_lds_sync();
+    }
+    // Cn: sorted unique new ids
+    const uint32_t cn = cnt[0], co = cnt[1];
+    const uint32_t vn = wave_sort64(static_cast<uint32_t>(lane) < cn ? arr_n[lane] : kNone);
+    const uint32_t nn = wave_unique64(vn, cid);
+    // Co: sorted unique old ids that are not in Cn
+    const uint32_t vo = wave_sort64(static_cast<uint32_t>(lane) < co ? arr_o[lane] : kNone);
+    wave_lds_sync();
+    const uint32_t prev = static_cast<uint32_t>(__shfl(static_cast<int>(vo), lane == 0 ? 0 : lane - 1, 64));
+    bool keep = vo != kNone && (lane == 0 || vo != prev);
+    if (keep) {
+      uint32_t lo = 0, hi = nn;
+      while (lo < hi) {
+        const uint32_t mid = (lo + hi) / 2;
+        if (cid[mid] < vo) lo = mid + 1;
+        else hi = mid;
       }
-      const uint64_t m0 = ballot(k0), m1 = ballot(k1);
-      const uint32_t n0 = static_cast<uint32_t>(popc64(m0));
-      if (k0) cid[nn + mbcnt(m0)] = v0;
-      if (k1) cid[nn + n0 + mbcnt(m1)] = v1;
-      if (lane == 0) counters[3] = n0 + static_cast<uint32_t>(popc64(m1));
+      keep = !(lo < nn && cid[lo] == vo);
     }
-    __syncthreads();
-    const uint32_t c = nn + counters[3];
-    for (uint32_t i = threadIdx.x; i < c; i += 128) a.cand[u * kMfmaMaxC + i] = cid[i];
-    if (threadIdx.x == 0) {
+    const uint64_t mk = ballot(keep);
+    if (keep) cid[nn + mbcnt(mk)] = vo;
+    const uint32_t no = static_cast<uint32_t>(popc64(mk));
+    wave_lds_sync();
+    for (uint32_t i = lane; i < nn + no; i += 64) a.cand[u * kMfmaMaxC + i] = cid[i];
+    if (lane == 0) {
       a.ccnt[2 * u] = nn;
-      a.ccnt[2 * u + 1] = counters[3];
+      a.ccnt[2 * u + 1] = no;
     }
-    __syncthreads();
+    wave_lds_sync();
   }
 }
 
@@ -1352,7 +1377,7 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
   if (rp.use_mfma) {
     if ((e = fill_u32(rp.ja.npairs, 0u, 1, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(cand_kernel, dim3(rp.cand_grid), dim3(128), 0, s, rp.ja);
+    hipLaunchKernelGGL(cand_kernel, dim3(rp.cand_grid), dim3(256), 0, s, rp.ja);
     hipLaunchKernelGGL(join_mfma_kernel, dim3(rp.join_grid), dim3(256), rp.join_smem, s, rp.ja);
     if (rp.mmax == 4)
       hipLaunchKernelGGL(recheck_kernel<4>, dim3(rp.recheck_grid), dim3(256), 0, s, rp.ja);
@@ -1523,7 +1548,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     rp.use_mfma = use_mfma;
     rp.join_smem = use_mfma ? mfma_smem : base_smem + (stage_rows ? rows_smem : 0);
     rp.join_grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));
-    rp.cand_grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 16));
+    rp.cand_grid = static_cast<uint32_t>(std::min<uint64_t>((N + 3) / 4, static_cast<uint64_t>(device_cus()) * 16));
     rp.recheck_grid = static_cast<uint32_t>(device_cus()) * 8;
     if (use_mfma && rp.join_smem > 64 * 1024)
       HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(join_mfma_kernel),
