@@ -653,20 +653,37 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
   uint32_t nrech = 0;  // pairs passing the screen (thread 0)
   if (threadIdx.x >= 8 && threadIdx.x < 16) counters[threadIdx.x] = 0;
 
+  // The next vertex's candidate ids load while the current one is screened,
+  // and their screen records after its MFMA tiles: thread t < 128 holds
+  // candidate t.
+  uint32_t pf_n = 0, pf_o = 0, pf_v = kNone;
+  CandAux pf_x{};
+  auto fetch_ids = [&](uint64_t w) {
+    if (w < a.N) {
+      pf_n = a.ccnt[2 * w];
+      pf_o = a.ccnt[2 * w + 1];
+      pf_v = threadIdx.x < kMfmaMaxC ? a.cand[w * kMfmaMaxC + threadIdx.x] : kNone;
+    }
+  };
+  auto fetch_aux = [&]() {
+    if (threadIdx.x < pf_n + pf_o) pf_x = a.aux[pf_v];
+  };
+  fetch_ids(blockIdx.x);
+  fetch_aux();
+
   for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
     if (threadIdx.x < 8) counters[threadIdx.x] = 0;
     if (threadIdx.x < kMfmaMaxC) pmask[threadIdx.x] = 0;
-    const uint32_t nn = a.ccnt[2 * u], no = a.ccnt[2 * u + 1];
+    const uint32_t nn = uniform(pf_n), no = uniform(pf_o);
     const uint32_t c = nn + no;
-    for (uint32_t i = threadIdx.x; i < c; i += 256) {
-      const uint32_t v = a.cand[u * kMfmaMaxC + i];
-      const CandAux x = a.aux[v];
-      cid[i] = v;
-      cg[i] = sub_of(a.sub_off, a.h, v);
-      cw[i] = x.worst;
-      cnrm[i] = x.nrm2;
-      cqe[i] = x.qerr;
+    if (threadIdx.x < c) {
+      cid[threadIdx.x] = pf_v;
+      cg[threadIdx.x] = sub_of(a.sub_off, a.h, pf_v);
+      cw[threadIdx.x] = pf_x.worst;
+      cnrm[threadIdx.x] = pf_x.nrm2;
+      cqe[threadIdx.x] = pf_x.qerr;
     }
+    fetch_ids(u + gridDim.x);
     __syncthreads();
     const uint32_t nI = (nn + 15) / 16, nC = (c + 15) / 16;
     uint32_t T = 0;
@@ -718,6 +735,7 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
         }
       }
     }
+    fetch_aux();
     // Screen (screen_estimate): a pair passes when its estimate minus the
     // bound could still beat the worst entry of either end.
 #pragma unroll
