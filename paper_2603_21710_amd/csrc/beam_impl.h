@@ -181,7 +181,7 @@ FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, cons
                           const BeamArgs& a, const WaveLds& lds, int m) {
   // group batches in flight: two for FP32 rows, else as many as about 32
   // registers of raw (BF16 / FP8) row data per lane hold, at most four
-  // (measured on d = 128 and d = 768)
+  // (eight measured slower on d = 128 and d = 768)
   constexpr int kRawRegs = static_cast<int>(sizeof(typename Row::Raw) / 4);
   constexpr int kLowP = 32 / (MMAX * kRawRegs) < 4 ? 32 / (MMAX * kRawRegs) : 4;
   constexpr int U = MMAX > 4 ? 1 : (kRawRegs == 4 ? 2 : kLowP);

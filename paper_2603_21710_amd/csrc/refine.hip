@@ -144,16 +144,6 @@ __global__ void copy_u32_kernel(const uint32_t* a, uint32_t* b, uint64_t n) {
 // ---------------------------------------------------------------------------
 // Visit: reverse lists
 
-__global__ void rev_count_kernel(const uint64_t* keys, const uint32_t* flags, uint64_t nk, uint32_t* cnt) {
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t k = keys[i];
-    if (k == kSentinel) continue;
-    const uint32_t seg = 2u * key_id(k) + ((flags[i] & kFlagNew) ? 0u : 1u);
-    atomicAdd(&cnt[seg], 1u);
-  }
-}
-
 // reverse entry of v in u's list: key (stored delta, u)
 __global__ void rev_scatter_kernel(const uint64_t* keys, const uint32_t* flags, uint64_t nk, uint32_t k,
                                    uint32_t* cur, uint64_t* rev) {
@@ -899,11 +889,14 @@ __global__ void prop_scatter_kernel(const uint32_t* ptgt, const uint64_t* pkey, 
 }
 
 // first k of snapshot (old) U proposals (new), one entry per id; every
-// list's new entries turn old
+// list's new entries turn old.  The indegrees T and the counts of new
+// in-edges follow the change: a dropped old entry lowers T, an accepted
+// proposal raises T and the new count (newc is zero on entry).
 template <int NR>
 __global__ void __launch_bounds__(256) apply_kernel(uint64_t* keys, uint32_t* flags, uint64_t N, uint32_t k,
                                                     const uint32_t* poff, const uint64_t* sorted,
-                                                    uint32_t* ptotal_max, const uint32_t* ptotal) {
+                                                    uint32_t* ptotal_max, const uint32_t* ptotal, uint32_t* T,
+                                                    uint32_t* newc) {
   const uint64_t wave = blockIdx.x * 4ull + threadIdx.x / 64;
   const uint64_t nw = gridDim.x * 4ull;
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -918,10 +911,25 @@ __global__ void __launch_bounds__(256) apply_kernel(uint64_t* keys, uint32_t* fl
       list.key[r] = e < k ? keys[a * k + e] : kSentinel;
     }
     list.exp = 0;
+    uint64_t old[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) old[r] = list.key[r];
     const uint32_t b0 = poff[a], b1 = poff[a + 1];
     for (uint32_t b = b0; b < b1; b += 64) {
       const uint64_t ck = b + lane_id() < b1 ? sorted[b + lane_id()] : kSentinel;
       list.insert_batch(ck, k, 1u);
+    }
+    if (b1 > b0) {
+      // an old entry is kept iff it is not beyond the new last entry
+      const uint64_t last = list.theta(k);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (old[r] != kSentinel && old[r] > last) atomicSub(&T[key_id(old[r])], 1u);
+        if ((list.exp >> r) & 1u) {
+          atomicAdd(&T[key_id(list.key[r])], 1u);
+          atomicAdd(&newc[key_id(list.key[r])], 1u);
+        }
+      }
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -931,6 +939,17 @@ __global__ void __launch_bounds__(256) apply_kernel(uint64_t* keys, uint32_t* fl
         flags[a * k + e] = (list.exp >> r) & 1u;
       }
     }
+  }
+}
+
+// reverse-list segment sizes of the next Visit from the maintained counts:
+// 2v holds v's new in-edges, 2v+1 its old ones
+__global__ void rev_sizes_kernel(const uint32_t* T, const uint32_t* newc, uint64_t N, uint32_t* cnt) {
+  for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < N;
+       v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint32_t n = newc[v];
+    cnt[2 * v] = n;
+    cnt[2 * v + 1] = T[v] - n;
   }
 }
 
@@ -1053,8 +1072,8 @@ FGIM_DEV Attempt<NR> try_neighbour(const uint64_t* keys, const uint32_t* flags, 
 // update the indegrees (no other step of a committed prefix touches T of
 // the evicted entry, so its indegree as read is still current)
 template <int NR>
-FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, const Attempt<NR>& at, uint32_t v,
-                             uint32_t vs, uint64_t nk, uint32_t k) {
+FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, uint32_t* newc, const Attempt<NR>& at,
+                             uint32_t v, uint32_t vs, uint64_t nk, uint32_t k) {
   int pos = 0;
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
@@ -1062,11 +1081,17 @@ FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, const
     pos += popc64(ballot(e != at.drop && at.lk[r] < nk));
   }
   uint64_t dk = kSentinel;
+  uint32_t df = 0;
 #pragma unroll
   for (int r = 0; r < NR; ++r)
-    if (at.drop >= 0 && r == at.drop / 64) dk = readlane64(at.lk[r], at.drop % 64);
-  if (at.drop >= 0 && lane_id() == 0)
+    if (at.drop >= 0 && r == at.drop / 64) {
+      dk = readlane64(at.lk[r], at.drop % 64);
+      df = readlane(at.lf[r], at.drop % 64);
+    }
+  if (at.drop >= 0 && lane_id() == 0) {
     __hip_atomic_store(&T[key_id(dk)], at.tdrop - 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (newc && (df & kFlagNew)) atomicSub(&newc[key_id(dk)], 1u);
+  }
 #pragma unroll
   for (int r = 0; r < NR; ++r) {
     const int e = r * 64 + lane_id();
@@ -1082,6 +1107,7 @@ FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, const
     keys[static_cast<uint64_t>(v) * k + pos] = nk;
     flags[static_cast<uint64_t>(v) * k + pos] = kFlagNew | kFlagReplaced;
     __hip_atomic_store(&T[vs], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (newc) newc[vs] = 1u;  // its one in-edge, flagged new
   }
 }
 
@@ -1136,8 +1162,9 @@ FGIM_DEV uint32_t first_write(const uint64_t* tab, uint32_t id) {
 
 template <int NR>
 __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* keys, uint32_t* flags, uint32_t* T,
-                                                                   const uint32_t* zero, const uint64_t* zkey,
-                                                                   const uint32_t* zcount, uint32_t k, uint32_t* nrep) {
+                                                                   uint32_t* newc, const uint32_t* zero,
+                                                                   const uint64_t* zkey, const uint32_t* zcount,
+                                                                   uint32_t k, uint32_t* nrep) {
   // nrep[0]: vertices repaired, nrep[3]: batches, nrep[4]: steps run alone
   constexpr int S = RepairShape<NR>::kSteps;
   constexpr uint32_t B = RepairShape<NR>::kBatch;
@@ -1260,7 +1287,7 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
     for (int s = 0; s < S; ++s) {
       const uint32_t i = s * kRepairWaves + w;
       if (i < pend && at[s].ok) {
-        commit_attempt<NR>(keys, flags, T, at[s], v[s], vs[s], nk[s], k);
+        commit_attempt<NR>(keys, flags, T, newc, at[s], v[s], vs[s], nk[s], k);
         ++fixed;
       }
     }
@@ -1276,7 +1303,7 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
           const uint32_t vt = key_id(ks);
           const Attempt<NR> a1 = try_neighbour<NR>(keys, flags, T, vt, k);
           if (a1.ok) {
-            commit_attempt<NR>(keys, flags, T, a1, vt, vs[0], (ks & 0xFFFFFFFF00000000ull) | vs[0], k);
+            commit_attempt<NR>(keys, flags, T, newc, a1, vt, vs[0], (ks & 0xFFFFFFFF00000000ull) | vs[0], k);
             ++fixed;
             break;
           }
@@ -1325,6 +1352,7 @@ struct RefineBufs {
   uint32_t* zoff;
   uint32_t* zero;
   uint64_t* zkey;
+  uint32_t* newc;  // per vertex: in-edges flagged new (nullable outside refinement)
   uint32_t* hdr;  // [0] proposals this round, [1] max per round, [2] repaired, [3] sum
   uint32_t* scan_tmp;
   uint64_t* sub_off;
@@ -1360,23 +1388,29 @@ struct RoundPlan {
   bool use_mfma;
 };
 
-// indegrees T of the lists in b.keys, then Algorithm 4 (count of repaired
-// vertices added to b.hdr[2])
-hipError_t launch_repair(const RefineBufs& b, uint64_t N, uint32_t k, hipStream_t s) {
+// indegrees T of the lists in b.keys
+hipError_t launch_indegree(const RefineBufs& b, uint64_t N, uint32_t k, hipStream_t s) {
   const uint64_t nk = N * k;
   hipError_t e;
   if ((e = fill_u32(b.T, 0u, N, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, b.T);
+  return hipGetLastError();
+}
+
+// Algorithm 4 on the lists in b.keys with their indegrees in b.T (kept
+// current, with b.newc when set); repaired count added to b.hdr[2]
+hipError_t launch_repair(const RefineBufs& b, uint64_t N, uint32_t k, hipStream_t s) {
+  hipError_t e;
   hipLaunchKernelGGL(zero_mask_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, N, b.zmask);
   if ((e = exclusive_scan(b.zmask, b.zoff, N, b.scan_tmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(zero_compact_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.zmask, b.zoff, N, b.keys, k, b.zero,
                      b.zkey);
   if (k <= 64)
-    hipLaunchKernelGGL(repair_kernel<1>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.zero, b.zkey,
-                       b.zoff + N, k, b.hdr + 2);
+    hipLaunchKernelGGL(repair_kernel<1>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.newc, b.zero,
+                       b.zkey, b.zoff + N, k, b.hdr + 2);
   else
-    hipLaunchKernelGGL(repair_kernel<2>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.zero, b.zkey,
-                       b.zoff + N, k, b.hdr + 2);
+    hipLaunchKernelGGL(repair_kernel<2>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.newc, b.zero,
+                       b.zkey, b.zoff + N, k, b.hdr + 2);
   return hipGetLastError();
 }
 
@@ -1384,10 +1418,11 @@ hipError_t launch_repair(const RefineBufs& b, uint64_t N, uint32_t k, hipStream_
 hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   const uint64_t N = rp.N, nk = N * rp.k;
   hipError_t e;
-  // Visit
-  if ((e = fill_u32(b.rev_cnt, 0u, 2 * N, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(rev_count_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, b.rev_cnt);
+  // Visit: reverse-list sizes from the maintained indegrees (T) and new
+  // in-edge counts, then the reverse CSR
+  hipLaunchKernelGGL(rev_sizes_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, b.newc, N, b.rev_cnt);
   if ((e = exclusive_scan(b.rev_cnt, b.rev_off, 2 * N, b.scan_tmp, s)) != hipSuccess) return e;
+  if ((e = fill_u32(b.newc, 0u, N, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(2 * N)), dim3(256), 0, s, b.rev_off, b.rev_cur, 2 * N);
   hipLaunchKernelGGL(rev_scatter_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, b.rev_cur,
                      b.rev);
@@ -1413,10 +1448,10 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
                      b.psorted);
   if (rp.nr == 1)
     hipLaunchKernelGGL(apply_kernel<1>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, b.poff,
-                       b.psorted, b.hdr + 1, b.hdr);
+                       b.psorted, b.hdr + 1, b.hdr, b.T, b.newc);
   else
     hipLaunchKernelGGL(apply_kernel<2>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, b.poff,
-                       b.psorted, b.hdr + 1, b.hdr);
+                       b.psorted, b.hdr + 1, b.hdr, b.T, b.newc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!rp.repair) return hipSuccess;
   return launch_repair(b, N, rp.k, s);
@@ -1483,6 +1518,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     FGIM_TRY(scr.get(&b.pcur, N + 1));
     FGIM_TRY(scr.get(&b.psorted, cap));
     FGIM_TRY(scr.get(&b.T, N));
+    FGIM_TRY(scr.get(&b.newc, N));
     FGIM_TRY(scr.get(&b.zmask, N + 1));
     FGIM_TRY(scr.get(&b.zoff, N + 1));
     FGIM_TRY(scr.get(&b.zero, N + 1));
@@ -1518,6 +1554,10 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     HIP_TRY(fill_u32(b.hdr, 0u, 16, s));
     hipLaunchKernelGGL(to_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, ids, dist, nk, b.keys, b.flags);
     HIP_TRY(hipGetLastError());
+    // indegrees of the input lists, all of whose entries are new; apply and
+    // repair keep both counts current from here on
+    HIP_TRY(launch_indegree(b, N, p->k, s));
+    HIP_TRY(hipMemcpyAsync(b.newc, b.T, 4 * N, hipMemcpyDeviceToDevice, s));
 
     RoundPlan rp{};
     rp.N = N;
@@ -1616,11 +1656,6 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     } else {
       for (uint32_t r = 0; r < p->rounds; ++r) HIP_TRY(run_round(rp, b, s));
     }
-    if (!repair || p->rounds == 0) {
-      HIP_TRY(fill_u32(b.T, 0u, N, s));
-      hipLaunchKernelGGL(indegree_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, b.T);
-      HIP_TRY(hipGetLastError());
-    }
     uint32_t hh[16] = {};
     HIP_TRY(hipMemcpyAsync(hh, b.hdr, sizeof(hh), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -1685,6 +1720,7 @@ fgim_status repair_impl(uint32_t* ids, float* dist, uint64_t N, uint32_t k, uint
   if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n");
   hipLaunchKernelGGL(to_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, ids, dist, nk, b.keys, b.flags);
   HIP_TRY(hipGetLastError());
+  HIP_TRY(launch_indegree(b, N, k, s));
   HIP_TRY(launch_repair(b, N, k, s));
   hipLaunchKernelGGL(from_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, ids, dist);
   HIP_TRY(hipGetLastError());
