@@ -132,25 +132,6 @@ FGIM_DEV float finish(float r) {
   return d + 0.0f;
 }
 
-// in-lane stride tree over M chunk sums (strides M/2 ... 1)
-template <int M>
-FGIM_DEV float lane_tree(float (&s)[M]) {
-#pragma unroll
-  for (int st = M / 2; st >= 1; st /= 2) {
-#pragma unroll
-    for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
-  }
-  return s[0];
-}
-
-// cross-lane strides P/2 ... 1
-template <int P>
-FGIM_DEV float group_tree(float r) {
-#pragma unroll
-  for (int st = P / 2; st >= 1; st /= 2) r = r + shfl_xor_f(r, st);
-  return r;
-}
-
 // ---------------------------------------------------------------------------
 // row formats
 

@@ -2,22 +2,27 @@
 // synchronous rounds, with indegree repair (Algorithm 4) after every round.
 //
 // Lists are held as sorted uint64 keys (delta, id) plus a flag word per slot
-// (bit 0 new, bit 1 replaced).  One round is a fixed sequence of kernels
-// with no host round trip, so it can be captured once in a hipGraph and
-// replayed:
-//   Visit   rev_count / scan / rev_scatter: reverse lists of new and old
-//           entries as a CSR (segment 2v: u with v new in u's list, 2v+1: old)
-//   Update  join: one workgroup per vertex u builds Cn(u) = fwd_new U
-//           rev_new and Co(u) = (fwd_old U rev_old) \ Cn (reverse lists cut
-//           to their k_rev best by (delta, u)), stages the candidate rows in
-//           LDS and scores every cross-sub-index pair of Cn^2 U Cn x Co in
-//           canonical FP32; a pair proposes each end to the other when it
-//           beats that end's current worst entry.  Proposals are appended to
-//           a global buffer and grouped by target with a CSR pass.
+// (bit 0 new, bit 1 replaced); the indegrees T and the counts of new
+// in-edges are kept current by apply and repair.  One round is a fixed
+// sequence of kernels with no host round trip, so it is captured once in a
+// hipGraph and replayed:
+//   Visit   reverse-list sizes from the maintained counts, scan, rev_scatter:
+//           reverse lists of new and old entries as a CSR (segment 2v: u
+//           with v new in u's list, 2v+1: old)
+//   Update  Cn(u) = fwd_new U rev_new and Co(u) = (fwd_old U rev_old) \ Cn,
+//           reverse lists cut to their k_rev best by (delta, u); every
+//           cross-sub-index pair of Cn^2 U Cn x Co proposes each end to the
+//           other when it beats that end's current worst entry.  When
+//           |Cn| + |Co| <= 128: cand_kernel builds the sets, join_mfma_kernel
+//           screens the pairs on MFMA with a rigorous error bound and
+//           recheck_kernel scores the survivors in canonical FP32; otherwise
+//           join_kernel scores every pair in FP32 from rows staged in LDS.
+//           Proposals are appended to a global buffer and grouped by target
+//           with a CSR pass.
 //   apply   per target: first k of the snapshot list (entries turn old) and
 //           its proposals (entries new), one entry per id.
-//   repair  indegree histogram, ordered list of zero-indegree vertices, then
-//           Algorithm 4 in one wavefront (it is sequential by definition).
+//   repair  ordered list of zero-indegree vertices, then Algorithm 4 in one
+//           workgroup in order-exact speculative batches.
 // Every step's result is independent of scheduling: CSR segments are
 // consumed through order-independent top-k selections under the total
 // order of keys, so the output is bit-identical to the sequential oracle.
@@ -435,62 +440,6 @@ hipError_t launch_row_norms(const float* X, uint64_t n, uint32_t dim, uint64_t l
   hipLaunchKernelGGL(row_norms_kernel, dim3(static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(b, 1), 65536))),
                      dim3(256), 0, s, X, n, dim, ld, nrm2, qerr2);
   return hipGetLastError();
-}
-
-// bitonic sort of up to 128 uint32 values held two per lane (element
-// e = r * 64 + lane), ascending
-FGIM_DEV void wave_sort128(uint32_t& v0, uint32_t& v1) {
-  const uint32_t lane = static_cast<uint32_t>(lane_id());
-#pragma unroll
-  for (uint32_t k = 2; k <= 128; k <<= 1) {
-#pragma unroll
-    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
-      if (j == 64) {
-        const uint32_t lo = min(v0, v1), hi = max(v0, v1);
-        v0 = lo;
-        v1 = hi;
-      } else {
-        const uint32_t o0 = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v0), static_cast<int>(j), 64));
-        const uint32_t o1 = static_cast<uint32_t>(__shfl_xor(static_cast<int>(v1), static_cast<int>(j), 64));
-        const bool lower = (lane & j) == 0;
-        const bool asc0 = (lane & k) == 0;
-        const bool asc1 = ((64u + lane) & k) == 0;
-        v0 = (lower == asc0) ? min(v0, o0) : max(v0, o0);
-        v1 = (lower == asc1) ? min(v1, o1) : max(v1, o1);
-      }
-    }
-  }
-}
-
-// unique non-NONE values of the sorted pair (v0, v1) appended to out in
-// order; returns the count (wave-uniform)
-FGIM_DEV uint32_t wave_unique128(uint32_t v0, uint32_t v1, uint32_t* out) {
-  const uint32_t prev0 = static_cast<uint32_t>(__shfl(static_cast<int>(v0), lane_id() == 0 ? 0 : lane_id() - 1, 64));
-  const uint32_t last0 = readlane(v0, 63);
-  const uint32_t prev1 = static_cast<uint32_t>(__shfl(static_cast<int>(v1), lane_id() == 0 ? 0 : lane_id() - 1, 64));
-  const bool k0 = v0 != kNone && (lane_id() == 0 || v0 != prev0);
-  const bool k1 = v1 != kNone && v1 != (lane_id() == 0 ? last0 : prev1);
-  const uint64_t m0 = ballot(k0), m1 = ballot(k1);
-  const uint32_t n0 = static_cast<uint32_t>(popc64(m0));
-  if (k0) out[mbcnt(m0)] = v0;
-  if (k1) out[n0 + mbcnt(m1)] = v1;
-  return n0 + static_cast<uint32_t>(popc64(m1));
-}
-
-FGIM_DEV void emit_proposal(const JoinArgs& a, bool emit, uint32_t tgt, uint64_t key) {
-  const uint64_t m = ballot(emit);
-  if (!m) return;
-  const int leader = ffs64(m);
-  uint32_t base = 0;
-  if (lane_id() == leader) base = atomicAdd(a.ptotal, static_cast<uint32_t>(popc64(m)));
-  base = readlane(base, leader);
-  if (emit) {
-    const uint32_t pos = base + static_cast<uint32_t>(mbcnt(m));
-    if (pos < a.cap) {
-      a.ptgt[pos] = tgt;
-      a.pkey[pos] = key;
-    }
-  }
 }
 
 constexpr uint32_t kMfmaMaxC = 128;       // candidates per vertex on the MFMA path
