@@ -1061,7 +1061,7 @@ FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, uint3
 }
 
 constexpr int kRepairWaves = 16;
-constexpr int kRepairHash = 2048;  // slots per table (a batch notes at most 128 ids in each)
+constexpr int kRepairHash = 2048;  // slots per table (a batch notes at most 256 ids in each)
 constexpr uint32_t kTail = 4;      // list entries whose indegree a first attempt reads
 
 template <int NR>
@@ -1280,6 +1280,204 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
   }
 }
 
+// Algorithm 4 for lists of at most 32 entries.  Each wavefront slot holds two
+// steps, one per half-wave (lanes 0-31 and 32-63, lane e of a half holding
+// entry e of that step's neighbour list), so a batch covers kHalfBatch = 256
+// steps with about the registers repair_kernel needs for 128.  The batch
+// protocol is repair_kernel's: every step's first attempt against the state
+// at the batch start, the two LDS tables of first writers, the longest
+// conflict-free prefix, and a step whose first attempt fails run alone.
+constexpr int kHalfSlots = 8;
+constexpr uint32_t kHalfBatch = 2u * kHalfSlots * kRepairWaves;
+
+// the attempt of each half's step from its list (lk, lf) and indegrees tv
+FGIM_DEV void decide_half(uint64_t lk, uint32_t lf, uint32_t tv, uint32_t k, uint32_t hf, int& drop, bool& ok) {
+  const uint32_t e = static_cast<uint32_t>(lane_id()) & 31u;
+  const uint64_t lastk = shfl64(lk, static_cast<int>(hf * 32 + k - 1));
+  const bool cand = e < k && !(lf & kFlagReplaced) && tv > 1u;
+  const uint32_t hm = static_cast<uint32_t>(ballot(cand) >> (32 * hf));
+  drop = -1;
+  ok = true;
+  if (lastk != kSentinel) {
+    drop = hm ? 31 - __clz(static_cast<int>(hm)) : -1;
+    ok = drop >= 0;
+  }
+}
+
+__global__ void __launch_bounds__(64 * kRepairWaves) repair_half_kernel(uint64_t* keys, uint32_t* flags, uint32_t* T,
+                                                                        uint32_t* newc, const uint32_t* zero,
+                                                                        const uint64_t* zkey, const uint32_t* zcount,
+                                                                        uint32_t k, uint32_t* nrep) {
+  constexpr int S = kHalfSlots;
+  constexpr uint32_t B = kHalfBatch;
+  __shared__ uint64_t h_list[kRepairHash];   // lists written
+  __shared__ uint64_t h_evict[kRepairHash];  // indegrees lowered
+  __shared__ uint32_t s_stop[2];
+  const uint32_t w = threadIdx.x / 64;
+  const int lane = lane_id();
+  const uint32_t hf = static_cast<uint32_t>(lane) >> 5;  // half
+  const uint32_t e = static_cast<uint32_t>(lane) & 31u;  // list entry of the half's step
+  const uint64_t hmask = hf ? 0xFFFFFFFF00000000ull : 0x00000000FFFFFFFFull;
+  for (int t = threadIdx.x; t < kRepairHash; t += blockDim.x) {
+    h_list[t] = kEmptySlot;
+    h_evict[t] = kEmptySlot;
+  }
+  if (threadIdx.x < 2) s_stop[threadIdx.x] = kNone;
+  __syncthreads();
+  const uint32_t Z = *zcount;
+  uint32_t fixed = 0, batches = 0, alone = 0;
+  uint32_t parity = 0;
+  // step (2s + hf) * kRepairWaves + w of a batch: slot s, half hf, wave w
+  for (uint32_t base = 0; base < Z; parity ^= 1u) {
+    uint32_t vs[S], v[S], lf[S], tv[S];
+    uint64_t zk[S], nk[S], lk[S];
+    bool has[S], ok[S], full[S];
+    int drop[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t zi = base + (2u * s + hf) * kRepairWaves + w;
+      vs[s] = zi < Z ? zero[zi] : kNone;
+      zk[s] = zi < Z ? zkey[zi] : kSentinel;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      has[s] = zk[s] != kSentinel;
+      v[s] = has[s] ? key_id(zk[s]) : kNone;
+      nk[s] = (zk[s] & 0xFFFFFFFF00000000ull) | vs[s];
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const bool in = has[s] && e < k;
+      lk[s] = in ? ld_wg64(&keys[static_cast<uint64_t>(v[s]) * k + e]) : kSentinel;
+      lf[s] = in ? ld_wg32(&flags[static_cast<uint64_t>(v[s]) * k + e]) : 0u;
+    }
+#pragma unroll
+    for (int s = 0; s < S; ++s)
+      tv[s] = lk[s] != kSentinel && e + kTail >= k ? ld_wg32(&T[key_id(lk[s])]) : 0u;
+    uint32_t my_list = kNone, my_evict = kNone, my_step = 0;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      decide_half(lk[s], lf[s], tv[s], k, hf, drop[s], ok[s]);
+      full[s] = has[s] && !ok[s];
+      if (ballot(full[s])) {
+        // a half whose tail has no qualifying entry reads every indegree
+        if (full[s] && lk[s] != kSentinel) tv[s] = ld_wg32(&T[key_id(lk[s])]);
+        decide_half(lk[s], lf[s], tv[s], k, hf, drop[s], ok[s]);
+      }
+      if (!has[s]) ok[s] = false;
+      const int dl = static_cast<int>(hf * 32) + (drop[s] >= 0 ? drop[s] : 0);
+      const uint32_t ev = ok[s] && drop[s] >= 0 ? key_id(shfl64(lk[s], dl)) : kNone;
+      // lanes 2s+h note step (s, h)'s list, lanes 32+2s+h its evicted entry
+#pragma unroll
+      for (uint32_t h = 0; h < 2; ++h) {
+        const uint32_t vh = readlane(ok[s] ? v[s] : kNone, static_cast<int>(32 * h));
+        const uint32_t eh = readlane(ev, static_cast<int>(32 * h));
+        const uint32_t ih = (2u * s + h) * kRepairWaves + w;
+        if (static_cast<uint32_t>(lane) == 2u * s + h) {
+          my_list = vh;
+          my_step = ih;
+        }
+        if (static_cast<uint32_t>(lane) == 32u + 2u * s + h) {
+          my_evict = eh;
+          my_step = ih;
+        }
+      }
+    }
+    if (my_list != kNone) note_write(h_list, my_list, my_step);
+    if (my_evict != kNone) note_write(h_evict, my_evict, my_step);
+    __syncthreads();
+    if (threadIdx.x == 0) s_stop[parity ^ 1u] = kNone;
+    uint32_t my_stop = kNone;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t i = (2u * s + hf) * kRepairWaves + w;
+      bool stop = has[s] && !ok[s];
+      if (ok[s] && first_write(h_list, v[s]) < i) stop = true;
+      const bool reads_t = ok[s] && drop[s] >= 0;
+      const bool hit = reads_t && lk[s] != kSentinel && (full[s] || e + kTail >= k) &&
+                       first_write(h_evict, key_id(lk[s])) < i;
+      if (ballot(hit) & hmask) stop = true;
+      if (stop && i < my_stop) my_stop = i;
+    }
+#pragma unroll
+    for (int st = 32; st >= 1; st /= 2) {
+      const uint32_t o = static_cast<uint32_t>(__shfl_xor(static_cast<int>(my_stop), st, 64));
+      my_stop = o < my_stop ? o : my_stop;
+    }
+    if (lane == 0 && my_stop != kNone) atomicMin(&s_stop[parity], my_stop);
+    __syncthreads();
+    const uint32_t nb = Z - base < B ? Z - base : B;
+    uint32_t pend = s_stop[parity] < nb ? s_stop[parity] : nb;
+    // commit both halves' steps of each slot at once
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t i = (2u * s + hf) * kRepairWaves + w;
+      const bool commit = i < pend && ok[s];
+      if (!ballot(commit)) continue;
+      const int d = drop[s];
+      const uint32_t pos = static_cast<uint32_t>(
+          popc64(ballot(e < k && static_cast<int>(e) != d && lk[s] < nk[s]) & hmask));
+      const int dl = static_cast<int>(hf * 32) + (d >= 0 ? d : 0);
+      const uint64_t dk = shfl64(lk[s], dl);
+      const uint32_t df = static_cast<uint32_t>(__shfl(static_cast<int>(lf[s]), dl, 64));
+      const uint32_t tdrop = static_cast<uint32_t>(__shfl(static_cast<int>(tv[s]), dl, 64));
+      const uint64_t row = static_cast<uint64_t>(v[s]) * k;
+      if (commit && d >= 0 && e == 0) {
+        __hip_atomic_store(&T[key_id(dk)], tdrop - 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (newc && (df & kFlagNew)) atomicSub(&newc[key_id(dk)], 1u);
+      }
+      if (commit && e < k && static_cast<int>(e) != d && lk[s] != kSentinel) {
+        uint32_t ne = e - (d >= 0 && static_cast<int>(e) > d ? 1u : 0u);
+        if (ne >= pos) ++ne;
+        if (ne < k) {
+          keys[row + ne] = lk[s];
+          flags[row + ne] = lf[s];
+        }
+      }
+      if (commit && e == 0) {
+        keys[row + pos] = nk[s];
+        flags[row + pos] = kFlagNew | kFlagReplaced;
+        __hip_atomic_store(&T[vs[s]], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (newc) newc[vs[s]] = 1u;
+        ++fixed;
+      }
+    }
+    ++batches;
+    if (pend == 0) {
+      // the batch's first step (slot 0, half 0 of wave 0) found no slot in
+      // its closest neighbour's list: it tries the next neighbours alone
+      ++alone;
+      if (w == 0) {
+        const uint32_t v0 = readlane(vs[0], 0);
+        for (uint32_t t = 1; t < k; ++t) {
+          const uint64_t ks = keys[static_cast<uint64_t>(v0) * k + t];
+          if (ks == kSentinel) break;
+          const uint32_t vt = key_id(ks);
+          const Attempt<1> a1 = try_neighbour<1>(keys, flags, T, vt, k);
+          if (a1.ok) {
+            commit_attempt<1>(keys, flags, T, newc, a1, vt, v0, (ks & 0xFFFFFFFF00000000ull) | v0, k);
+            if (lane == 0) ++fixed;
+            break;
+          }
+        }
+      }
+      pend = 1;
+    }
+    for (int t = threadIdx.x; t < kRepairHash; t += blockDim.x) {
+      h_list[t] = kEmptySlot;
+      h_evict[t] = kEmptySlot;
+    }
+    __threadfence_block();
+    __syncthreads();
+    base += pend;
+  }
+  if (e == 0 && fixed) atomicAdd(nrep, fixed);
+  if (threadIdx.x == 0) {
+    atomicAdd(nrep + 3, batches);
+    atomicAdd(nrep + 4, alone);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host driver
 
@@ -1354,7 +1552,10 @@ hipError_t launch_repair(const RefineBufs& b, uint64_t N, uint32_t k, hipStream_
   if ((e = exclusive_scan(b.zmask, b.zoff, N, b.scan_tmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(zero_compact_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.zmask, b.zoff, N, b.keys, k, b.zero,
                      b.zkey);
-  if (k <= 64)
+  if (k <= 32)
+    hipLaunchKernelGGL(repair_half_kernel, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.newc,
+                       b.zero, b.zkey, b.zoff + N, k, b.hdr + 2);
+  else if (k <= 64)
     hipLaunchKernelGGL(repair_kernel<1>, dim3(1), dim3(64 * kRepairWaves), 0, s, b.keys, b.flags, b.T, b.newc, b.zero,
                        b.zkey, b.zoff + N, k, b.hdr + 2);
   else
