@@ -950,25 +950,27 @@ FGIM_DEV uint32_t ld_wg32(const uint32_t* p) {
 // list holds a zero-indegree vertex before its own turn).
 //
 // The pass keeps this sequential order but runs speculatively, in batches of
-// kRepairBatch consecutive steps: every step makes its first attempt (the
-// closest neighbour v) against the current state, all at once; then the
-// batch commits its longest prefix in which no step read a list or an
-// indegree that an earlier step of the batch writes.  A step writes N(v),
-// T(v') of the entry v' it evicts and T(v*); it read N(v) and T of N(v)'s
-// entries (and v*'s own list, which no step changes).  Earlier writes are
-// looked up in two LDS hash tables that map a vertex to the first step of
-// the batch writing its list or lowering its indegree.  A step whose first
-// attempt fails continues alone, as the first step of a batch.  Committed
-// steps therefore see exactly the state of the sequential loop.
+// consecutive steps: every step makes its first attempt (the closest
+// neighbour v) against the state at the batch start, all at once; then the
+// batch commits its longest prefix in which no step read a list that an
+// earlier step of the batch writes, or an indegree that earlier steps may
+// lower to 1 or below.  A step writes N(v), T(v') of the entry v' it evicts
+// (a decrement) and T(v*); it read N(v) and T of N(v)'s entries (and v*'s
+// own list, which no step changes), and of those indegrees only the test
+// "> 1" decides anything.  Earlier writes are looked up in two LDS hash
+// tables that map a vertex to the first step of the batch writing its list
+// or evicting it, the second with the batch's eviction count.  A step whose
+// first attempt fails continues alone, as the first step of a batch.
+// Committed steps therefore take exactly the decisions of the sequential
+// loop, and reach its state.
 
 // state read by one attempt (v = the neighbour of v* tried)
 template <int NR>
 struct Attempt {
   uint64_t lk[NR];
   uint32_t lf[NR];
-  int drop;      // entry to evict, -1 for a free slot
-  uint32_t tdrop;  // indegree of the evicted entry as read
-  bool ok;       // v* can enter N(v)
+  int drop;  // entry to evict, -1 for a free slot
+  bool ok;   // v* can enter N(v)
 };
 
 // decide an attempt from N(v) (keys lk, flags lf) and the entries'
@@ -994,9 +996,6 @@ FGIM_DEV void decide_attempt(Attempt<NR>& at, const uint32_t (&tv)[NR], uint32_t
       if (at.drop < 0 && m) at.drop = r * 64 + 63 - __clzll(static_cast<long long>(m));
     }
     at.ok = at.drop >= 0;
-#pragma unroll
-    for (int r = 0; r < NR; ++r)
-      if (at.drop >= 0 && r == at.drop / 64) at.tdrop = __builtin_amdgcn_readlane(tv[r], at.drop % 64);
   }
 }
 
@@ -1018,8 +1017,8 @@ FGIM_DEV Attempt<NR> try_neighbour(const uint64_t* keys, const uint32_t* flags, 
 }
 
 // write N(v) with entry `drop` removed (if any) and key nk inserted, and
-// update the indegrees (no other step of a committed prefix touches T of
-// the evicted entry, so its indegree as read is still current)
+// update the indegrees (the evicted entry's by an atomic decrement: other
+// steps of a committed prefix may lower it too)
 template <int NR>
 FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, uint32_t* newc, const Attempt<NR>& at,
                              uint32_t v, uint32_t vs, uint64_t nk, uint32_t k) {
@@ -1038,7 +1037,7 @@ FGIM_DEV void commit_attempt(uint64_t* keys, uint32_t* flags, uint32_t* T, uint3
       df = readlane(at.lf[r], at.drop % 64);
     }
   if (at.drop >= 0 && lane_id() == 0) {
-    __hip_atomic_store(&T[key_id(dk)], at.tdrop - 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_sub(&T[key_id(dk)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (newc && (df & kFlagNew)) atomicSub(&newc[key_id(dk)], 1u);
   }
 #pragma unroll
@@ -1075,38 +1074,62 @@ FGIM_DEV uint32_t repair_slot(uint32_t id) { return (id * 0x9E3779B1u) >> 21; }
 // A table slot packs (vertex << 32) | step; kEmptySlot is free.
 constexpr uint64_t kEmptySlot = ~0ull;
 
-// record that step i writes id (keeps the smallest step per id)
-FGIM_DEV void note_write(uint64_t* tab, uint32_t id, uint32_t i) {
+// record that step i writes id (keeps the smallest step per id); returns
+// the id's slot
+FGIM_DEV uint32_t note_write(uint64_t* tab, uint32_t id, uint32_t i) {
   uint32_t s = repair_slot(id);
   const uint64_t mine = (static_cast<uint64_t>(id) << 32) | i;
   for (;;) {
     const uint64_t prev = atomicCAS(reinterpret_cast<unsigned long long*>(&tab[s]), kEmptySlot, mine);
-    if (prev == kEmptySlot) return;
+    if (prev == kEmptySlot) return s;
     if (static_cast<uint32_t>(prev >> 32) == id) {
       atomicMin(reinterpret_cast<unsigned long long*>(&tab[s]), mine);
-      return;
+      return s;
     }
     s = (s + 1) & (kRepairHash - 1);
   }
 }
 
-FGIM_DEV uint32_t first_write_chain(const uint64_t* tab, uint32_t id, uint32_t s) {
+// record that step i evicts id: first such step, and how many steps of the
+// batch evict it
+FGIM_DEV void note_evict(uint64_t* tab, uint32_t* cnt, uint32_t id, uint32_t i) {
+  atomicAdd(&cnt[note_write(tab, id, i)], 1u);
+}
+
+FGIM_DEV uint32_t find_slot_chain(const uint64_t* tab, uint32_t id, uint32_t s) {
   for (;;) {
     s = (s + 1) & (kRepairHash - 1);
     const uint64_t cur = tab[s];
-    if (static_cast<uint32_t>(cur >> 32) == id) return static_cast<uint32_t>(cur);
+    if (static_cast<uint32_t>(cur >> 32) == id) return s;
     if (cur == kEmptySlot) return kNone;
   }
 }
 
-// first step of the batch that writes id (kNone: none); one LDS read unless
-// the home slot holds another vertex
-FGIM_DEV uint32_t first_write(const uint64_t* tab, uint32_t id) {
+// the slot holding id (kNone: absent); one LDS read unless the home slot
+// holds another vertex
+FGIM_DEV uint32_t find_slot(const uint64_t* tab, uint32_t id) {
   const uint32_t s = repair_slot(id);
   const uint64_t cur = tab[s];
-  if (static_cast<uint32_t>(cur >> 32) == id) return static_cast<uint32_t>(cur);
+  if (static_cast<uint32_t>(cur >> 32) == id) return s;
   if (cur == kEmptySlot) return kNone;
-  return first_write_chain(tab, id, s);
+  return find_slot_chain(tab, id, s);
+}
+
+// first step of the batch that writes id (kNone: none)
+FGIM_DEV uint32_t first_write(const uint64_t* tab, uint32_t id) {
+  const uint32_t s = find_slot(tab, id);
+  return s == kNone ? kNone : static_cast<uint32_t>(tab[s]);
+}
+
+// Whether step i's reading t of id's indegree may differ from the sequential
+// state: a step before i evicts id, and the batch's evictions of id (all of
+// them, a bound on those before i) could bring it to 1 or below, which
+// flips the test "indegree > 1".  Evictions that leave it above 1 change no
+// decision, and commits lower indegrees by atomic decrements.
+FGIM_DEV bool evict_conflict(const uint64_t* tab, const uint32_t* cnt, uint32_t id, uint32_t t, uint32_t i) {
+  const uint32_t s = find_slot(tab, id);
+  if (s == kNone) return false;
+  return static_cast<uint32_t>(tab[s]) < i && t <= cnt[s] + 1u;
 }
 
 template <int NR>
@@ -1119,12 +1142,14 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
   constexpr uint32_t B = RepairShape<NR>::kBatch;
   __shared__ uint64_t h_list[kRepairHash];   // lists written
   __shared__ uint64_t h_evict[kRepairHash];  // indegrees lowered
+  __shared__ uint32_t h_ecnt[kRepairHash];   // evictions per h_evict slot
   __shared__ uint32_t s_stop[2];  // first step of the batch that cannot commit
   const int w = threadIdx.x / 64;
   const int lane = lane_id();
   for (int t = threadIdx.x; t < kRepairHash; t += blockDim.x) {
     h_list[t] = kEmptySlot;
     h_evict[t] = kEmptySlot;
+    h_ecnt[t] = 0u;
   }
   if (threadIdx.x < 2) s_stop[threadIdx.x] = kNone;
   __syncthreads();
@@ -1197,7 +1222,7 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
       }
     }
     if (my_list != kNone) note_write(h_list, my_list, my_step);
-    if (my_evict != kNone) note_write(h_evict, my_evict, my_step);
+    if (my_evict != kNone) note_evict(h_evict, h_ecnt, my_evict, my_step);
     __syncthreads();
     if (threadIdx.x == 0) s_stop[parity ^ 1u] = kNone;
     uint32_t my_stop = kNone;
@@ -1214,7 +1239,7 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
       for (int r = 0; r < NR; ++r) {
         const uint32_t e = r * 64 + lane;
         if (reads_t && at[s].lk[r] != kSentinel && (full[s] || e + kTail >= k))
-          hit |= first_write(h_evict, key_id(at[s].lk[r])) < i;
+          hit |= evict_conflict(h_evict, h_ecnt, key_id(at[s].lk[r]), tv[s][r], i);
       }
       if (ballot(hit)) stop = true;
       if (stop && i < my_stop) my_stop = i;
@@ -1263,6 +1288,7 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_kernel(uint64_t* key
     for (int t = threadIdx.x; t < kRepairHash; t += blockDim.x) {
       h_list[t] = kEmptySlot;
       h_evict[t] = kEmptySlot;
+      h_ecnt[t] = 0u;
     }
     __threadfence_block();
     __syncthreads();
@@ -1312,6 +1338,7 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_half_kernel(uint64_t
   constexpr uint32_t B = kHalfBatch;
   __shared__ uint64_t h_list[kRepairHash];   // lists written
   __shared__ uint64_t h_evict[kRepairHash];  // indegrees lowered
+  __shared__ uint32_t h_ecnt[kRepairHash];   // evictions per h_evict slot
   __shared__ uint32_t s_stop[2];
   const uint32_t w = threadIdx.x / 64;
   const int lane = lane_id();
@@ -1321,6 +1348,7 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_half_kernel(uint64_t
   for (int t = threadIdx.x; t < kRepairHash; t += blockDim.x) {
     h_list[t] = kEmptySlot;
     h_evict[t] = kEmptySlot;
+    h_ecnt[t] = 0u;
   }
   if (threadIdx.x < 2) s_stop[threadIdx.x] = kNone;
   __syncthreads();
@@ -1384,7 +1412,7 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_half_kernel(uint64_t
       }
     }
     if (my_list != kNone) note_write(h_list, my_list, my_step);
-    if (my_evict != kNone) note_write(h_evict, my_evict, my_step);
+    if (my_evict != kNone) note_evict(h_evict, h_ecnt, my_evict, my_step);
     __syncthreads();
     if (threadIdx.x == 0) s_stop[parity ^ 1u] = kNone;
     uint32_t my_stop = kNone;
@@ -1395,7 +1423,7 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_half_kernel(uint64_t
       if (ok[s] && first_write(h_list, v[s]) < i) stop = true;
       const bool reads_t = ok[s] && drop[s] >= 0;
       const bool hit = reads_t && lk[s] != kSentinel && (full[s] || e + kTail >= k) &&
-                       first_write(h_evict, key_id(lk[s])) < i;
+                       evict_conflict(h_evict, h_ecnt, key_id(lk[s]), tv[s], i);
       if (ballot(hit) & hmask) stop = true;
       if (stop && i < my_stop) my_stop = i;
     }
@@ -1420,10 +1448,9 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_half_kernel(uint64_t
       const int dl = static_cast<int>(hf * 32) + (d >= 0 ? d : 0);
       const uint64_t dk = shfl64(lk[s], dl);
       const uint32_t df = static_cast<uint32_t>(__shfl(static_cast<int>(lf[s]), dl, 64));
-      const uint32_t tdrop = static_cast<uint32_t>(__shfl(static_cast<int>(tv[s]), dl, 64));
       const uint64_t row = static_cast<uint64_t>(v[s]) * k;
       if (commit && d >= 0 && e == 0) {
-        __hip_atomic_store(&T[key_id(dk)], tdrop - 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_fetch_sub(&T[key_id(dk)], 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         if (newc && (df & kFlagNew)) atomicSub(&newc[key_id(dk)], 1u);
       }
       if (commit && e < k && static_cast<int>(e) != d && lk[s] != kSentinel) {
@@ -1466,6 +1493,7 @@ __global__ void __launch_bounds__(64 * kRepairWaves) repair_half_kernel(uint64_t
     for (int t = threadIdx.x; t < kRepairHash; t += blockDim.x) {
       h_list[t] = kEmptySlot;
       h_evict[t] = kEmptySlot;
+      h_ecnt[t] = 0u;
     }
     __threadfence_block();
     __syncthreads();
