@@ -180,10 +180,11 @@ template <bool L2, int MMAX, class Row>
 FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, const float4 (&q)[MMAX],
                           const BeamArgs& a, const WaveLds& lds, int m) {
   // group batches in flight: two for FP32 rows, else as many as about 32
-  // registers of raw (BF16 / FP8) row data per lane hold, at most four
-  // (eight measured slower on d = 128 and d = 768)
+  // registers of raw (BF16 / FP8) row data per lane hold, at most three:
+  // four take the kernel past 128 VGPRs, to 12 resident waves per CU, and
+  // measured 12-25 % slower on d = 96, 128 and 768 (eight slower still)
   constexpr int kRawRegs = static_cast<int>(sizeof(typename Row::Raw) / 4);
-  constexpr int kLowP = 32 / (MMAX * kRawRegs) < 4 ? 32 / (MMAX * kRawRegs) : 4;
+  constexpr int kLowP = 32 / (MMAX * kRawRegs) < 3 ? 32 / (MMAX * kRawRegs) : 3;
   constexpr int U = MMAX > 4 ? 1 : (kRawRegs == 4 ? 2 : kLowP);
   const int P = static_cast<int>(a.P);
   const int M = static_cast<int>(a.M);
@@ -194,8 +195,12 @@ FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, cons
     typename Row::Raw rv[U][MMAX];
     float sc[U];
     uint32_t rid[U];
+    // batches past the last candidate are skipped (wave-uniform): an
+    // expansion brings about as many new ids as a vertex has neighbours,
+    // often fewer than G * U
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      if (base + u * G >= m) break;
       const int c = base + u * G + g;
       const bool act = c < m;
       rid[u] = lds.cand[act ? c : 0];
@@ -208,6 +213,7 @@ FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, cons
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
+      if (base + u * G >= m) break;
       const int c = base + u * G + g;
       const bool act = c < m;
       float s[MMAX];
