@@ -98,6 +98,10 @@ def cpu_baseline(cfg, X, graphs, budget_nodes: int):
     t0 = time.perf_counter()
     oracle.cross_query(X, graphs, cfg.k, cfg.L, cfg.metric, nodes=nodes, threads=threads)
     t_s1 = (time.perf_counter() - t0) / len(nodes)
+    one = nodes[:1000]
+    t0 = time.perf_counter()
+    oracle.cross_query(X, graphs, cfg.k, cfg.L, cfg.metric, nodes=one, threads=1)
+    t_s1_one = (time.perf_counter() - t0) / len(one)
     small = cfg.scaled(tuple(min(s, 20000) for s in cfg.sizes[:2]) if cfg.h > 2 else (20000,) * cfg.h)
     Xs = make_vectors(small)
     gs = []
@@ -114,7 +118,20 @@ def cpu_baseline(cfg, X, graphs, budget_nodes: int):
             "sample": (f"stage 1 on {len(nodes)} seeded vertices of the full workload "
                        f"({t_s1 * 1e3:.3f} ms/vertex); stages 2-3 in full on a "
                        f"{'+'.join(str(s) for s in small.sizes)} draw of the same distribution "
-                       f"({t_s23 * 1e3:.3f} ms/vertex)")}
+                       f"({t_s23 * 1e3:.3f} ms/vertex)"),
+            "cpu": cpu_model(),
+            "stage1_ms_per_vertex_1thread": round(t_s1_one * 1e3, 4)}
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def main():
