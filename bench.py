@@ -231,6 +231,8 @@ def main():
             "algorithmic_bytes": int(alg_bytes), "ndc_per_search": round(ndc / max(1, searches), 2),
             "expansions_per_search": round(nexp / max(1, searches), 2),
             "ndc_source": "timed launch" if args.no_ndc_count else "counting launch, 16384 visited slots",
+            "launch": {"lanes_per_dist": st["lanes_per_dist"], "waves_per_cu": st["waves_per_cu"],
+                       "visited_slots": st["visited_slots"]},
             "beam_sources_sha256": beam_source_hash()}
 
     out = {"metric": METRIC, "value": round(value, 1), "unit": "vectors/s", "n_gpus": 1,

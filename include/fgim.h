@@ -165,6 +165,9 @@ fgim_status fgim_cross_query(const fgim_dataset* data, const fgim_params* params
  * zero-indegree vertex into a neighbour's list.  All input entries count as
  * new.  knn_ids / knn_dist (device, n_total x k) are read and rewritten;
  * indegree (device, n_total, nullable) receives T after the last round.
+ * Errors: FGIM_ERR_INVALID_ARG (arguments), FGIM_ERR_GRAPH (a list id that
+ * is neither FGIM_NONE nor below n_total; checked on the device before any
+ * list is changed, the call then synchronises).
  */
 fgim_status fgim_refine(const fgim_dataset* data, const fgim_params* params,
                         uint32_t* knn_ids, float* knn_dist, uint32_t* indegree,
@@ -235,6 +238,18 @@ fgim_status fgim_quantize(const float* base, uint64_t n, uint32_t dim, uint64_t 
  * every vertex still collects k candidates (minimum querying strategy,
  * Section 4.1.2).  0 when h < 2. */
 uint32_t fgim_min_beam_width(uint32_t k, uint32_t min_local, uint32_t h);
+
+/*
+ * Scratch memory.  Every call takes its temporary buffers from a device
+ * arena that the library keeps between calls (it grows to the largest total
+ * a call has needed; until then the excess comes from the device's
+ * stream-ordered memory pool).  Calls on one device therefore run one at a
+ * time on the host, and a call's device work starts after that of the
+ * previous call.  fgim_release_scratch waits for the current device's last
+ * call to finish on the device and frees its arena; the next call starts a
+ * new one.  Errors: FGIM_ERR_DEVICE (no device, or a HIP failure).
+ */
+fgim_status fgim_release_scratch(void);
 
 const char* fgim_status_string(fgim_status status);
 /* Detail of the last error on the calling thread ("" if none). */

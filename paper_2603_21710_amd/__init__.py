@@ -31,7 +31,8 @@ STATUS = {0: "FGIM_OK", 1: "FGIM_ERR_INVALID_ARG", 2: "FGIM_ERR_GRAPH",
           3: "FGIM_ERR_OUT_OF_MEMORY", 4: "FGIM_ERR_DEVICE", 5: "FGIM_ERR_UNSUPPORTED"}
 
 EXPORTS = ["fgim_cross_query", "fgim_refine", "fgim_repair", "fgim_prune", "fgim_merge", "fgim_search",
-           "fgim_quantize", "fgim_min_beam_width", "fgim_status_string", "fgim_last_error"]
+           "fgim_quantize", "fgim_min_beam_width", "fgim_release_scratch", "fgim_status_string",
+           "fgim_last_error"]
 
 
 class FgimError(RuntimeError):
@@ -110,6 +111,8 @@ def lib() -> ctypes.CDLL:
         L.fgim_status_string.argtypes = [i32]
         L.fgim_last_error.restype = ctypes.c_char_p
         L.fgim_last_error.argtypes = []
+        L.fgim_release_scratch.restype = ctypes.c_int
+        L.fgim_release_scratch.argtypes = []
         _lib = L
     return _lib
 
@@ -209,6 +212,12 @@ def repair(ids: torch.Tensor, dist: torch.Tensor):
     _check(lib().fgim_repair(ids.data_ptr(), dist.data_ptr(), ids.shape[0], ids.shape[1], T.data_ptr(),
                              ctypes.byref(n), _stream()))
     return T, n.value
+
+
+def release_scratch() -> None:
+    """Free the current device's scratch arena (after its last call has
+    finished on the device); the next call starts a new one."""
+    _check(lib().fgim_release_scratch())
 
 
 def prune(m: Merge, p: Params, ids: torch.Tensor, dist: torch.Tensor, T: torch.Tensor):

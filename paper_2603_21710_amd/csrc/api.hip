@@ -53,6 +53,120 @@ hipError_t library_stream(hipStream_t* out) {
   return hipSuccess;
 }
 
+void keep_scratch_cached() {
+  static std::once_flag once[64];
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return;
+  }
+  std::call_once(once[dev], [dev] {
+    hipMemPool_t pool = nullptr;
+    uint64_t cur = 0;
+    if (hipDeviceGetMemPool(&pool, dev) == hipSuccess && pool &&
+        hipMemPoolGetAttribute(pool, hipMemPoolAttrReleaseThreshold, &cur) == hipSuccess && cur == 0) {
+      uint64_t keep = ~0ull;
+      (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &keep);
+    }
+    (void)hipGetLastError();
+  });
+}
+
+namespace {
+
+struct Arena {
+  std::recursive_mutex mu;
+  char* base = nullptr;
+  size_t cap = 0;   // bytes at base
+  size_t top = 0;   // bytes taken by the live scopes
+  size_t virt = 0;  // bytes the live scopes asked for, spilled ones included
+  size_t high = 0;  // the largest virt seen: the size the next growth aims at
+  int depth = 0;    // live scopes
+  hipEvent_t done = nullptr;
+  bool pending = false;  // done marks the last call's device work
+};
+
+Arena g_arena[64];
+constexpr size_t kArenaAlign = 256;
+
+size_t arena_align(size_t x) { return (x + kArenaAlign - 1) & ~(kArenaAlign - 1); }
+
+}  // namespace
+
+Scratch::Scratch(hipStream_t st) : s(st) {
+  keep_scratch_cached();
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    dev = -1;
+    return;
+  }
+  Arena& a = g_arena[dev];
+  a.mu.lock();
+  if (a.depth == 0) {
+    if (a.pending) (void)hipStreamWaitEvent(s, a.done, 0);
+    if (a.high > a.cap) {
+      // the last call's device work may still use the old buffer
+      if (a.pending) (void)hipEventSynchronize(a.done);
+      if (a.base) (void)hipFree(a.base);
+      a.base = nullptr;
+      a.cap = 0;
+      const size_t want = arena_align(a.high + a.high / 8);
+      if (hipMalloc(&a.base, want) == hipSuccess && a.base) a.cap = want;
+      else a.base = nullptr;
+    }
+    (void)hipGetLastError();
+    a.top = 0;
+    a.virt = 0;
+  }
+  mark_top = a.top;
+  mark_virt = a.virt;
+  ++a.depth;
+}
+
+void* Scratch::take(size_t bytes) {
+  if (dev < 0) return nullptr;
+  Arena& a = g_arena[dev];
+  const size_t b = arena_align(bytes);
+  a.virt += b;
+  a.high = std::max(a.high, a.virt);
+  if (a.top + b > a.cap) return nullptr;
+  void* p = a.base + a.top;
+  a.top += b;
+  return p;
+}
+
+Scratch::~Scratch() {
+  for (void* p : spill) (void)hipFreeAsync(p, s);
+  if (dev < 0) return;
+  Arena& a = g_arena[dev];
+  a.top = mark_top;
+  a.virt = mark_virt;
+  if (--a.depth == 0) {
+    if (!a.done && hipEventCreateWithFlags(&a.done, hipEventDisableTiming) != hipSuccess) a.done = nullptr;
+    a.pending = a.done && hipEventRecord(a.done, s) == hipSuccess;
+    (void)hipGetLastError();
+  }
+  a.mu.unlock();
+}
+
+fgim_status release_scratch() {
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) {
+    (void)hipGetLastError();
+    return fail(FGIM_ERR_DEVICE, "no current HIP device");
+  }
+  Arena& a = g_arena[dev];
+  std::lock_guard<std::recursive_mutex> lock(a.mu);
+  if (a.depth) return fail(FGIM_ERR_INVALID_ARG, "scratch is in use by a call on this thread");
+  if (a.pending) HIP_TRY(hipEventSynchronize(a.done));
+  a.pending = false;
+  if (a.base) HIP_TRY(hipFree(a.base));
+  a.base = nullptr;
+  a.cap = 0;
+  a.high = 0;
+  return FGIM_OK;
+}
+
 // ---------------------------------------------------------------------------
 // utility kernels
 
@@ -441,6 +555,11 @@ const char* fgim_status_string(fgim_status s) {
 }
 
 const char* fgim_last_error(void) { return g_last_error.c_str(); }
+
+fgim_status fgim_release_scratch(void) {
+  g_last_error.clear();
+  return release_scratch();
+}
 
 uint32_t fgim_min_beam_width(uint32_t k, uint32_t min_local, uint32_t h) {
   if (h < 2) return 0;

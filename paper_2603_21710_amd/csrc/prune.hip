@@ -372,8 +372,11 @@ static uint32_t pow2_ceil(uint32_t x) {
   return p;
 }
 
+// Stage 3.  Lists from a caller are checked first (ids in range, no entry
+// after a free slot); the merge passes its own refined lists as trusted
+// and skips the check and its host wait.
 fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32_t* ids, const float* dist,
-                       const uint32_t* T, uint32_t* pg_ids, uint32_t* pg_deg, hipStream_t s) {
+                       const uint32_t* T, uint32_t* pg_ids, uint32_t* pg_deg, hipStream_t s, bool trusted) {
   FGIM_TRY(check_dataset(d, false));
   if (!p) return fail(FGIM_ERR_INVALID_ARG, "params is NULL");
   if (!ids || !dist || !T || !pg_ids || !pg_deg) return fail(FGIM_ERR_INVALID_ARG, "NULL buffer");
@@ -403,12 +406,14 @@ fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32
   FGIM_TRY(scr.get(&rev, N * R));
   FGIM_TRY(scr.get(&tmp, scan_tmp_words(N) + 16));
   FGIM_TRY(scr.get(&err, 4));
-  HIP_TRY(fill_u32(err, 0u, 1, s));
-  hipLaunchKernelGGL(validate_lists_kernel, dim3(grid_n(N * k)), dim3(256), 0, s, ids, N * k, N, p->k, err);
-  uint32_t herr = 0;
-  HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipStreamSynchronize(s));
-  if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n_total or an entry after a free slot");
+  if (!trusted) {
+    HIP_TRY(fill_u32(err, 0u, 1, s));
+    hipLaunchKernelGGL(validate_lists_kernel, dim3(grid_n(N * k)), dim3(256), 0, s, ids, N * k, N, p->k, err);
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n_total or an entry after a free slot");
+  }
 
   SelectArgs sa{d->base, d->ld, nc, d->metric, N, p->k, p->R, ids, dist, T, sel_ids, sel_dist, sel_n, P, M, stage,
                 nullptr, nullptr, 0, 0};
@@ -463,7 +468,7 @@ fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32
 fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist,
                              fgim_stats* stats, hipStream_t s, uint32_t* L_used);
 fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist, uint32_t* T_out,
-                        fgim_stats* stats, hipStream_t s);
+                        fgim_stats* stats, hipStream_t s, bool trusted);
 
 }  // namespace fgim
 
@@ -475,7 +480,7 @@ fgim_status fgim_prune(const fgim_dataset* data, const fgim_params* params, cons
                        const float* knn_dist, const uint32_t* indegree, uint32_t* pg_ids, uint32_t* pg_deg,
                        void* stream) {
   fail(FGIM_OK, "");
-  return prune_impl(data, params, knn_ids, knn_dist, indegree, pg_ids, pg_deg, static_cast<hipStream_t>(stream));
+  return prune_impl(data, params, knn_ids, knn_dist, indegree, pg_ids, pg_deg, static_cast<hipStream_t>(stream), false);
 }
 
 fgim_status fgim_merge(const fgim_dataset* data, const fgim_params* params, uint32_t* pg_ids, uint32_t* pg_deg,
@@ -500,9 +505,9 @@ fgim_status fgim_merge(const fgim_dataset* data, const fgim_params* params, uint
   fgim_stats st1{}, st2{};
   FGIM_TRY(cross_query_impl(data, params, ids, dist, stats ? &st1 : nullptr, s, nullptr));
   HIP_TRY(hipEventRecord(ev[1], s));
-  FGIM_TRY(refine_impl(data, params, ids, dist, T, stats ? &st2 : nullptr, s));
+  FGIM_TRY(refine_impl(data, params, ids, dist, T, stats ? &st2 : nullptr, s, true));
   HIP_TRY(hipEventRecord(ev[2], s));
-  FGIM_TRY(prune_impl(data, params, ids, dist, T, pg_ids, pg_deg, s));
+  FGIM_TRY(prune_impl(data, params, ids, dist, T, pg_ids, pg_deg, s, true));
   HIP_TRY(hipEventRecord(ev[3], s));
   HIP_TRY(hipEventSynchronize(ev[3]));
   uint32_t best = 0;

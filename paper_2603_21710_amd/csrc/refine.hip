@@ -1641,8 +1641,17 @@ uint32_t ceil_pow2_u(uint32_t x) {
   return p;
 }
 
+__global__ void check_ids_kernel(const uint32_t* ids, uint64_t nk, uint64_t N, uint32_t* err) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    if (ids[i] != kNone && ids[i] >= N) atomicOr(err, 1u);
+}
+
+// Stage 2 on the lists (ids, dist).  Lists from a caller are checked first
+// (an id >= n would index the indegrees out of bounds); the merge passes its
+// own stage-1 lists as trusted and skips the check and its host wait.
 fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist, uint32_t* T_out,
-                        fgim_stats* stats, hipStream_t s) {
+                        fgim_stats* stats, hipStream_t s, bool trusted) {
   FGIM_TRY(check_dataset(d, false));
   if (!p) return fail(FGIM_ERR_INVALID_ARG, "params is NULL");
   if (!ids || !dist) return fail(FGIM_ERR_INVALID_ARG, "lists are NULL");
@@ -1653,6 +1662,18 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   if (nk >= 0xFFFFFFFFull || 2 * N + 1 >= 0xFFFFFFFFull)
     return fail(FGIM_ERR_UNSUPPORTED, "N x k = %llu list entries exceed 32-bit offsets", (unsigned long long)nk);
   const bool repair = !(p->flags & FGIM_FLAG_NO_REPAIR);
+  if (!trusted) {
+    Scratch chk(s);
+    uint32_t* err = nullptr;
+    FGIM_TRY(chk.get(&err, 4));
+    HIP_TRY(fill_u32(err, 0u, 1, s));
+    hipLaunchKernelGGL(check_ids_kernel, dim3(grid_for(nk)), dim3(256), 0, s, ids, nk, N, err);
+    HIP_TRY(hipGetLastError());
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n_total");
+  }
 
   const uint32_t dim = d->dim, nc = dim / 4;
   const uint32_t Nch = ceil_pow2_u(nc);
@@ -1700,7 +1721,6 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     FGIM_TRY(scr.get(&b.zmask, N + 1));
     FGIM_TRY(scr.get(&b.zoff, N + 1));
     FGIM_TRY(scr.get(&b.zero, N + 1));
-  FGIM_TRY(scr.get(&b.zkey, N + 1));
     FGIM_TRY(scr.get(&b.zkey, N + 1));
     FGIM_TRY(scr.get(&b.hdr, 16));
     float *nrm2 = nullptr, *qerr2 = nullptr;
@@ -1802,9 +1822,13 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     }
     const bool capture = !(p->flags & FGIM_FLAG_NO_GRAPH_CAPTURE) && p->rounds > 1;
     if (capture) {
-      // Rounds are captured once and replayed.  Capture needs a stream other
-      // than the legacy null stream, so the rounds run on a library stream
-      // ordered after, and before, the caller's stream by events.
+      // The first round runs directly on the caller's stream; while the
+      // device works on it, the host captures one round into a graph and
+      // instantiates it, and the remaining rounds replay that graph.
+      // Capture needs a stream other than the legacy null stream, so the
+      // replays run on a library stream ordered after, and before, the
+      // caller's stream by events.
+      HIP_TRY(run_round(rp, b, s));
       hipStream_t cs = nullptr;
       HIP_TRY(library_stream(&cs));
       hipEvent_t joined = nullptr, done = nullptr;
@@ -1820,7 +1844,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
       hipError_t ie = hipSuccess;
       if (le == hipSuccess && ce == hipSuccess) ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
       hipError_t ge = hipSuccess;
-      for (uint32_t r = 0; r < p->rounds && le == hipSuccess && ce == hipSuccess && ie == hipSuccess && ge == hipSuccess; ++r)
+      for (uint32_t r = 1; r < p->rounds && le == hipSuccess && ce == hipSuccess && ie == hipSuccess && ge == hipSuccess; ++r)
         ge = hipGraphLaunch(exec, cs);
       HIP_TRY(hipEventRecord(done, cs));
       HIP_TRY(hipStreamWaitEvent(s, done, 0));
@@ -1863,12 +1887,6 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     return FGIM_OK;
   }
   return fail(FGIM_ERR_OUT_OF_MEMORY, "join proposals keep overflowing the buffer");
-}
-
-__global__ void check_ids_kernel(const uint32_t* ids, uint64_t nk, uint64_t N, uint32_t* err) {
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-    if (ids[i] != kNone && ids[i] >= N) atomicOr(err, 1u);
 }
 
 fgim_status repair_impl(uint32_t* ids, float* dist, uint64_t N, uint32_t k, uint32_t* T_out, uint64_t* repaired,
@@ -1924,5 +1942,5 @@ extern "C" fgim_status fgim_refine(const fgim_dataset* data, const fgim_params* 
                                    float* knn_dist, uint32_t* indegree, fgim_stats* stats, void* stream) {
   fgim::fail(FGIM_OK, "");
   if (stats) memset(stats, 0, sizeof(*stats));
-  return fgim::refine_impl(data, params, knn_ids, knn_dist, indegree, stats, static_cast<hipStream_t>(stream));
+  return fgim::refine_impl(data, params, knn_ids, knn_dist, indegree, stats, static_cast<hipStream_t>(stream), false);
 }

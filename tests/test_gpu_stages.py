@@ -112,6 +112,38 @@ def test_prune_rejects_list_holes():
     assert ei.value.name == "FGIM_ERR_GRAPH"
 
 
+def test_scratch_arena_reuse_and_release():
+    """Calls reuse the library's scratch arena (grown after the first call);
+    releasing it, or running on another stream, changes no result."""
+    cfg, X, graphs, _ = workload("cfg1", (700, 500))
+    m = to_gpu(X, graphs, cfg.metric)
+    p = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds)
+    fg.release_scratch()
+    ref, rdeg, rent, _ = fg.merge(m, p)  # spills to the memory pool, then sizes the arena
+    for _ in range(2):
+        pg, deg, ent, _ = fg.merge(m, p)  # from the arena
+        assert torch.equal(pg, ref) and torch.equal(deg, rdeg) and ent == rent
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        pg, deg, ent, _ = fg.merge(m, p)
+    side.synchronize()
+    assert torch.equal(pg, ref) and ent == rent
+    fg.release_scratch()
+    pg, _, _, _ = fg.merge(m, p)
+    assert torch.equal(pg, ref)
+
+
+def test_refine_rejects_out_of_range_ids():
+    cfg, X, graphs, m, ids, dist = _stage1("cfg1", None)
+    bad = ids.clone()
+    bad[5, 1] = X.shape[0] + 7  # an id past n_total
+    keep = bad.clone()
+    with pytest.raises(fg.FgimError) as ei:
+        fg.refine(m, fg.params(k=cfg.k, L=cfg.L, rounds=1), bad, dist)
+    assert ei.value.name == "FGIM_ERR_GRAPH"
+    assert torch.equal(bad, keep)  # rejected before any list was changed
+
+
 @pytest.mark.parametrize("name,sizes", CASES, ids=IDS)
 def test_merge_matches_oracle(name, sizes):
     cfg, X, graphs, _ = workload(name, sizes)
