@@ -447,6 +447,7 @@ constexpr uint32_t kMfmaMaxCn = 64;       // |Cn| bound on the MFMA path (k + k_
 constexpr uint32_t kMfmaTilesPerWave = 7; // ceil(26 tile pairs / 4 waves) for |Cn| <= 64, c <= 128
 constexpr uint32_t kPairChunk = 1024;     // pair-buffer slots a join workgroup claims at a time
 constexpr uint64_t kNoPair = ~0ull;       // an unused pair-buffer slot
+constexpr uint32_t kJoinStage = 4;  // row chunks a thread gathers before storing them
 
 // position of the r-th set bit (r < popcount) of the 128-bit mask (m0, m1)
 FGIM_DEV uint32_t select_bit(uint64_t m0, uint64_t m1, uint32_t r) {
@@ -635,25 +636,36 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
       const uint32_t sw = min(a.slice, a.dpad - s0);   // multiple of 32
       __syncthreads();
       const uint32_t per_row = sw / 8;
-      for (uint32_t idx = threadIdx.x; idx < nC * 16 * per_row; idx += 256) {
-        const uint32_t e = idx / per_row, q = idx - e * per_row;
-        const uint32_t t0 = s0 + 8 * q;
-        shortx8_t v8;
-        if (e < c && t0 < a.dim) {
-          const uint64_t v = cid[e];
-          if (a.xb) {
-            v8 = *reinterpret_cast<const shortx8_t*>(a.xb + v * a.dim + t0);
-          } else {
-            const float4 f0 = *reinterpret_cast<const float4*>(a.X + v * a.ld + t0);
-            const float4 f1 = t0 + 4 < a.dim ? *reinterpret_cast<const float4*>(a.X + v * a.ld + t0 + 4)
-                                             : make_float4(0.f, 0.f, 0.f, 0.f);
-            v8[0] = bf16_rne(f0.x); v8[1] = bf16_rne(f0.y); v8[2] = bf16_rne(f0.z); v8[3] = bf16_rne(f0.w);
-            v8[4] = bf16_rne(f1.x); v8[5] = bf16_rne(f1.y); v8[6] = bf16_rne(f1.z); v8[7] = bf16_rne(f1.w);
+      const uint32_t total = nC * 16 * per_row;
+      // kJoinStage chunks per thread are gathered before any is stored, so
+      // their memory latencies overlap (one wait per batch, not per chunk)
+      for (uint32_t base = 0; base < total; base += 256 * kJoinStage) {
+        shortx8_t v8[kJoinStage];
+#pragma unroll
+        for (uint32_t b = 0; b < kJoinStage; ++b) {
+          const uint32_t idx = base + b * 256 + threadIdx.x;
+          const uint32_t e = idx / per_row, q = idx - e * per_row;
+          const uint32_t t0 = s0 + 8 * q;
+          v8[b] = shortx8_t{0, 0, 0, 0, 0, 0, 0, 0};
+          if (idx < total && e < c && t0 < a.dim) {
+            const uint64_t v = cid[e];
+            if (a.xb) {
+              v8[b] = *reinterpret_cast<const shortx8_t*>(a.xb + v * a.dim + t0);
+            } else {
+              const float4 f0 = *reinterpret_cast<const float4*>(a.X + v * a.ld + t0);
+              const float4 f1 = t0 + 4 < a.dim ? *reinterpret_cast<const float4*>(a.X + v * a.ld + t0 + 4)
+                                               : make_float4(0.f, 0.f, 0.f, 0.f);
+              v8[b][0] = bf16_rne(f0.x); v8[b][1] = bf16_rne(f0.y); v8[b][2] = bf16_rne(f0.z); v8[b][3] = bf16_rne(f0.w);
+              v8[b][4] = bf16_rne(f1.x); v8[b][5] = bf16_rne(f1.y); v8[b][6] = bf16_rne(f1.z); v8[b][7] = bf16_rne(f1.w);
+            }
           }
-        } else {
-          v8 = shortx8_t{0, 0, 0, 0, 0, 0, 0, 0};
         }
-        *reinterpret_cast<shortx8_t*>(brows + e * srow + 8 * q) = v8;
+#pragma unroll
+        for (uint32_t b = 0; b < kJoinStage; ++b) {
+          const uint32_t idx = base + b * 256 + threadIdx.x;
+          const uint32_t e = idx / per_row, q = idx - e * per_row;
+          if (idx < total) *reinterpret_cast<shortx8_t*>(brows + e * srow + 8 * q) = v8[b];
+        }
       }
       __syncthreads();
 #pragma unroll
