@@ -160,6 +160,8 @@ FGIM_DEV uint32_t select_bit64(uint64_t m, uint32_t r) {
 // delta(u, v_p), left clear when the estimate minus the bound exceeds it,
 // and otherwise decided by the canonical FP32 distance.  The bits are those
 // of the plain computation.
+constexpr uint32_t kSelStage = 2;  // row chunks a lane loads before staging them
+
 template <int MMAX>
 __global__ void __launch_bounds__(128) select_mfma_kernel(SelectArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -206,17 +208,32 @@ __global__ void __launch_bounds__(128) select_mfma_kernel(SelectArgs a) {
     for (uint32_t s0 = 0; s0 < a.dpad; s0 += slice) {
       const uint32_t sw = a.dpad - s0 < slice ? a.dpad - s0 : slice;  // multiple of 32
       const uint32_t per_row = sw / 8;
-      for (uint32_t idx = lane; idx < kpad * per_row; idx += 64) {
-        const uint32_t e = idx / per_row, c8 = 8 * (idx - e * per_row), t0 = s0 + c8;
-        shortx8_t v8 = shortx8_t{0, 0, 0, 0, 0, 0, 0, 0};
-        if (e < cnt && t0 < dim) {
-          const float* xr = a.X + static_cast<uint64_t>(vid[e]) * a.ld + t0;
-          const float4 f0 = *reinterpret_cast<const float4*>(xr);
-          const float4 f1 = t0 + 4 < dim ? *reinterpret_cast<const float4*>(xr + 4) : make_float4(0.f, 0.f, 0.f, 0.f);
+      const uint32_t total = kpad * per_row;
+      // kSelStage chunks per lane are loaded before any is converted and
+      // stored, so their memory latencies overlap
+      for (uint32_t base = 0; base < total; base += 64 * kSelStage) {
+        float4 f[kSelStage][2];
+#pragma unroll
+        for (uint32_t b = 0; b < kSelStage; ++b) {
+          const uint32_t idx = base + b * 64 + lane;
+          const uint32_t e = idx / per_row, t0 = s0 + 8 * (idx - e * per_row);
+          f[b][0] = f[b][1] = make_float4(0.f, 0.f, 0.f, 0.f);
+          if (idx < total && e < cnt && t0 < dim) {
+            const float* xr = a.X + static_cast<uint64_t>(vid[e]) * a.ld + t0;
+            f[b][0] = *reinterpret_cast<const float4*>(xr);
+            if (t0 + 4 < dim) f[b][1] = *reinterpret_cast<const float4*>(xr + 4);
+          }
+        }
+#pragma unroll
+        for (uint32_t b = 0; b < kSelStage; ++b) {
+          const uint32_t idx = base + b * 64 + lane;
+          const uint32_t e = idx / per_row, c8 = 8 * (idx - e * per_row);
+          const float4 f0 = f[b][0], f1 = f[b][1];
+          shortx8_t v8;
           v8[0] = bf16_rne(f0.x); v8[1] = bf16_rne(f0.y); v8[2] = bf16_rne(f0.z); v8[3] = bf16_rne(f0.w);
           v8[4] = bf16_rne(f1.x); v8[5] = bf16_rne(f1.y); v8[6] = bf16_rne(f1.z); v8[7] = bf16_rne(f1.w);
+          if (idx < total) *reinterpret_cast<shortx8_t*>(rows + e * srow + c8) = v8;
         }
-        *reinterpret_cast<shortx8_t*>(rows + e * srow + c8) = v8;
       }
       wave_lds_sync();
       // D[i][j] = <row i, row j> over this slice, accumulated
