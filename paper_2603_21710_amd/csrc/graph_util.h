@@ -20,21 +20,28 @@ hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t n, uint32_
                           hipStream_t s);
 uint64_t scan_tmp_words(uint64_t n);
 
-// canonical distance between rows a and b (pointers to row starts), computed
-// by a group of P lanes (sub-lane l); every lane of the group gets the result
+// the P-lane group's chunks of the row at a (sub-lane l holds chunks l,
+// l + P, ...; zero where it holds none or when !act)
 template <int MMAX>
-FGIM_DEV float pair_distance(const float* a, const float* b, int metric, uint32_t nc, int P, int M, int l,
-                             bool act) {
+FGIM_DEV void load_row_chunks(float4 (&x)[MMAX], const float* a, uint32_t nc, int P, int M, int l, bool act) {
+#pragma unroll
+  for (int mi = 0; mi < MMAX; ++mi) {
+    const uint32_t ch = static_cast<uint32_t>(l + mi * P);
+    x[mi] = (mi < M && act && ch < nc) ? *reinterpret_cast<const float4*>(a + 4 * ch) : make_float4(0.f, 0.f, 0.f, 0.f);
+  }
+}
+
+// canonical distance between two rows whose chunks the group holds (as
+// load_row_chunks leaves them); every lane of the group gets the result
+template <int MMAX>
+FGIM_DEV float chunks_distance(const float4 (&x)[MMAX], const float4 (&y)[MMAX], int metric, uint32_t nc, int P, int M,
+                               int l, bool act) {
   float s[MMAX];
 #pragma unroll
   for (int mi = 0; mi < MMAX; ++mi) {
     s[mi] = 0.0f;
     const uint32_t ch = static_cast<uint32_t>(l + mi * P);
-    if (mi < M && act && ch < nc) {
-      const float4 x = *reinterpret_cast<const float4*>(a + 4 * ch);
-      const float4 y = *reinterpret_cast<const float4*>(b + 4 * ch);
-      s[mi] = metric == kL2 ? chunk_sum<kL2>(x, y) : chunk_sum<kIP>(x, y);
-    }
+    if (mi < M && act && ch < nc) s[mi] = metric == kL2 ? chunk_sum<kL2>(x[mi], y[mi]) : chunk_sum<kIP>(x[mi], y[mi]);
   }
 #pragma unroll
   for (int st = MMAX / 2; st >= 1; st /= 2) {
@@ -50,6 +57,17 @@ FGIM_DEV float pair_distance(const float* a, const float* b, int metric, uint32_
   if (metric == kL2) return finish<kL2>(r);
   if (metric == kIP) return finish<kIP>(r);
   return finish<kCos>(r);
+}
+
+// canonical distance between rows a and b (pointers to row starts), computed
+// by a group of P lanes (sub-lane l); every lane of the group gets the result
+template <int MMAX>
+FGIM_DEV float pair_distance(const float* a, const float* b, int metric, uint32_t nc, int P, int M, int l,
+                             bool act) {
+  float4 x[MMAX], y[MMAX];
+  load_row_chunks<MMAX>(x, a, nc, P, M, l, act);
+  load_row_chunks<MMAX>(y, b, nc, P, M, l, act);
+  return chunks_distance<MMAX>(x, y, metric, nc, P, M, l, act);
 }
 
 // canonical distance of the P-lane group's row (chunks held in x) to row b

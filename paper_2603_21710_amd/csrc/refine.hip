@@ -805,30 +805,52 @@ __global__ void __launch_bounds__(256) recheck_kernel(JoinArgs a) {
     if (threadIdx.x == 0) scount = 0;
     __syncthreads();
   };
-  for (uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * per_block; b0 < n;
-       b0 += static_cast<uint64_t>(gridDim.x) * per_block) {
-    const uint64_t idx = b0 + threadIdx.x / P;
-    uint64_t pr = idx < n ? a.pairs[idx] : kNoPair;
-    const bool act = pr != kNoPair;
-    if (!act) pr = 0;
-    const uint32_t vi = static_cast<uint32_t>(pr), vj = static_cast<uint32_t>(pr >> 32);
-    const float dd = pair_distance<MMAX>(a.X + static_cast<uint64_t>(vi) * a.ld, a.X + static_cast<uint64_t>(vj) * a.ld,
-                                         a.metric, a.nc, P, M, l, act);
-    if (act && l == 0) {
-      const uint64_t ki = make_key(dd, vj), kj = make_key(dd, vi);
-      if (ki < a.aux[vi].worst) {
-        const uint32_t pos = atomicAdd(&scount, 1u);
-        stgt[pos] = vi;
-        skey[pos] = ki;
+  // R pairs per group and iteration: both ends' rows and worst keys of
+  // every pair are loaded before any distance is reduced
+  constexpr int R = MMAX <= 4 ? 2 : 1;
+  const uint64_t step = static_cast<uint64_t>(per_block) * R;
+  for (uint64_t b0 = static_cast<uint64_t>(blockIdx.x) * step; b0 < n; b0 += static_cast<uint64_t>(gridDim.x) * step) {
+    uint64_t pr[R], wi[R], wj[R];
+    bool act[R];
+    float4 x[R][MMAX], y[R][MMAX];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t idx = b0 + static_cast<uint64_t>(r) * per_block + threadIdx.x / P;
+      pr[r] = idx < n ? a.pairs[idx] : kNoPair;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      act[r] = pr[r] != kNoPair;
+      if (!act[r]) pr[r] = 0;
+      const uint32_t vi = static_cast<uint32_t>(pr[r]), vj = static_cast<uint32_t>(pr[r] >> 32);
+      load_row_chunks<MMAX>(x[r], a.X + static_cast<uint64_t>(vi) * a.ld, a.nc, P, M, l, act[r]);
+      load_row_chunks<MMAX>(y[r], a.X + static_cast<uint64_t>(vj) * a.ld, a.nc, P, M, l, act[r]);
+      wi[r] = wj[r] = 0;
+      if (act[r] && l == 0) {
+        wi[r] = a.aux[vi].worst;
+        wj[r] = a.aux[vj].worst;
       }
-      if (kj < a.aux[vj].worst) {
-        const uint32_t pos = atomicAdd(&scount, 1u);
-        stgt[pos] = vj;
-        skey[pos] = kj;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const float dd = chunks_distance<MMAX>(x[r], y[r], a.metric, a.nc, P, M, l, act[r]);
+      if (act[r] && l == 0) {
+        const uint32_t vi = static_cast<uint32_t>(pr[r]), vj = static_cast<uint32_t>(pr[r] >> 32);
+        const uint64_t ki = make_key(dd, vj), kj = make_key(dd, vi);
+        if (ki < wi[r]) {
+          const uint32_t pos = atomicAdd(&scount, 1u);
+          stgt[pos] = vi;
+          skey[pos] = ki;
+        }
+        if (kj < wj[r]) {
+          const uint32_t pos = atomicAdd(&scount, 1u);
+          stgt[pos] = vj;
+          skey[pos] = kj;
+        }
       }
     }
     __syncthreads();
-    if (scount + 2 * per_block > kRecheckStage) flush();
+    if (scount + 2 * step > kRecheckStage) flush();
   }
   flush();
 }
