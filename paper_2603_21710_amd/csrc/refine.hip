@@ -506,44 +506,63 @@ FGIM_DEV uint32_t wave_unique64(uint32_t v, uint32_t* out) {
 // value per lane.
 __global__ void __launch_bounds__(256) cand_kernel(JoinArgs a) {
   __shared__ uint32_t s_n[4][kMfmaMaxCn], s_o[4][kMfmaMaxCn], s_c[4][kMfmaMaxC];
-  __shared__ uint32_t s_cnt[4][2];
   const int wave = threadIdx.x / 64;
   const int lane = lane_id();
   uint32_t* arr_n = s_n[wave];
   uint32_t* arr_o = s_o[wave];
   uint32_t* cid = s_c[wave];
-  uint32_t* cnt = s_cnt[wave];
   const float gam = fp32_gamma(a.dim);
   for (uint64_t u = blockIdx.x * 4ull + wave; u < a.N; u += gridDim.x * 4ull) {
-    // forward entries, split by flag
+    // u's list, the bounds of its two reverse segments and its screen data
+    // are independent loads, issued together
     const bool in = static_cast<uint32_t>(lane) < a.k;
     const uint64_t kk = in ? a.keys[u * a.k + lane] : kSentinel;
+    const uint32_t fl = in ? a.flags[u * a.k + lane] : 0u;
+    const uint32_t o0 = a.rev_off[2 * u], o1 = a.rev_off[2 * u + 1], o2 = a.rev_off[2 * u + 2];
+    const float nrm = lane == 0 ? a.nrm2[u] : 0.0f, qe2 = lane == 0 ? a.qerr2[u] : 0.0f;
+    const uint32_t len[2] = {o1 - o0, o2 - o1};
+    const uint32_t off[2] = {o0, o1};
+    // the first 64 entries of both reverse segments
+    uint64_t first[2];
+#pragma unroll
+    for (int kind = 0; kind < 2; ++kind)
+      first[kind] = static_cast<uint32_t>(lane) < len[kind] ? a.rev[off[kind] + lane] : kSentinel;
+    // forward entries, split by flag
     const bool valid = kk != kSentinel;
-    const bool isnew = valid && (a.flags[u * a.k + lane] & kFlagNew);
+    const bool isnew = valid && (fl & kFlagNew);
     const uint64_t mn = ballot(isnew), mo = ballot(valid && !isnew);
     if (isnew) arr_n[mbcnt(mn)] = key_id(kk);
     if (valid && !isnew) arr_o[mbcnt(mo)] = key_id(kk);
-    if (lane == 0) {
-      cnt[0] = static_cast<uint32_t>(popc64(mn));
-      cnt[1] = static_cast<uint32_t>(popc64(mo));
-    }
+    uint32_t cnt[2] = {static_cast<uint32_t>(popc64(mn)), static_cast<uint32_t>(popc64(mo))};
     const uint64_t wk = readlane64(kk, static_cast<int>(a.k - 1));
     if (lane == 0) {
       CandAux x;
       x.worst = wk;
-      x.nrm2 = a.nrm2[u];
-      x.qerr = sqrtf(a.qerr2[u]) * (1.0f + gam) * 1.0001f;
+      x.nrm2 = nrm;
+      x.qerr = sqrtf(qe2) * (1.0f + gam) * 1.0001f;
       a.aux[u] = x;
     }
-    wave_lds_sync();
-    // the k_rev closest reverse entries of each kind
+    // the k_rev closest reverse entries of each kind, appended by ballot
 #pragma unroll
     for (int kind = 0; kind < 2; ++kind) {
-      const uint64_t seg = 2u * u + static_cast<uint64_t>(kind);
-      const uint32_t b0 = a.rev_off[seg], b1 = a.rev_off[seg + 1];
-      rev_top<1>(a.rev + b0, b1 - b0, a.k_rev, kind == 0 ? arr_n : arr_o, &cnt[kind]);
-      wave_lds_sync();
+      uint32_t* list = kind == 0 ? arr_n : arr_o;
+      uint64_t pick = first[kind];
+      if (len[kind] > a.k_rev) {
+        Pool<1> top;
+        top.clear();
+        top.insert_batch(first[kind], a.k_rev);
+        for (uint32_t b = 64; b < len[kind]; b += 64) {
+          const uint64_t ck = b + lane < len[kind] ? a.rev[off[kind] + b + lane] : kSentinel;
+          top.insert_batch(ck, a.k_rev);
+        }
+        pick = static_cast<uint32_t>(lane) < a.k_rev ? top.key[0] : kSentinel;
+      }
+      const bool take = pick != kSentinel;
+      const uint64_t mt = ballot(take);
+      if (take) list[cnt[kind] + mbcnt(mt)] = key_id(pick);
+      cnt[kind] += static_cast<uint32_t>(popc64(mt));
     }
+    wave_lds_sync();
     // Cn: sorted unique new ids
     const uint32_t cn = cnt[0], co = cnt[1];
     const uint32_t vn = wave_sort64(static_cast<uint32_t>(lane) < cn ? arr_n[lane] : kNone);
