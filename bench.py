@@ -246,6 +246,9 @@ def main():
                       "rounds": cfg.rounds, "R": cfg.R, "precision": precision,
                       "parallelism": "1 GPU"},
            "stages_ms": [round(x, 3) for x in np.mean(stage_ms, 0).tolist()],
+           "refine": {"proposals": st["proposals"], "rechecked": st["rechecked"], "repaired": st["repaired"],
+                      "repair_batches": st["repair_batches"], "repair_alone": st["repair_alone"],
+                      "attempts": st["refine_attempts"]},
            "roofline": roof}
     if quant_ms is not None:
         out["quantize_ms"] = round(quant_ms, 3)

@@ -139,6 +139,8 @@ typedef struct {
     double ms_tune;           /* time spent on tuner trial launches (autotune=1; 0 on a cache hit) */
     uint64_t repair_batches;  /* speculative batches of the indegree-repair passes */
     uint64_t repair_alone;    /* repair steps that needed more than one attempt (run alone) */
+    uint32_t refine_attempts; /* refinement runs: above 1 when a pair or proposal buffer
+                                 overflowed and the rounds ran again with larger ones */
 } fgim_stats;
 
 /*

@@ -72,7 +72,7 @@ class Stats(ctypes.Structure):
                 ("L_used", ctypes.c_uint32), ("lanes_per_dist", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("visited_slots", ctypes.c_uint32),
                 ("ms_tune", ctypes.c_double), ("repair_batches", ctypes.c_uint64),
-                ("repair_alone", ctypes.c_uint64)]
+                ("repair_alone", ctypes.c_uint64), ("refine_attempts", ctypes.c_uint32)]
 
     def to_dict(self) -> dict:
         d = {f: getattr(self, f) for f, _ in self._fields_ if f != "ms_stage"}

@@ -543,6 +543,7 @@ fgim_status fgim_merge(const fgim_dataset* data, const fgim_params* params, uint
     stats->rechecked = st2.rechecked;
     stats->repair_batches = st2.repair_batches;
     stats->repair_alone = st2.repair_alone;
+    stats->refine_attempts = st2.refine_attempts;
   }
   for (auto& e : ev) (void)hipEventDestroy(e);
   return FGIM_OK;

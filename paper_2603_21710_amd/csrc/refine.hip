@@ -28,6 +28,8 @@
 // order of keys, so the output is bit-identical to the sequential oracle.
 #include <string.h>
 
+#include <mutex>
+
 #include "fgim_internal.h"
 #include "graph_util.h"
 #include "mfma_util.h"
@@ -199,8 +201,8 @@ struct JoinArgs {
   uint32_t* ccnt;            // 2N: |Cn|, |Co|
   struct CandAux* aux;       // N: per-vertex screen data
   uint64_t* pairs;           // pairs passing the screen: (Cn id) | (partner id) << 32
-  uint32_t* npairs;          // pairs emitted this round (may exceed pair_cap)
-  uint32_t* npairs_max;      // largest npairs over the rounds
+  unsigned long long* npairs;      // pairs emitted this round (may exceed pair_cap; 64-bit: no wrap)
+  unsigned long long* npairs_max;  // largest npairs over the rounds
   uint32_t pair_cap;
 };
 
@@ -759,7 +761,10 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
       if (np > rem) {  // second part: a new chunk
         const uint32_t need = np - rem;
         const uint32_t sz = max(kPairChunk, need);
-        counters[8] = atomicAdd(a.npairs, sz);
+        // a chunk past the buffer starts at pair_cap, so that every position
+        // in it is dropped (and the 32-bit positions cannot wrap)
+        const unsigned long long b64 = atomicAdd(a.npairs, static_cast<unsigned long long>(sz));
+        counters[8] = b64 < a.pair_cap ? static_cast<uint32_t>(b64) : a.pair_cap;
         counters[9] = need;
         counters[10] = sz;
         counters[6] = counters[8];
@@ -803,8 +808,9 @@ __global__ void __launch_bounds__(256) recheck_kernel(JoinArgs a) {
   const int P = static_cast<int>(a.P), M = static_cast<int>(a.M);
   const int l = threadIdx.x % P;
   const uint32_t per_block = 256 / P;
-  const uint64_t n = min(*a.npairs, a.pair_cap);
-  if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(a.npairs_max, *a.npairs);
+  const uint64_t demand = *a.npairs;
+  const uint64_t n = demand < a.pair_cap ? demand : a.pair_cap;
+  if (blockIdx.x == 0 && threadIdx.x == 0) atomicMax(a.npairs_max, static_cast<unsigned long long>(demand));
   if (threadIdx.x == 0) scount = 0;
   __syncthreads();
   // proposals are staged in LDS and flushed with one global atomic per
@@ -1581,7 +1587,9 @@ struct RefineBufs {
   uint32_t* zero;
   uint64_t* zkey;
   uint32_t* newc;  // per vertex: in-edges flagged new (nullable outside refinement)
-  uint32_t* hdr;  // [0] proposals this round, [1] max per round, [2] repaired, [3] sum
+  uint32_t* hdr;  // [0] proposals this round, [1] max per round, [2] repaired, [3] sum,
+                  // [4] rechecked, [5] repair batches, [6] run alone, [16..17] pairs
+                  // this round and [18..19] their largest count (64-bit)
   uint32_t* scan_tmp;
   uint64_t* sub_off;
 };
@@ -1660,7 +1668,7 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   // Update
   if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
   if (rp.use_mfma) {
-    if ((e = fill_u32(rp.ja.npairs, 0u, 1, s)) != hipSuccess) return e;
+    if ((e = fill_u32(reinterpret_cast<uint32_t*>(rp.ja.npairs), 0u, 2, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(cand_kernel, dim3(rp.cand_grid), dim3(256), 0, s, rp.ja);
     hipLaunchKernelGGL(join_mfma_kernel, dim3(rp.join_grid), dim3(256), rp.join_smem, s, rp.ja);
     if (rp.mmax == 4)
@@ -1699,6 +1707,11 @@ __global__ void check_ids_kernel(const uint32_t* ids, uint64_t nk, uint64_t N, u
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
     if (ids[i] != kNone && ids[i] >= N) atomicOr(err, 1u);
 }
+
+// largest proposals and screened pairs per vertex that a refinement round
+// has needed in this process (sizes the buffers of later calls)
+std::mutex g_demand_mu;
+double g_props_per_vertex = 0.0, g_pairs_per_vertex = 0.0;
 
 // Stage 2 on the lists (ids, dist).  Lists from a caller are checked first
 // (an id >= n would index the indegrees out of bounds); the merge passes its
@@ -1747,12 +1760,19 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   const size_t mfma_smem = mfma_head + static_cast<size_t>(kMfmaMaxC) * (slice + 8) * 2;
 
   uint64_t cap = std::max<uint64_t>(N * std::max<uint32_t>(4 * p->k, 64), 1 << 16);
-  cap = std::min<uint64_t>(cap, 0xF0000000ull);
   // pairs passing the screen: about k per vertex in the first round at
-  // k = 32; an overflow re-runs with a larger buffer
-  uint64_t pair_cap = std::min<uint64_t>(std::max<uint64_t>(N * 3 * p->k, 1 << 16) +
-                                             static_cast<uint64_t>(device_cus()) * 8 * kPairChunk,
-                                         0xF0000000ull);
+  // k = 32 on clustered data, several times that on others; an overflow
+  // re-runs the rounds with larger buffers, and the per-vertex demand seen
+  // so far sizes the buffers of later calls
+  uint64_t pair_cap = std::max<uint64_t>(N * 3 * p->k, 1 << 16) + static_cast<uint64_t>(device_cus()) * 8 * kPairChunk;
+  {
+    std::lock_guard<std::mutex> lock(g_demand_mu);
+    cap = std::max<uint64_t>(cap, static_cast<uint64_t>(g_props_per_vertex * 1.25 * static_cast<double>(N)) + 1024);
+    pair_cap = std::max<uint64_t>(pair_cap, static_cast<uint64_t>(g_pairs_per_vertex * 1.25 * static_cast<double>(N)) +
+                                                static_cast<uint64_t>(device_cus()) * 8 * kPairChunk);
+  }
+  cap = std::min<uint64_t>(cap, 0xF0000000ull);
+  pair_cap = std::min<uint64_t>(pair_cap, 0xF0000000ull);
 
   for (int attempt = 0; attempt < 3; ++attempt) {
     Scratch scr(s);
@@ -1775,7 +1795,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     FGIM_TRY(scr.get(&b.zoff, N + 1));
     FGIM_TRY(scr.get(&b.zero, N + 1));
     FGIM_TRY(scr.get(&b.zkey, N + 1));
-    FGIM_TRY(scr.get(&b.hdr, 16));
+    FGIM_TRY(scr.get(&b.hdr, 24));
     float *nrm2 = nullptr, *qerr2 = nullptr;
     uint32_t *cand = nullptr, *ccnt = nullptr;
     uint16_t* xb = nullptr;
@@ -1802,7 +1822,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     std::vector<uint64_t> hoff(d->h);
     for (uint32_t i = 0; i < d->h; ++i) hoff[i] = d->subs[i].row_offset;
     HIP_TRY(hipMemcpyAsync(b.sub_off, hoff.data(), 8 * d->h, hipMemcpyHostToDevice, s));
-    HIP_TRY(fill_u32(b.hdr, 0u, 16, s));
+    HIP_TRY(fill_u32(b.hdr, 0u, 24, s));
     hipLaunchKernelGGL(to_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, ids, dist, nk, b.keys, b.flags);
     HIP_TRY(hipGetLastError());
     // indegrees of the input lists, all of whose entries are new; apply and
@@ -1851,8 +1871,8 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     ja.ccnt = ccnt;
     ja.aux = aux;
     ja.pairs = pairs;
-    ja.npairs = b.hdr + 8;
-    ja.npairs_max = b.hdr + 9;
+    ja.npairs = reinterpret_cast<unsigned long long*>(b.hdr + 16);
+    ja.npairs_max = reinterpret_cast<unsigned long long*>(b.hdr + 18);
     ja.pair_cap = static_cast<uint32_t>(pair_cap);
     rp.use_mfma = use_mfma;
     rp.join_smem = use_mfma ? mfma_smem : base_smem + (stage_rows ? rows_smem : 0);
@@ -1911,13 +1931,19 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     } else {
       for (uint32_t r = 0; r < p->rounds; ++r) HIP_TRY(run_round(rp, b, s));
     }
-    uint32_t hh[16] = {};
+    uint32_t hh[24] = {};
     HIP_TRY(hipMemcpyAsync(hh, b.hdr, sizeof(hh), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    if (hh[1] > cap || hh[9] > pair_cap) {
+    const uint64_t pairs_max = static_cast<uint64_t>(hh[18]) | (static_cast<uint64_t>(hh[19]) << 32);
+    {
+      std::lock_guard<std::mutex> lock(g_demand_mu);
+      g_props_per_vertex = std::max(g_props_per_vertex, static_cast<double>(hh[1]) / static_cast<double>(N));
+      g_pairs_per_vertex = std::max(g_pairs_per_vertex, static_cast<double>(pairs_max) / static_cast<double>(N));
+    }
+    if (hh[1] > cap || pairs_max > pair_cap) {
       // a buffer overflowed: run again with larger ones (same result)
       if (hh[1] > cap) cap = std::min<uint64_t>(static_cast<uint64_t>(hh[1]) * 5 / 4 + 1024, 0xF0000000ull);
-      if (hh[9] > pair_cap) pair_cap = std::min<uint64_t>(static_cast<uint64_t>(hh[9]) * 5 / 4 + 1024, 0xF0000000ull);
+      if (pairs_max > pair_cap) pair_cap = std::min<uint64_t>(pairs_max * 5 / 4 + 1024, 0xF0000000ull);
       continue;
     }
     hipLaunchKernelGGL(from_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, ids, dist);
@@ -1934,6 +1960,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
       stats->rechecked = hh[4];
       stats->repair_batches = hh[5];
       stats->repair_alone = hh[6];
+      stats->refine_attempts = static_cast<uint32_t>(attempt + 1);
       (void)hipEventDestroy(e0);
       (void)hipEventDestroy(e1);
     }
