@@ -120,6 +120,9 @@ typedef struct {
 #define FGIM_FLAG_NO_MFMA_SCREEN 4u /* score every join pair and every occlusion pair of the
                                        neighbour selection in FP32 instead of screening the
                                        tiles on MFMA first (same result; test hook) */
+#define FGIM_FLAG_MIN_BUFFERS 8u   /* start the refinement's screened-pair and proposal buffers
+                                      at their minimum (2^16 entries), ignoring the demand seen
+                                      before, so that the overflow-and-rerun path runs (test hook) */
 
 /* Per-call counters; passing a non-NULL stats pointer synchronises the
  * stream at the end of the call. */

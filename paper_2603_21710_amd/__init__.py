@@ -24,6 +24,7 @@ FGIM_FP32, FGIM_BF16, FGIM_FP8_E4M3 = 0, 1, 2
 FGIM_FLAG_NO_REPAIR = 1
 FGIM_FLAG_NO_GRAPH_CAPTURE = 2
 FGIM_FLAG_NO_MFMA_SCREEN = 4
+FGIM_FLAG_MIN_BUFFERS = 8
 METRICS = {"l2": FGIM_L2, "ip": FGIM_IP, "cos": FGIM_COSINE}
 PRECISIONS = {"fp32": FGIM_FP32, "bf16": FGIM_BF16, "fp8": FGIM_FP8_E4M3}
 

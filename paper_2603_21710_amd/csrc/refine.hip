@@ -1765,7 +1765,10 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   // re-runs the rounds with larger buffers, and the per-vertex demand seen
   // so far sizes the buffers of later calls
   uint64_t pair_cap = std::max<uint64_t>(N * 3 * p->k, 1 << 16) + static_cast<uint64_t>(device_cus()) * 8 * kPairChunk;
-  {
+  if (p->flags & FGIM_FLAG_MIN_BUFFERS) {
+    cap = 1 << 16;
+    pair_cap = 1 << 16;
+  } else {
     std::lock_guard<std::mutex> lock(g_demand_mu);
     cap = std::max<uint64_t>(cap, static_cast<uint64_t>(g_props_per_vertex * 1.25 * static_cast<double>(N)) + 1024);
     pair_cap = std::max<uint64_t>(pair_cap, static_cast<uint64_t>(g_pairs_per_vertex * 1.25 * static_cast<double>(N)) +
@@ -1942,8 +1945,10 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     }
     if (hh[1] > cap || pairs_max > pair_cap) {
       // a buffer overflowed: run again with larger ones (same result)
-      if (hh[1] > cap) cap = std::min<uint64_t>(static_cast<uint64_t>(hh[1]) * 5 / 4 + 1024, 0xF0000000ull);
-      if (pairs_max > pair_cap) pair_cap = std::min<uint64_t>(pairs_max * 5 / 4 + 1024, 0xF0000000ull);
+      // later rounds of a truncated run may have needed less than a full
+      // run does: at least double the buffer that overflowed
+      if (hh[1] > cap) cap = std::min<uint64_t>(std::max<uint64_t>(static_cast<uint64_t>(hh[1]) * 5 / 4, 2 * cap) + 1024, 0xF0000000ull);
+      if (pairs_max > pair_cap) pair_cap = std::min<uint64_t>(std::max<uint64_t>(pairs_max * 5 / 4, 2 * pair_cap) + 1024, 0xF0000000ull);
       continue;
     }
     hipLaunchKernelGGL(from_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, ids, dist);

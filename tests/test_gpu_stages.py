@@ -133,6 +133,21 @@ def test_scratch_arena_reuse_and_release():
     assert torch.equal(pg, ref)
 
 
+def test_buffer_overflow_reruns_to_the_same_result():
+    """Refinement buffers that start too small overflow; the rounds run again
+    with larger ones and give the result of a run that never overflowed."""
+    cfg, X, graphs, _ = workload("cfg1", None)
+    m = to_gpu(X, graphs, cfg.metric)
+    p = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds)
+    ref, rdeg, rent, st0 = fg.merge(m, p, stats=True)
+    small = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds, flags=fg.FGIM_FLAG_MIN_BUFFERS)
+    pg, deg, ent, st = fg.merge(m, small, stats=True)
+    print(f"attempts {st['refine_attempts']} (normal {st0['refine_attempts']})", flush=True)
+    assert st["refine_attempts"] >= 2
+    assert torch.equal(pg, ref) and torch.equal(deg, rdeg) and ent == rent
+    assert st["proposals"] == st0["proposals"] and st["rechecked"] == st0["rechecked"]
+
+
 def test_refine_rejects_out_of_range_ids():
     cfg, X, graphs, m, ids, dist = _stage1("cfg1", None)
     bad = ids.clone()
