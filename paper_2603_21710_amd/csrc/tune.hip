@@ -31,8 +31,9 @@
 namespace fgim {
 namespace {
 
-constexpr uint64_t kShapeSample = 131072;  // vertices per shape trial
-constexpr uint64_t kWidthSample = 16384;   // vertices per beam-width trial
+constexpr uint64_t kShapeSearches = 131072;    // searches per shape trial (h - 1 per vertex)
+constexpr uint64_t kShapeMinVertices = 8192;   // ... from at least this many vertices
+constexpr uint64_t kWidthSample = 16384;       // vertices per beam-width trial
 constexpr double kWidthAgreement = 0.99;   // share of the configured-L ids kept
 
 std::mutex g_mu;
@@ -117,6 +118,12 @@ uint64_t layout_hash(const fgim_dataset* d) {
     mix(d->subs[i].entry);
   }
   return hsh;
+}
+
+// vertices a shape trial searches from: about kShapeSearches searches
+uint64_t shape_sample(const fgim_dataset* d) {
+  const uint64_t per = d->h > 1 ? d->h - 1 : 1;
+  return std::min<uint64_t>(d->n_total, std::max<uint64_t>(kShapeMinVertices, kShapeSearches / per));
 }
 
 uint32_t pow2_at_least(uint32_t x) {
@@ -230,7 +237,7 @@ fgim_status tune_shape(BeamArgs a, const fgim_dataset* d, const fgim_params* p, 
     if (beam_shape(d->dim, L, p->k, &q, out) == FGIM_OK) return FGIM_OK;
   }
   *ran = true;
-  const uint64_t S = std::min<uint64_t>(d->n_total, kShapeSample);
+  const uint64_t S = shape_sample(d);
   a.n_items = S;
   a.item_stride = d->n_total / S;
   a.L = L;
@@ -242,10 +249,12 @@ fgim_status tune_shape(BeamArgs a, const fgim_dataset* d, const fgim_params* p, 
   else
     for (uint32_t P = 1; P <= 64; P <<= 1)
       if (P <= N && N / P <= 16 && P * 8 >= N) Ps.push_back(P);
+  // 24 waves per CU never differed from 32 by more than noise, and 512 slots
+  // never won: they are left out of the grid
   if (p->waves_per_cu) Ws.push_back(p->waves_per_cu);
-  else Ws = {16, 24, 32};
+  else Ws = {16, 32};
   if (p->visited_slots) Vs.push_back(p->visited_slots);
-  else Vs = {512, 1024, 2048, 4096};
+  else Vs = {1024, 2048, 4096};
 
   struct Cand {
     float ms;
@@ -304,7 +313,7 @@ fgim_status tune_stage1(const BeamArgs& a0, const fgim_dataset* d, const fgim_pa
   HIP_TRY(hipEventCreate(&ev.e0));
   HIP_TRY(hipEventCreate(&ev.e1));
   Scratch scr(s);
-  const uint64_t S = std::min<uint64_t>(d->n_total, std::max(kShapeSample, kWidthSample));
+  const uint64_t S = std::max(shape_sample(d), std::min<uint64_t>(d->n_total, kWidthSample));
   BeamArgs a = a0;
   FGIM_TRY(scr.get(&a.out_ids, S * p->k));
   FGIM_TRY(scr.get(&a.out_dist, S * p->k));
