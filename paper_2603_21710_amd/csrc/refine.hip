@@ -652,8 +652,9 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
     floatx4_t acc[kMfmaTilesPerWave];
 #pragma unroll
     for (uint32_t t = 0; t < kMfmaTilesPerWave; ++t) acc[t] = floatx4_t{0.f, 0.f, 0.f, 0.f};
-    // BF16 slices of the dimensions through LDS
-    for (uint32_t s0 = 0; s0 < a.dpad; s0 += a.slice) {
+    // BF16 slices of the dimensions through LDS (none when the vertex has
+    // no new candidate: then it has no tile and no pair; T is uniform)
+    for (uint32_t s0 = 0; T > 0 && s0 < a.dpad; s0 += a.slice) {
       const uint32_t sw = min(a.slice, a.dpad - s0);   // multiple of 32
       __syncthreads();
       const uint32_t per_row = sw / 8;
