@@ -4,8 +4,12 @@
 // Lists are held as sorted uint64 keys (delta, id) plus a flag word per slot
 // (bit 0 new, bit 1 replaced); the indegrees T and the counts of new
 // in-edges are kept current by apply and repair.  One round is a fixed
-// sequence of kernels with no host round trip, so it is captured once in a
-// hipGraph and replayed:
+// sequence of kernels with no host round trip: the first round runs
+// directly while the host captures one round into a hipGraph, and the other
+// rounds replay it.  The screened-pair and proposal buffers are sized from
+// the demand seen in earlier calls; a round that needs more is detected at
+// the end (64-bit demand counters) and the rounds run again with larger
+// buffers.
 //   Visit   reverse-list sizes from the maintained counts, scan, rev_scatter:
 //           reverse lists of new and old entries as a CSR (segment 2v: u
 //           with v new in u's list, 2v+1: old)
@@ -15,14 +19,16 @@
 //           other when it beats that end's current worst entry.  When
 //           |Cn| + |Co| <= 128: cand_kernel builds the sets, join_mfma_kernel
 //           screens the pairs on MFMA with a rigorous error bound and
-//           recheck_kernel scores the survivors in canonical FP32; otherwise
+//           recheck_kernel scores the survivors in canonical FP32 (a vertex
+//           without a new candidate has no pair and stages no row); otherwise
 //           join_kernel scores every pair in FP32 from rows staged in LDS.
 //           Proposals are appended to a global buffer and grouped by target
 //           with a CSR pass.
 //   apply   per target: first k of the snapshot list (entries turn old) and
 //           its proposals (entries new), one entry per id.
 //   repair  ordered list of zero-indegree vertices, then Algorithm 4 in one
-//           workgroup in order-exact speculative batches.
+//           workgroup in order-exact speculative batches (two steps per
+//           wavefront slot for k <= 32).
 // Every step's result is independent of scheduling: CSR segments are
 // consumed through order-independent top-k selections under the total
 // order of keys, so the output is bit-identical to the sequential oracle.
