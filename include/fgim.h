@@ -23,8 +23,9 @@
  *  - Every list is sorted by (delta ascending, id ascending); ties are
  *    broken by id everywhere.
  *  - Pointers marked "device" are HIP device pointers; the caller owns all
- *    buffers and the library never frees them.  Scratch memory is allocated
- *    stream-ordered on `stream` and released before the call returns.
+ *    buffers and the library never frees them.  Temporary buffers come from
+ *    a per-device scratch arena that the library keeps between calls (see
+ *    fgim_release_scratch).
  *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream).
  *    Argument errors are returned before anything is enqueued.  Calls that
  *    must report FGIM_ERR_GRAPH (or fill a host-side result) synchronise the
@@ -32,9 +33,11 @@
  *  - With precision FGIM_FP32 the outputs do not depend on launch
  *    configuration (lanes per distance, waves per CU, visited-cache size):
  *    they are bit-identical across runs and tuning choices.
- *  - Outputs are undefined after any error.  Calls on the same device that
- *    overlap in time are independent (no shared state) unless they write the
- *    same buffers.
+ *  - Outputs are undefined after any error.  Calls on one device share its
+ *    scratch arena: they run one at a time on the host (other threads wait),
+ *    and each call's device work starts after that of the previous call.
+ *    The tuner's decisions and the refinement's buffer sizes seen so far are
+ *    the only other state kept between calls; neither changes a result.
  */
 #ifndef FGIM_H
 #define FGIM_H
