@@ -36,8 +36,9 @@
  *  - Outputs are undefined after any error.  Calls on one device share its
  *    scratch arena: they run one at a time on the host (other threads wait),
  *    and each call's device work starts after that of the previous call.
- *    The tuner's decisions and the refinement's buffer sizes seen so far are
- *    the only other state kept between calls; neither changes a result.
+ *    The only other state kept between calls is the tuner's cache (used
+ *    with autotune = 1 only) and the refinement's buffer demand seen so far
+ *    (it sizes buffers and never changes a result).
  */
 #ifndef FGIM_H
 #define FGIM_H
