@@ -158,13 +158,17 @@ __global__ void copy_u32_kernel(const uint32_t* a, uint32_t* b, uint64_t n) {
 // Visit: reverse lists
 
 // reverse entry of v in u's list: key (stored delta, u)
+// old entries of an inactive vertex's reverse list are not placed: no
+// join reads them (see rev_sizes_kernel)
 __global__ void rev_scatter_kernel(const uint64_t* keys, const uint32_t* flags, uint64_t nk, uint32_t k,
-                                   uint32_t* cur, uint64_t* rev) {
+                                   const uint32_t* active, uint32_t* cur, uint64_t* rev) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const uint64_t kk = keys[i];
     if (kk == kSentinel) continue;
-    const uint32_t seg = 2u * key_id(kk) + ((flags[i] & kFlagNew) ? 0u : 1u);
+    const bool isnew = flags[i] & kFlagNew;
+    if (!isnew && !active[key_id(kk)]) continue;
+    const uint32_t seg = 2u * key_id(kk) + (isnew ? 0u : 1u);
     const uint32_t pos = atomicAdd(&cur[seg], 1u);
     rev[pos] = (kk & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(i / k);
   }
@@ -959,12 +963,21 @@ __global__ void __launch_bounds__(256) apply_kernel(uint64_t* keys, uint32_t* fl
 
 // reverse-list segment sizes of the next Visit from the maintained counts:
 // 2v holds v's new in-edges, 2v+1 its old ones
-__global__ void rev_sizes_kernel(const uint32_t* T, const uint32_t* newc, uint64_t N, uint32_t* cnt) {
+// Reverse-list sizes from the maintained counts.  A vertex is active when
+// its list holds a new entry or it has a new in-edge: otherwise its Cn is
+// empty, its join forms no pair and reads no reverse entry, so its old
+// reverse segment is left empty (the reverse lists of new entries are
+// always complete).
+__global__ void rev_sizes_kernel(const uint32_t* T, const uint32_t* newc, const uint32_t* flags, uint32_t k,
+                                 uint64_t N, uint32_t* cnt, uint32_t* active) {
   for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < N;
        v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const uint32_t n = newc[v];
+    bool act = n > 0;
+    for (uint32_t e = 0; e < k && !act; ++e) act = (flags[v * k + e] & kFlagNew) != 0;
+    active[v] = act ? 1u : 0u;
     cnt[2 * v] = n;
-    cnt[2 * v + 1] = T[v] - n;
+    cnt[2 * v + 1] = act ? T[v] - n : 0u;
   }
 }
 
@@ -1666,11 +1679,13 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   hipError_t e;
   // Visit: reverse-list sizes from the maintained indegrees (T) and new
   // in-edge counts, then the reverse CSR
-  hipLaunchKernelGGL(rev_sizes_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, b.newc, N, b.rev_cnt);
+  // (b.zmask holds the active flags until the repair reuses it)
+  hipLaunchKernelGGL(rev_sizes_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, b.newc, b.flags, rp.k, N, b.rev_cnt,
+                     b.zmask);
   if ((e = exclusive_scan(b.rev_cnt, b.rev_off, 2 * N, b.scan_tmp, s)) != hipSuccess) return e;
   if ((e = fill_u32(b.newc, 0u, N, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(2 * N)), dim3(256), 0, s, b.rev_off, b.rev_cur, 2 * N);
-  hipLaunchKernelGGL(rev_scatter_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, b.rev_cur,
+  hipLaunchKernelGGL(rev_scatter_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, b.zmask, b.rev_cur,
                      b.rev);
   // Update
   if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
