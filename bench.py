@@ -17,6 +17,7 @@ from __future__ import annotations
 
 import argparse
 import hashlib
+import re
 import json
 import os
 import sys
@@ -40,10 +41,16 @@ def log(*a):
 
 
 def beam_source_hash() -> str:
+    """sha256 of the beam-kernel sources with comments and blank space
+    removed: a comment edit keeps committed counters valid, a code edit
+    does not."""
     h = hashlib.sha256()
     for p in BEAM_SOURCES:
-        with open(os.path.join(ROOT, p), "rb") as f:
-            h.update(f.read())
+        with open(os.path.join(ROOT, p)) as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
     return h.hexdigest()[:16]
 
 

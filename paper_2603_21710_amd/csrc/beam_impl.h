@@ -14,9 +14,9 @@
 // gathers, canonical sum, xor-butterfly reduction) and inserts the keys that
 // beat the current L-th entry.
 //
-// Visited cache.  The cache is direct-mapped and may forget ids (a later id
-// with the same slot overwrites an earlier one); it never reports an id that
-// was not scored in this search.  Forgetting cannot change the result: a
+// Visited cache.  The cache holds whole ids in two-choice slots and may
+// forget ids (a new id overwrites an occupied slot when both of its slots
+// are taken); it never reports an id that was not scored in this search.  Forgetting cannot change the result: a
 // re-scored id is either still in the pool -- its key is identical, so the
 // insertion sees a duplicate and drops it -- or it left the pool earlier,
 // which means its key exceeded the L-th key at that time; the L-th key never

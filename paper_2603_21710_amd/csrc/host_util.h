@@ -1,5 +1,5 @@
 // Host helpers shared by the library's translation units: error reporting,
-// stream-ordered scratch, launch helpers and dataset validation.
+// the scratch arena, launch helpers and dataset validation.
 #pragma once
 
 #include <hip/hip_runtime.h>
