@@ -574,6 +574,14 @@ __global__ void __launch_bounds__(256) cand_kernel(JoinArgs a) {
       if (take) list[cnt[kind] + mbcnt(mt)] = key_id(pick);
       cnt[kind] += static_cast<uint32_t>(popc64(mt));
     }
+    // no new candidate: no pair, so no set (the join skips the vertex)
+    if (cnt[0] == 0) {
+      if (lane == 0) {
+        a.ccnt[2 * u] = 0;
+        a.ccnt[2 * u + 1] = 0;
+      }
+      continue;
+    }
     wave_lds_sync();
     // Cn: sorted unique new ids
     const uint32_t cn = cnt[0], co = cnt[1];
