@@ -317,21 +317,20 @@ def knng_recall(X, ids, nodes, k: int, metric: str = "l2", threads=None) -> floa
 
 
 def _tie_recall(X, Q, found, kth, k, metric) -> float:
-    X = np.asarray(X, dtype=np.float64)
-    Q = np.asarray(Q, dtype=np.float64)
+    """Tie-aware recall: a found id counts when its FP64 distance, computed
+    by the same loop as the brute force's (so equal ids give equal bits), is
+    at most the true k-th distance."""
+    X, Q = _f32(X), _f32(Q)
+    f64 = lib().oracle_distance64
+    m = METRICS[metric]
     hit = 0
     for i in range(found.shape[0]):
-        f = found[i, :k]
-        f = f[f != NONE].astype(np.int64)
-        if f.size == 0:
-            continue
-        if metric == "l2":
-            d = ((X[f] - Q[i]) ** 2).sum(1)
-        elif metric == "ip":
-            d = -(X[f] @ Q[i])
-        else:
-            d = 1.0 - X[f] @ Q[i]
-        hit += int((d <= kth[i]).sum())
+        q = Q[i]
+        for v in found[i, :k]:
+            if v == NONE:
+                continue
+            x = X[int(v)]
+            hit += f64(_p(q), _p(x), X.shape[1], m) <= kth[i]
     return hit / float(found.shape[0] * k)
 
 

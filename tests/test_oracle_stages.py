@@ -183,6 +183,72 @@ def test_stage1_rerank_with_identical_copy_matches_fp32():
     assert (a == b).all() and (ad == bd).all()
 
 
+def _stage1_from_parts(X, Xs, subs, u, k, L, keep, metric, score_on):
+    """Stage 1 of vertex u rebuilt from its parts: C+(u) scored on X, plus the
+    first `keep` results of Algorithm 1 (oracle.knn_search, pinned by the
+    hand trace) run on the copy Xs in every other sub-index, each re-scored
+    on `score_on`; sorted by (delta, id) and cut to k."""
+    offs = [s[0] for s in subs]
+    g = int(np.searchsorted(offs, u, side="right") - 1)
+    off, adj, _ = subs[g]
+    cand = [(oracle.distance(X[u], X[off + int(v)], metric), off + int(v))
+            for v in adj[u - off] if v != NONE]
+    for j, (offj, adjj, ej) in enumerate(subs):
+        if j == g:
+            continue
+        n = adjj.shape[0]
+        ids, _, _, _ = oracle.knn_search(X[u], Xs[offj:offj + n], adjj, ej, L, metric)
+        for v in ids[:keep]:
+            gv = offj + int(v)
+            cand.append((oracle.distance(X[u], score_on[gv], metric), gv))
+    cand.sort()
+    return cand[:k]
+
+
+@pytest.mark.parametrize("metric,k,L,rerank", [("l2", 16, 32, 8), ("l2", 16, 32, 20),
+                                               ("ip", 12, 24, 12)])
+def test_stage1_rerank_branch_with_a_distinct_copy(metric, k, L, rerank):
+    # The low-precision form: the beam scores a copy Xs that differs from X,
+    # each search keeps its first `rerank` results, and those are re-scored
+    # on the FP32 rows before the union (rerank < L; the first case also has
+    # rerank < k).  Xs = X + noise comparable to the spread of a cluster, so
+    # that the copy's search order differs from X's.
+    name = "cfg1ov" if metric == "l2" else "cfg3ov"
+    cfg, X, subs = _cfg_small(name, sizes=(500, 400, 300))
+    rng = np.random.default_rng(31)
+    scale = 0.5 if metric == "l2" else 0.05
+    Xs = (X + rng.normal(0, scale, X.shape)).astype(np.float32)
+    nodes = np.arange(0, X.shape[0], 23, dtype=np.uint64)
+    ids, dd, _ = oracle.cross_query(X, subs, k, L, metric, nodes=nodes, Xs=Xs, rerank=rerank)
+    wrong_count = wrong_rows = 0
+    for r, u in enumerate(nodes.astype(np.int64)):
+        want = _stage1_from_parts(X, Xs, subs, u, k, L, rerank, metric, X)
+        got = [(float(dd[r, t]), int(ids[r, t])) for t in range(k) if ids[r, t] != NONE]
+        assert got == want, f"vertex {u}"
+        # every distance is the FP32 distance of its id on the FP32 rows
+        for d, v in got:
+            assert d == oracle.distance(X[u], X[v], metric)
+        # the two plausible mistakes give other lists on this input
+        wrong_count += _stage1_from_parts(X, Xs, subs, u, k, L, L, metric, X) != want
+        wrong_rows += _stage1_from_parts(X, Xs, subs, u, k, L, rerank, metric, Xs) != want
+    assert wrong_count > 0 and wrong_rows > 0
+
+
+def test_merged_entry_on_unequal_subindexes():
+    # The merged entry is the entry of the largest sub-index, the lowest
+    # index among equal sizes, as a global id.
+    def subs(sizes, entries):
+        out, off = [], 0
+        for n, e in zip(sizes, entries):
+            out.append((off, np.zeros((n, 1), np.uint32), e))
+            off += n
+        return out
+    assert oracle.merged_entry(subs((300, 700, 700, 200), (5, 11, 17, 3))) == 311
+    assert oracle.merged_entry(subs((100, 50, 400), (1, 2, 7))) == 157
+    assert oracle.merged_entry(subs((90, 40), (89, 0))) == 89
+    assert oracle.merged_entry(subs((40, 90), (0, 89))) == 129
+
+
 def test_join_keeps_exact_knng():
     # An exact k-NNG is a fixed point of Update: no pair can beat an entry of
     # a true k-NN list (repair off, so only the join acts).
@@ -297,3 +363,35 @@ def test_evaluation_ground_truth_matches_oracle():
         assert tie_recall(X, Q, gi.astype(np.uint32), od[:, -1], 10, metric) == 1.0
     wrong = np.full((50, 10), 0xFFFFFFFF, np.uint32)
     assert tie_recall(X, Q, wrong, od[:, -1], 10, "ip") == 0.0
+
+
+@pytest.mark.parametrize("metric", ["l2", "ip", "cos"])
+def test_recall_of_the_exact_answer_is_one_on_float_data(metric):
+    # On float data the Gram form (|q|^2 + |x|^2 - 2<q,x>) and the direct
+    # form of a distance differ in the last bits.  The ground truth is
+    # re-ranked by the direct form that scores returned ids, so the exact
+    # answer -- the oracle's FP64 brute force, an independent loop -- scores
+    # exactly 1.0 and the truth's ids are the oracle's.
+    from workloads.evaluate import exact_knn_fp64, tie_recall
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(4000, 96)).astype(np.float32)
+    Q = rng.normal(size=(300, 96)).astype(np.float32)
+    if metric == "cos":
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    gi, gd = exact_knn_fp64(X, Q, 10, metric)
+    oi, od = oracle.bruteforce(X, Q, 10, metric)
+    assert (gi == oi.astype(np.int64)).all()
+    assert np.allclose(gd, od, rtol=1e-12, atol=1e-12)
+    assert tie_recall(X, Q, oi, gd[:, -1], 10, metric) == 1.0
+    assert tie_recall(X, Q, gi.astype(np.uint32), gd[:, -1], 10, metric) == 1.0
+    # one wrong id per query costs exactly 1/10
+    worse = oi.copy()
+    worse[:, 0] = oracle.bruteforce(X, Q, 40, metric)[0][:, 39]
+    assert tie_recall(X, Q, worse, gd[:, -1], 10, metric) == pytest.approx(0.9)
+    # the k-NNG form (each point's own id excluded)
+    nodes = np.arange(0, 4000, 50)
+    ki, kd = exact_knn_fp64(X, X[nodes], 10, metric, exclude=nodes)
+    bi, bd = oracle.bruteforce(X, X[nodes], 10, metric, exclude=nodes)
+    assert (ki == bi.astype(np.int64)).all()
+    assert tie_recall(X, X[nodes], bi, kd[:, -1], 10, metric) == 1.0

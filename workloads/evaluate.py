@@ -3,8 +3,13 @@
 Recall@k = |R ∩ R~| / k (Section 2.1).  A returned id counts as correct when
 its FP64 distance to the query is at most the FP64 distance of the true k-th
 neighbour, so ties at the k-th place are not penalised (integer-valued data
-has real ties).  The ground truth runs on the CPU in float64 with torch's
-multi-threaded matmul; it is evaluation arithmetic, not part of the merge.
+has real ties).  The ground truth runs on the CPU in float64: torch's
+multi-threaded matmul (Gram form |q|^2 + |x|^2 - 2<q,x>) picks a shortlist,
+which is re-ranked by the direct form that dist64_rows also uses to score
+returned ids.  Both sides of the comparison "distance <= k-th distance" are
+then the same function of the same rows, so the exact answer scores 1.0 on
+float data too (the Gram and direct forms differ in the last bits).  It is
+evaluation arithmetic, not part of the merge.
 """
 
 from __future__ import annotations
@@ -25,24 +30,65 @@ def _dist64(Xb: torch.Tensor, sqb: torch.Tensor, Q: torch.Tensor, metric: str) -
 
 
 def exact_knn_fp64(X: np.ndarray, Q: np.ndarray, k: int, metric: str = "l2",
-                   exclude: np.ndarray | None = None, block: int = 256):
-    """(ids int64 [nq, k], dists float64 [nq, k]) of the exact k-NN in FP64.
-    exclude[i] (optional) is a base id removed from query i's candidates."""
+                   exclude: np.ndarray | None = None, block: int = 256, margin: int = 16):
+    """(ids int64 [nq, k], dists float64 [nq, k]) of the exact k-NN in FP64,
+    ordered by (distance, id); the distances are dist64_rows' direct form.
+    exclude[i] (optional) is a base id removed from query i's candidates.
+
+    The Gram form picks the k + margin closest candidates; they are re-scored
+    in the direct form and the first k kept.  The Gram form's error is below
+    tol = 1e-9 (|q|^2 + max|x|^2) (its rounding is ~1e-16 of those terms),
+    so a true k-th neighbour can only be missed when the shortlist's last
+    Gram distance lies within 2 tol of the direct k-th distance; such queries
+    are recomputed directly over every base row."""
     Xt = torch.from_numpy(np.ascontiguousarray(X)).to(torch.float64)
     sq = (Xt * Xt).sum(1)
     Qt = torch.from_numpy(np.ascontiguousarray(Q)).to(torch.float64)
-    nq = Qt.shape[0]
+    nq, n = Qt.shape[0], Xt.shape[0]
+    m = min(n, k + margin)
     ids = np.empty((nq, k), np.int64)
     dd = np.empty((nq, k), np.float64)
+    sqmax = float(sq.max()) if n else 0.0
     for s in range(0, nq, block):
         e = min(nq, s + block)
         D = _dist64(Xt, sq, Qt[s:e], metric)
         if exclude is not None:
             ex = torch.from_numpy(np.asarray(exclude[s:e], np.int64))
             D[torch.arange(e - s), ex] = float("inf")
-        v, i = torch.topk(D, k, dim=1, largest=False, sorted=True)
-        ids[s:e], dd[s:e] = i.numpy(), v.numpy()
+        v, i = torch.topk(D, m, dim=1, largest=False, sorted=True)
+        cand = i.numpy()
+        dc = dist64_rows(X, Q[s:e], cand.astype(np.uint32), metric)
+        if exclude is not None:
+            dc[cand == np.asarray(exclude[s:e], np.int64)[:, None]] = np.inf
+        order = np.lexsort((cand, dc), axis=1)
+        cs = np.take_along_axis(cand, order, 1)[:, :k]
+        ds = np.take_along_axis(dc, order, 1)[:, :k]
+        tol = 1e-9 * ((Qt[s:e] * Qt[s:e]).sum(1).numpy() + sqmax + 1.0)
+        last = v.numpy()[:, -1]
+        for r in np.nonzero((m < n) & (last <= ds[:, -1] + 2 * tol))[0]:
+            ex = None if exclude is None else int(exclude[s + r])
+            cs[r], ds[r] = _direct_knn_one(X, Q[s + r], k, metric, ex)
+        ids[s:e], dd[s:e] = cs, ds
     return ids, dd
+
+
+def _direct_knn_one(X: np.ndarray, q: np.ndarray, k: int, metric: str, exclude=None,
+                    chunk: int = 1 << 18):
+    """Exact k-NN of one query by the direct FP64 form over every base row,
+    in chunks of rows: (ids int64 [k], dists float64 [k])."""
+    best_i = np.empty(0, np.int64)
+    best_d = np.empty(0, np.float64)
+    for c0 in range(0, X.shape[0], chunk):
+        c1 = min(X.shape[0], c0 + chunk)
+        idx = np.arange(c0, c1, dtype=np.int64)
+        d = dist64_rows(X, q[None, :], idx[None, :].astype(np.uint32), metric)[0]
+        if exclude is not None and c0 <= exclude < c1:
+            d[exclude - c0] = np.inf
+        ai = np.concatenate([best_i, idx])
+        ad = np.concatenate([best_d, d])
+        o = np.lexsort((ai, ad))[:k]
+        best_i, best_d = ai[o], ad[o]
+    return best_i, best_d
 
 
 def dist64_rows(X: np.ndarray, Q: np.ndarray, ids: np.ndarray, metric: str) -> np.ndarray:
