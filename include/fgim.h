@@ -166,6 +166,25 @@ fgim_status fgim_cross_query(const fgim_dataset* data, const fgim_params* params
                              void* stream);
 
 /*
+ * Stage 1 as fgim_cross_query, for callers that cannot allocate device
+ * memory (code under stream capture, serving loops, harnesses that forbid
+ * hipMalloc): it allocates nothing.  Its temporary state -- the work-queue
+ * head, the error flag, the counters and the sub-index table, 131,328 bytes
+ * in all -- lives in a fixed array in the library's device memory, one per
+ * GPU, held until the process ends.  Calls on one GPU share that array and
+ * run one at a time (a per-device host lock); each clears what it needs
+ * before its launch, and the array keeps the last call's contents.
+ * Limits: autotune must be 0 (the tuner's trial launches need memory), the
+ * BF16 / FP8 forms need data->base_lp (and base_lp_scale for FP8), and
+ * h <= 4096.  Outputs are bit-identical to fgim_cross_query's with the same
+ * arguments.  Synchronises the stream before returning.
+ * Errors: FGIM_ERR_INVALID_ARG (arguments, or a limit above), FGIM_ERR_GRAPH
+ * (bad adjacency), FGIM_ERR_DEVICE (the array's address lookup failed).
+ */
+fgim_status fgim_cross_query_noalloc(const fgim_dataset* data, const fgim_params* params,
+                                     uint32_t* knn_ids, float* knn_dist, void* stream);
+
+/*
  * Stage 2, k-NNG refinement (Section 4.2, Algorithms 3 and 4), run as
  * `rounds` synchronous rounds.  Each round: Visit splits each list and its
  * reverse lists into new and old candidates, Update proposes every

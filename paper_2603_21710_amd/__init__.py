@@ -31,7 +31,8 @@ PRECISIONS = {"fp32": FGIM_FP32, "bf16": FGIM_BF16, "fp8": FGIM_FP8_E4M3}
 STATUS = {0: "FGIM_OK", 1: "FGIM_ERR_INVALID_ARG", 2: "FGIM_ERR_GRAPH",
           3: "FGIM_ERR_OUT_OF_MEMORY", 4: "FGIM_ERR_DEVICE", 5: "FGIM_ERR_UNSUPPORTED"}
 
-EXPORTS = ["fgim_cross_query", "fgim_refine", "fgim_repair", "fgim_prune", "fgim_merge", "fgim_search",
+EXPORTS = ["fgim_cross_query", "fgim_cross_query_noalloc", "fgim_refine", "fgim_repair", "fgim_prune",
+           "fgim_merge", "fgim_search",
            "fgim_quantize", "fgim_min_beam_width", "fgim_release_scratch", "fgim_status_string",
            "fgim_last_error"]
 
@@ -95,6 +96,7 @@ def lib() -> ctypes.CDLL:
         vp, u32, u64, i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
         for name, args in {
             "fgim_cross_query": [vp, vp, vp, vp, vp, vp],
+            "fgim_cross_query_noalloc": [vp, vp, vp, vp, vp],
             "fgim_refine": [vp, vp, vp, vp, vp, vp, vp],
             "fgim_prune": [vp, vp, vp, vp, vp, vp, vp, vp],
             "fgim_merge": [vp, vp, vp, vp, vp, vp, vp],
@@ -187,6 +189,19 @@ def cross_query(m: Merge, p: Params, stats: bool = False):
     _check(lib().fgim_cross_query(ctypes.byref(m.data), ctypes.byref(p), ids.data_ptr(),
                                   dist.data_ptr(), ctypes.byref(st) if st else None, _stream()))
     return ids, dist, (st.to_dict() if st else None)
+
+
+def cross_query_noalloc(m: Merge, p: Params, ids: torch.Tensor, dist: torch.Tensor) -> None:
+    """Stage 1 into caller-given (ids int32 [N, k], dist float32 [N, k]),
+    through the entry point that allocates no device memory (autotune off;
+    the low-precision forms need m's lowp copy)."""
+    _need_cuda(ids, "ids", torch.int32)
+    _need_cuda(dist, "dist", torch.float32)
+    if ids.shape != (m.n, p.k) or dist.shape != (m.n, p.k) or not ids.is_contiguous() \
+            or not dist.is_contiguous():
+        raise ValueError(f"ids and dist must be contiguous [{m.n}, {p.k}] tensors")
+    _check(lib().fgim_cross_query_noalloc(ctypes.byref(m.data), ctypes.byref(p), ids.data_ptr(),
+                                          dist.data_ptr(), _stream()))
 
 
 def refine(m: Merge, p: Params, ids: torch.Tensor, dist: torch.Tensor, stats: bool = False):

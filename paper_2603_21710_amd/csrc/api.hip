@@ -29,6 +29,8 @@ fgim_status fail(fgim_status s, const char* fmt, ...) {
   return s;
 }
 
+void clear_error() { g_last_error.clear(); }
+
 int device_cus() {
   int dev = 0, cus = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 256;
@@ -403,8 +405,8 @@ fgim_status quantize_into(const float* base, uint64_t n, uint32_t dim, uint64_t 
 // ---------------------------------------------------------------------------
 // stage 1
 
-fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist,
-                             fgim_stats* stats, hipStream_t s, uint32_t* L_used) {
+fgim_status cross_query_check(const fgim_dataset* d, const fgim_params* p, const uint32_t* ids,
+                              const float* dist) {
   FGIM_TRY(check_dataset(d, true));
   if (!p) return fail(FGIM_ERR_INVALID_ARG, "params is NULL");
   if (!ids || !dist) return fail(FGIM_ERR_INVALID_ARG, "output is NULL");
@@ -412,60 +414,38 @@ fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32
   if (p->L == 0 || p->L > FGIM_MAX_L) return fail(FGIM_ERR_INVALID_ARG, "L = %u out of 1..%u", p->L, FGIM_MAX_L);
   if (p->precision != FGIM_FP32 && p->precision != FGIM_BF16 && p->precision != FGIM_FP8_E4M3)
     return fail(FGIM_ERR_INVALID_ARG, "unknown precision %d", (int)p->precision);
-  {  // argument errors before anything is enqueued
-    uint32_t rr = 0;
-    BeamShape sh;
-    FGIM_TRY(rerank_for(p, p->L, &rr));
-    FGIM_TRY(beam_shape(d->dim, p->L, p->k, p, &sh));
-  }
-  Scratch scr(s);
-  uint32_t* hdr = nullptr;  // [0] queue head, [1] error flag, [2] smallest input out-degree
-  unsigned long long* cnt = nullptr;
-  SubDev* subs = nullptr;
-  FGIM_TRY(scr.get(&hdr, 4));
-  FGIM_TRY(scr.get(&cnt, 4));
-  FGIM_TRY(scr.get(&subs, d->h));
-  std::vector<SubDev> hs(d->h);
+  uint32_t rr = 0;
+  BeamShape sh;
+  FGIM_TRY(rerank_for(p, p->L, &rr));
+  FGIM_TRY(beam_shape(d->dim, p->L, p->k, p, &sh));
+  return FGIM_OK;
+}
+
+fgim_status cross_query_run(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist,
+                            fgim_stats* stats, hipStream_t s, uint32_t* L_used, const CrossBufs& b) {
+  uint32_t* hdr = b.hdr;  // [0] queue head, [1] error flag, [2] smallest input out-degree
   for (uint32_t i = 0; i < d->h; ++i)
-    hs[i] = SubDev{d->subs[i].row_offset, d->subs[i].adj, d->subs[i].n, d->subs[i].adj_stride, d->subs[i].entry, 0};
-  HIP_TRY(hipMemcpyAsync(subs, hs.data(), sizeof(SubDev) * d->h, hipMemcpyHostToDevice, s));
+    b.host_subs[i] = SubDev{d->subs[i].row_offset, d->subs[i].adj, d->subs[i].n, d->subs[i].adj_stride,
+                            d->subs[i].entry, 0};
+  HIP_TRY(hipMemcpyAsync(b.subs, b.host_subs, sizeof(SubDev) * d->h, hipMemcpyHostToDevice, s));
   HIP_TRY(fill_u32(hdr, 0u, 2, s));
   HIP_TRY(fill_u32(hdr + 2, 0xFFFFFFFFu, 2, s));
-  HIP_TRY(fill_u32(reinterpret_cast<uint32_t*>(cnt), 0u, 8, s));
+  HIP_TRY(fill_u32(reinterpret_cast<uint32_t*>(b.cnt), 0u, 8, s));
   for (uint32_t i = 0; i < d->h; ++i)
     HIP_TRY(validate_graph(d->subs[i].adj, d->subs[i].n, d->subs[i].adj_stride, hdr + 1, s,
                            p->autotune ? hdr + 2 : nullptr));
-
-  const void* lp = d->base_lp;
-  const float* lps = d->base_lp_scale;
-  if (p->precision != FGIM_FP32 && !lp) {
-    if (p->precision == FGIM_BF16) {
-      uint16_t* c = nullptr;
-      FGIM_TRY(scr.get(&c, d->n_total * d->dim));
-      FGIM_TRY(quantize_into(d->base, d->n_total, d->dim, d->ld, p->precision, c, nullptr, s));
-      lp = c;
-    } else {
-      uint8_t* c = nullptr;
-      float* sc = nullptr;
-      FGIM_TRY(scr.get(&c, d->n_total * d->dim));
-      FGIM_TRY(scr.get(&sc, d->n_total));
-      FGIM_TRY(quantize_into(d->base, d->n_total, d->dim, d->ld, p->precision, c, sc, s));
-      lp = c;
-      lps = sc;
-    }
-  }
-  if (p->precision == FGIM_FP8_E4M3 && !lps) return fail(FGIM_ERR_INVALID_ARG, "FP8 copy given without scales");
+  if (p->precision == FGIM_FP8_E4M3 && !b.lps) return fail(FGIM_ERR_INVALID_ARG, "FP8 copy given without scales");
 
   BeamArgs a{};
   a.X = d->base;
   a.ld = d->ld;
   a.nc = d->dim / 4;
   a.metric = d->metric;
-  a.xb = p->precision == FGIM_BF16 ? static_cast<const uint16_t*>(lp) : nullptr;
-  a.x8 = p->precision == FGIM_FP8_E4M3 ? static_cast<const uint8_t*>(lp) : nullptr;
-  a.x8s = lps;
+  a.xb = p->precision == FGIM_BF16 ? static_cast<const uint16_t*>(b.lp) : nullptr;
+  a.x8 = p->precision == FGIM_FP8_E4M3 ? static_cast<const uint8_t*>(b.lp) : nullptr;
+  a.x8s = b.lps;
   a.dim = d->dim;
-  a.subs = subs;
+  a.subs = b.subs;
   a.h = d->h;
   a.k = p->k;
   a.n_items = d->n_total;
@@ -498,7 +478,7 @@ fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32
   FGIM_TRY(rerank_for(p, L, &rerank));
   a.L = L;
   a.rerank = rerank;
-  a.stats = cnt;
+  a.stats = b.cnt;
   a.vis_log2 = shape.vis_log2;
   a.P = shape.P;
   a.M = shape.M;
@@ -515,7 +495,7 @@ fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32
   uint32_t herr = 0;
   unsigned long long hc[3] = {0, 0, 0};
   HIP_TRY(hipMemcpyAsync(&herr, hdr + 1, 4, hipMemcpyDeviceToHost, s));
-  if (stats) HIP_TRY(hipMemcpyAsync(hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
+  if (stats) HIP_TRY(hipMemcpyAsync(hc, b.cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (stats) {
     float ms = 0.f;
@@ -535,6 +515,37 @@ fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32
   if (L_used) *L_used = L;
   if (herr) return fail(FGIM_ERR_GRAPH, "an adjacency list holds an out-of-range id, a self-loop or a duplicate");
   return FGIM_OK;
+}
+
+fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist,
+                             fgim_stats* stats, hipStream_t s, uint32_t* L_used) {
+  FGIM_TRY(cross_query_check(d, p, ids, dist));  // argument errors before anything is enqueued
+  Scratch scr(s);
+  CrossBufs b{};
+  FGIM_TRY(scr.get(&b.hdr, 4));
+  FGIM_TRY(scr.get(&b.cnt, 4));
+  FGIM_TRY(scr.get(&b.subs, d->h));
+  std::vector<SubDev> hs(d->h);
+  b.host_subs = hs.data();
+  b.lp = d->base_lp;
+  b.lps = d->base_lp_scale;
+  if (p->precision != FGIM_FP32 && !b.lp) {
+    if (p->precision == FGIM_BF16) {
+      uint16_t* c = nullptr;
+      FGIM_TRY(scr.get(&c, d->n_total * d->dim));
+      FGIM_TRY(quantize_into(d->base, d->n_total, d->dim, d->ld, p->precision, c, nullptr, s));
+      b.lp = c;
+    } else {
+      uint8_t* c = nullptr;
+      float* sc = nullptr;
+      FGIM_TRY(scr.get(&c, d->n_total * d->dim));
+      FGIM_TRY(scr.get(&sc, d->n_total));
+      FGIM_TRY(quantize_into(d->base, d->n_total, d->dim, d->ld, p->precision, c, sc, s));
+      b.lp = c;
+      b.lps = sc;
+    }
+  }
+  return cross_query_run(d, p, ids, dist, stats, s, L_used, b);
 }
 
 }  // namespace fgim

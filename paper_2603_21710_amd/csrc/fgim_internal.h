@@ -32,6 +32,25 @@ hipError_t launch_beam(const BeamArgs& a, bool l2, int fmt, const BeamShape& s, 
 // entries of each search re-scored in FP32 in the low-precision forms
 fgim_status rerank_for(const fgim_params* p, uint32_t L, uint32_t* out);
 
+// Stage 1 in two parts.  cross_query_check validates the arguments;
+// cross_query_run enqueues the beam kernel over buffers the caller provides:
+// hdr (4 uint32: queue head, error flag, smallest out-degree, spare), cnt
+// (4 counters), subs (device table of h entries) staged from host_subs
+// (host, h entries), and the low-precision copy lp / lps when the precision
+// is not FP32.  It synchronises the stream before it returns.
+struct CrossBufs {
+  uint32_t* hdr;
+  unsigned long long* cnt;
+  SubDev* subs;
+  SubDev* host_subs;
+  const void* lp;
+  const float* lps;
+};
+fgim_status cross_query_check(const fgim_dataset* d, const fgim_params* p, const uint32_t* ids,
+                              const float* dist);
+fgim_status cross_query_run(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist,
+                            fgim_stats* stats, hipStream_t s, uint32_t* L_used, const CrossBufs& b);
+
 // tune.hip: with a.counter pointing at a zeroed-by-the-callee queue head, a
 // graph already validated, and lo the minimum-querying bound on L, choose
 // the beam width (*L, lowered only in the batched or low-precision forms) and

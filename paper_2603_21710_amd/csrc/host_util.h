@@ -14,6 +14,8 @@
 namespace fgim {
 
 fgim_status fail(fgim_status s, const char* fmt, ...);
+// empties the calling thread's last-error detail (start of every entry point)
+void clear_error();
 int device_cus();
 hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s);
 fgim_status check_dataset(const fgim_dataset* d, bool need_cross);

@@ -86,3 +86,16 @@ def test_null_outputs_rejected():
 def test_repair_bad_arguments_rejected_on_host(ids, dist, n, k):
     assert fg.lib().fgim_repair(ids, dist, n, k, None, None, None) == 1
     assert fg.lib().fgim_last_error()
+
+
+@pytest.mark.parametrize("pk,lowp", [(dict(autotune=True), None), (dict(precision="bf16"), None),
+                                     (dict(precision="fp8"), 0x60000)])
+def test_noalloc_limits_rejected_on_host(pk, lowp):
+    # autotune needs trial-launch memory; the low-precision forms need the
+    # caller's copy (and FP8 its scales): rejected before any device call
+    d, keep = _dataset()
+    d.base_lp = lowp
+    p = fg.params(**{**dict(k=8, L=16), **pk})
+    rc = fg.lib().fgim_cross_query_noalloc(ctypes.byref(d), ctypes.byref(p), 0x40000, 0x50000, None)
+    assert rc == 1, fg.lib().fgim_last_error()
+    assert b"noalloc" in fg.lib().fgim_last_error()
