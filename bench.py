@@ -1,25 +1,41 @@
 """Benchmark of the FGIM merge on one MI355X.
 
 One step = one fgim_merge call (stage 1 cross-querying, stage 2 refinement
-rounds with indegree repair, stage 3 prune + reverse fill) over the
-synthetic workload, with inputs resident in HBM.  Prints one JSON line.
+rounds with indegree repair, stage 3 prune + reverse fill) over a seeded
+synthetic workload, with inputs resident in HBM.  Every form of the metric
+is timed over the same K steps after W warm-up steps: the FP32 form (the
+exact, parity form; it gives `value`) and the BF16 and FP8 forms (beam on a
+low-precision copy, FP32 re-rank).  Prints one JSON line.
 
-  python bench.py [--steps K] [--warmup W] [--config cfg2] [--precision fp32|bf16|fp8]
-                  [--no-cpu-baseline] [--no-recall] [--queries Q]
+  python bench.py [--steps K] [--warmup W] [--config cfg4] [--also cfg3]
+                  [--forms fp32,bf16,fp8] [--no-cpu-baseline] [--no-recall]
+                  [--no-parity] [--queries Q] [--cpu-nodes N] [--autotune]
+
+Defaults: the precision-form workload (2 x 500,000 vectors, d = 768,
+cosine), plus the batching-form workload (8 uneven sub-indexes, 2 M vectors,
+d = 96, inner product) as `also`.
 
 Roofline of the dominant kernel (the stage-1 beam search): algorithmic bytes
 per launch (distance computations x row bytes + expansions x adjacency row
 bytes + per-vertex query, local candidates and output) over the kernel's
-duration, timed with hipEvents on the stream the kernel runs on.
+duration, timed with hipEvents on the stream the kernel runs on.  The
+denominators are the published 8 TB/s and a copy kernel's bandwidth
+measured in the same run.
+
+Parity at full size: every form's stage-1 rows of sampled vertices are
+compared bit for bit with the oracle's (the FP8 form excepted: the oracle's
+exhaustive FP8 encoder is too slow for a full copy), and the FP32 form's
+stage-3 rows of sampled vertices with the oracle's Algorithm 5 on the same
+stage-2 lists.  A mismatch is reported in the line and makes the exit code 3.
 """
 
 from __future__ import annotations
 
 import argparse
 import hashlib
-import re
 import json
 import os
+import re
 import sys
 import time
 
@@ -34,6 +50,8 @@ METRIC = "vectors merged/sec + k-NNG recall & search recall@10, FP32 vs BF16/FP8
 BEAM_SOURCES = ["paper_2603_21710_amd/csrc/beam_impl.h", "paper_2603_21710_amd/csrc/fgim_device.h",
                 "paper_2603_21710_amd/csrc/beam_f32.hip", "paper_2603_21710_amd/csrc/beam_bf16.hip",
                 "paper_2603_21710_amd/csrc/beam_fp8.hip"]
+ROW_BYTES = {"fp32": 4, "bf16": 2, "fp8": 1}
+DTYPE = {"fp32": "f32", "bf16": "bf16 scoring, f32 re-rank", "fp8": "fp8-e4m3 scoring, f32 re-rank"}
 
 
 def log(*a):
@@ -74,6 +92,28 @@ def measured_traffic(cfg_name: str, precision: str):
         return None
 
 
+def copy_peak_gbs(dev, gib: float = 2.0, reps: int = 20) -> float:
+    """Bandwidth of a plain device-to-device copy (read + write bytes over
+    time, median of reps): the measured HBM ceiling the roofline is also
+    quoted against."""
+    n = int(gib * (1 << 30)) // 4
+    src = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        dst.copy_(src)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * n * 4 / float(np.median(ts)) / 1e9
+
+
 def build_inputs(cfg, device):
     from workloads import build_input_pg, make_vectors, reach_fraction, split_sizes
     t0 = time.time()
@@ -88,24 +128,238 @@ def build_inputs(cfg, device):
         deg.append(pg.mean_degree)
         if n >= 1_000_000:
             log(f"input graph {i + 1}/{len(parts)}: n={n} in {time.time() - t1:.1f}s")
-    log(f"inputs: N={X.shape[0]} d={X.shape[1]} h={len(graphs)} built in {time.time() - t0:.1f}s; "
+    build_s = time.time() - t0
+    log(f"inputs {cfg.name}: N={X.shape[0]} d={X.shape[1]} h={len(graphs)} built in {build_s:.1f}s; "
         f"input reach {min(reach):.4f}..{max(reach):.4f}, mean degree {np.mean(deg):.2f}")
-    return X, graphs, reach
+    return X, graphs, reach, build_s
 
 
-def cpu_baseline(cfg, X, graphs, budget_nodes: int):
-    """The oracle timed on this host: stage 1 on a seeded sample of vertices
-    of the full workload, stages 2-3 in full on a 2 x 20,000 draw of the same
-    distribution and parameters.  Returns vectors/s of the combined cost."""
+def beam_roofline(fg, m, cfg, X, graphs, precision, st, beam_ms, peak_meas, count_launch=True):
+    """Roofline of the beam kernel for one form (see the module docstring)."""
+    # The distance count is measured with the largest visited cache, which
+    # re-scores almost no vertex, so it is (slightly above) the count of
+    # Algorithm 1.  That counting launch uses another lanes-per-distance
+    # (another kernel instance, the same count), so a kernel trace of this
+    # script lists the timed launches under their own name.
+    used_p = st["lanes_per_dist"]
+    alt_p = used_p * 2 if used_p * 2 <= min(64, X.shape[1] // 4) else max(1, used_p // 2)
+    st_big = st
+    if count_launch:
+        _, _, st_big = fg.cross_query(m, fg.params(k=cfg.k, L=st["L_used"], precision=precision,
+                                                   visited_slots=16384, waves_per_cu=8,
+                                                   lanes_per_dist=alt_p), stats=True)
+    d, k = X.shape[1], cfg.k
+    ndc, nexp, searches = st_big["ndc"], st_big["expansions"], st_big["searches"]
+    local = sum(int((a != 0xFFFFFFFF).sum()) for _, a, _ in graphs)
+    stride_mean = float(np.mean([a.shape[1] for _, a, _ in graphs]))
+    row_bytes = d * ROW_BYTES[precision] + (4 if precision == "fp8" else 0)
+    alg_bytes = (ndc * row_bytes + nexp * stride_mean * 4
+                 + X.shape[0] * (d * 4 + stride_mean * 4 + k * 8) + local * d * 4)
+    if precision != "fp32":
+        alg_bytes += searches * min(st["L_used"], 2 * cfg.k) * d * 4
+    kern_s = float(np.mean(beam_ms)) / 1e3
+    achieved = alg_bytes / kern_s / 1e9
+    traffic = measured_traffic(cfg.name, precision)
+    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+            "measured_peak": round(peak_meas, 1),
+            "frac_of_measured_peak": round(achieved / peak_meas, 4),
+            "traffic_frac_of_measured_peak": None if traffic is None else round(traffic / kern_s / 1e9 / peak_meas, 4),
+            "kernel": "beam_kernel (stage-1 cross-query)", "kernel_ms": round(kern_s * 1e3, 3),
+            "algorithmic_bytes": int(alg_bytes), "ndc_per_search": round(ndc / max(1, searches), 2),
+            "expansions_per_search": round(nexp / max(1, searches), 2),
+            "ndc_source": "counting launch, 16384 visited slots" if count_launch else "timed launch",
+            "launch": {"lanes_per_dist": st["lanes_per_dist"], "waves_per_cu": st["waves_per_cu"],
+                       "visited_slots": st["visited_slots"]},
+            "beam_sources_sha256": beam_source_hash()}
+    # Algorithmic bytes count every row gather as an HBM read; rows re-read
+    # by concurrent searches (the entry region of each graph above all) hit
+    # L2 and the memory-side cache, so `frac` can pass what HBM alone could
+    # serve.  `traffic` is the counted fabric traffic (an upper bound of HBM
+    # bytes), and its fraction of the measured copy peak is the physically
+    # bounded figure.
+    roof["cache_assisted"] = bool(traffic is not None and alg_bytes > traffic)
+    return roof
+
+
+def sample_nodes(N: int, n: int, seed: int) -> np.ndarray:
+    return np.sort(np.random.default_rng(seed).choice(N, min(n, N), replace=False))
+
+
+def stage1_parity(fg, m, cfg, X, graphs, precision, L_used, nodes, deq=None):
+    """Stage-1 rows of `nodes` from the GPU (the timed launch configuration)
+    against the oracle's, bit for bit (ids and distance bits).  Returns the
+    report and the oracle's time per vertex."""
+    import oracle
+    ids, dist, _ = fg.cross_query(m, fg.params(k=cfg.k, L=L_used, precision=precision))
+    gi = ids.cpu().numpy().view(np.uint32)[nodes]
+    gd = dist.cpu().numpy()[nodes]
+    t0 = time.perf_counter()
+    if precision == "fp32":
+        oi, od, _ = oracle.cross_query(X, graphs, cfg.k, L_used, cfg.metric, nodes=nodes)
+    else:
+        oi, od, _ = oracle.cross_query(X, graphs, cfg.k, L_used, cfg.metric, nodes=nodes, Xs=deq,
+                                       rerank=min(L_used, 2 * cfg.k))
+    t = (time.perf_counter() - t0) / len(nodes)
+    bad = np.nonzero((gi != oi).any(1) | (gd.view(np.uint32) != od.view(np.uint32)).any(1))[0]
+    rep = {"vertices": int(len(nodes)), "mismatched_vertices": int(bad.size)}
+    if bad.size:
+        rep["first_mismatch"] = int(nodes[bad[0]])
+    return rep, ids, dist, t
+
+
+def stage23_parity(fg, m, cfg, X, p, ids, dist, nodes):
+    """Stage 2 on the GPU from its stage-1 lists, checked by properties that
+    hold at any size (sorted unique lists without self-loops, distances equal
+    to the oracle's distance of each sampled pair, indegrees equal to a
+    recount); stage 3 on those lists, sampled rows against the oracle's
+    Algorithm 5 on the same lists."""
+    import oracle
+    T, _ = fg.refine(m, p, ids, dist)
+    li = ids.cpu().numpy().view(np.uint32)
+    ld = dist.cpu().numpy()
+    Th = T.cpu().numpy().view(np.uint32)
+    N = li.shape[0]
+    rec = np.bincount(li[li != 0xFFFFFFFF].astype(np.int64), minlength=N)
+    bad2 = 0
+    for u in nodes[:2000]:
+        row = [(float(ld[u, t]), int(li[u, t])) for t in range(cfg.k) if li[u, t] != 0xFFFFFFFF]
+        ok = row == sorted(row) and len({v for _, v in row}) == len(row) and all(v != u for _, v in row)
+        ok = ok and all(d == oracle.distance(X[u], X[v], cfg.metric) for d, v in row)
+        bad2 += not ok
+    pg, deg = fg.prune(m, p, ids, dist, T)
+    pi, pd, pdeg = oracle.prune_rows(X, li, ld, Th, cfg.R, nodes[:2000], cfg.metric)
+    gp = pg.cpu().numpy().view(np.uint32)[nodes[:2000]]
+    gdeg = deg.cpu().numpy()[nodes[:2000]]
+    bad3 = int(((gp != pi).any(1) | (gdeg != pdeg)).sum())
+    return {"stage2_property_checked_vertices": int(min(2000, len(nodes))),
+            "stage2_bad_vertices": int(bad2), "stage2_indegree_recount_ok": bool((rec == Th).all()),
+            "stage3_vertices": int(min(2000, len(nodes))), "stage3_mismatched_vertices": bad3}
+
+
+def measure(fg, cfg, forms, args, dev, peak_meas, with_parity, with_recall):
+    """Build the inputs of one workload and time every form over K steps."""
+    from workloads import make_queries
+    from workloads.evaluate import exact_knn_screened, tie_recall
+    X, graphs, reach, build_s = build_inputs(cfg, "cuda")
+    Xd = torch.from_numpy(X).to(dev)
+    gl = [(torch.from_numpy(a.view(np.int32)).to(dev), int(e)) for _, a, e in graphs]
+    out = {"workload": cfg.name, "sizes": list(cfg.sizes), "dim": cfg.dim, "metric": cfg.metric,
+           "r_in": cfg.r_in, "k": cfg.k, "L": cfg.L, "rounds": cfg.rounds, "R": cfg.R,
+           "input_build_s": round(build_s, 1), "input_reach": [round(r, 4) for r in reach], "forms": {}}
+    nodes = sample_nodes(X.shape[0], args.parity_nodes, 12345)
+    gt = None
+    if with_recall:
+        t0 = time.time()
+        Q = make_queries(cfg, args.queries)
+        knodes = sample_nodes(X.shape[0], args.queries, 7)
+        _, kd, fb1 = exact_knn_screened(X, X[knodes], cfg.k, cfg.metric, exclude=knodes, Xdev=Xd)
+        _, qd, fb2 = exact_knn_screened(X, Q, 10, cfg.metric, Xdev=Xd)
+        gt = (Q, knodes, kd, qd)
+        log(f"ground truth {cfg.name}: {time.time() - t0:.1f}s (fallbacks {fb1}, {fb2})")
+    for form in forms:
+        t0 = time.time()
+        lowp = lows = None
+        quant_ms = None
+        if form != "fp32":
+            torch.cuda.synchronize()
+            tq = time.perf_counter()
+            lowp, lows = fg.quantize(Xd, form)
+            torch.cuda.synchronize()
+            quant_ms = (time.perf_counter() - tq) * 1e3
+        m = fg.Merge(Xd, gl, cfg.metric, lowp, lows)
+        p = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds, precision=form, autotune=args.autotune)
+        tune_ms = None
+        for _ in range(args.warmup):
+            _, _, _, stw = fg.merge(m, p, stats=True)
+            tune_ms = stw["ms_tune"] if tune_ms is None else tune_ms
+        torch.cuda.synchronize()
+        beam_ms, stage_ms = [], []
+        t1 = time.perf_counter()
+        for _ in range(args.steps):
+            pg, deg, entry, st = fg.merge(m, p, stats=True)
+            beam_ms.append(st["ms_beam_kernel"])
+            stage_ms.append(st["ms_stage"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t1
+        ms = wall * 1e3 / args.steps
+        f = {"value": round(X.shape[0] / (ms / 1e3), 1), "unit": "vectors/s", "ms_per_step": round(ms, 3),
+             "dtype": DTYPE[form], "L_used": st["L_used"],
+             "stages_ms": [round(x, 3) for x in np.mean(stage_ms, 0).tolist()],
+             "refine": {"proposals": st["proposals"], "rechecked": st["rechecked"], "repaired": st["repaired"],
+                        "repair_batches": st["repair_batches"], "repair_alone": st["repair_alone"],
+                        "attempts": st["refine_attempts"]}}
+        if quant_ms is not None:
+            f["quantize_ms"] = round(quant_ms, 3)
+        f["roofline"] = beam_roofline(fg, m, cfg, X, graphs, form, st, beam_ms, peak_meas,
+                                      count_launch=not args.no_ndc_count)
+        if args.autotune:
+            f["roofline"]["launch"]["tune_ms_first_call"] = round(tune_ms or 0.0, 1)
+        log(f"{cfg.name} {form}: {ms:.2f} ms/step, stages {f['stages_ms']} ms, beam kernel "
+            f"{np.mean(beam_ms):.2f} ms ({f['roofline']['frac']} of 8 TB/s algorithmic)")
+        ids = dist = None
+        if with_parity and form != "fp8":
+            deq = None
+            if form == "bf16":
+                import oracle
+                deq = oracle.quantize_bf16(X)[1]
+            rep, ids, dist, t_vertex = stage1_parity(fg, m, cfg, X, graphs, form, st["L_used"], nodes, deq)
+            f["parity"] = {"stage1": rep}
+            if form == "fp32":
+                f["oracle_stage1_ms_per_vertex"] = t_vertex * 1e3
+                f["parity"].update(stage23_parity(fg, m, cfg, X, p, ids, dist, nodes))
+                ids = dist = None
+            log(f"{cfg.name} {form} parity: {f['parity']}")
+        if with_recall:
+            Q, knodes, kd, qd = gt
+            if ids is None:
+                ids, dist, _ = fg.cross_query(m, fg.params(k=cfg.k, L=st["L_used"], precision=form))
+            fg.refine(m, p, ids, dist)
+            knn = fg.as_uint32(ids)
+            sr = {}
+            Qd = torch.from_numpy(Q).to(dev)
+            for Ls in (16, 32, 64, 128):
+                found, _ = fg.search(Xd, pg, entry, Qd, Ls, 10, cfg.metric)
+                sr[str(Ls)] = round(tie_recall(X, Q, fg.as_uint32(found), qd[:, -1], 10, cfg.metric), 5)
+            f["quality"] = {"knng_recall": round(tie_recall(X, X[knodes], knn[knodes], kd[:, -1], cfg.k,
+                                                            cfg.metric), 5),
+                            "search_recall@10": sr}
+        out["forms"][form] = f
+        del m, lowp, lows
+        torch.cuda.empty_cache()
+        log(f"{cfg.name} {form} done in {time.time() - t0:.1f}s")
+    if with_recall:
+        out["quality_setup"] = {"knng_recall_nodes": len(gt[1]), "queries": int(gt[0].shape[0]),
+                                "search_L_headline": 64,
+                                "ground_truth": "FP64 direct form, FP32 GPU shortlist proved complete"}
+    base = out["forms"].get("fp32")
+    if base is not None:
+        for form, f in out["forms"].items():
+            if form == "fp32":
+                continue
+            f["speedup_vs_fp32"] = round(f["value"] / base["value"], 4)
+            if "quality" in f and "quality" in base:
+                f["search_recall_gap_pp_L64"] = round(
+                    (base["quality"]["search_recall@10"]["64"] - f["quality"]["search_recall@10"]["64"]) * 100, 3)
+                f["knng_recall_gap_pp"] = round((base["quality"]["knng_recall"] - f["quality"]["knng_recall"]) * 100, 3)
+    return out, X, graphs
+
+
+def cpu_baseline(cfg, X, graphs, t_s1_vertex, nodes_used):
+    """The oracle timed on this host: stage 1 on the seeded vertices of the
+    full workload that the parity check ran (its time per vertex), one
+    thread on 500 of them, and stages 2-3 in full on a 2 x 20,000 draw of
+    the same distribution and parameters.  Returns vectors/s of the summed
+    per-vertex cost."""
     import oracle
     from workloads import build_input_pg, make_vectors, split_sizes
     threads = oracle.default_threads()
-    rng = np.random.default_rng(12345)
-    nodes = np.sort(rng.choice(X.shape[0], min(budget_nodes, X.shape[0]), replace=False)).astype(np.uint64)
-    t0 = time.perf_counter()
-    oracle.cross_query(X, graphs, cfg.k, cfg.L, cfg.metric, nodes=nodes, threads=threads)
-    t_s1 = (time.perf_counter() - t0) / len(nodes)
-    one = nodes[:1000]
+    nodes = sample_nodes(X.shape[0], nodes_used, 12345)
+    if t_s1_vertex is None:
+        t0 = time.perf_counter()
+        oracle.cross_query(X, graphs, cfg.k, cfg.L, cfg.metric, nodes=nodes, threads=threads)
+        t_s1_vertex = (time.perf_counter() - t0) / len(nodes)
+    one = nodes[:500]
     t0 = time.perf_counter()
     oracle.cross_query(X, graphs, cfg.k, cfg.L, cfg.metric, nodes=one, threads=1)
     t_s1_one = (time.perf_counter() - t0) / len(one)
@@ -120,12 +374,14 @@ def cpu_baseline(cfg, X, graphs, budget_nodes: int):
     i2, d2, _, T, _ = oracle.refine(Xs, gs, ids, dd, small.rounds, small.metric, threads=threads)
     oracle.prune(Xs, i2, d2, T, small.R, small.metric, threads=threads)
     t_s23 = (time.perf_counter() - t0) / Xs.shape[0]
-    per_vec = t_s1 + t_s23
+    per_vec = t_s1_vertex + t_s23
     return {"value": 1.0 / per_vec, "unit": "vectors/s", "cores": threads, "kind": "oracle",
             "sample": (f"stage 1 on {len(nodes)} seeded vertices of the full workload "
-                       f"({t_s1 * 1e3:.3f} ms/vertex); stages 2-3 in full on a "
+                       f"({t_s1_vertex * 1e3:.3f} ms/vertex); stages 2-3 in full on a "
                        f"{'+'.join(str(s) for s in small.sizes)} draw of the same distribution "
                        f"({t_s23 * 1e3:.3f} ms/vertex)"),
+            "host_nproc": os.cpu_count(), "threads": threads,
+            "threads_note": "one GPU's share of the host is 16 cores; the oracle uses min(16, nproc) threads",
             "cpu": cpu_model(),
             "stage1_ms_per_vertex_1thread": round(t_s1_one * 1e3, 4)}
 
@@ -146,12 +402,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", default="cfg2")
-    ap.add_argument("--precision", default=None, choices=[None, "fp32", "bf16", "fp8"])
+    ap.add_argument("--config", default="cfg4")
+    ap.add_argument("--also", default="cfg3", help="comma-separated extra workloads, or 'none'")
+    ap.add_argument("--forms", default="fp32,bf16,fp8")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-recall", action="store_true")
+    ap.add_argument("--no-parity", action="store_true")
     ap.add_argument("--queries", type=int, default=10000)
-    ap.add_argument("--cpu-nodes", type=int, default=20000)
+    ap.add_argument("--parity-nodes", type=int, default=10000)
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-ndc-count", action="store_true",
                     help="take the distance count from the timed launch (re-scored ids included) "
@@ -163,138 +421,58 @@ def main():
         sys.exit(2)
 
     import paper_2603_21710_amd as fg
-    from workloads import get_config, make_queries
-    from workloads.evaluate import exact_knn_fp64, tie_recall
+    from workloads import get_config
 
-    cfg = get_config(args.config)
-    precision = args.precision or "fp32"
+    forms = [f for f in args.forms.split(",") if f]
+    if not forms or any(f not in ROW_BYTES for f in forms):
+        print(f"--forms must list fp32, bf16 and/or fp8, got {args.forms!r}", file=sys.stderr)
+        sys.exit(2)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    X, graphs, reach = build_inputs(cfg, "cuda")
-    Xd = torch.from_numpy(X).to(dev)
-    gl = [(torch.from_numpy(a.view(np.int32)).to(dev), int(e)) for _, a, e in graphs]
-    lowp = lowp_scale = None
-    quant_ms = None
-    if precision != "fp32":
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        lowp, lowp_scale = fg.quantize(Xd, precision)
-        torch.cuda.synchronize()
-        quant_ms = (time.perf_counter() - t0) * 1e3
-    m = fg.Merge(Xd, gl, cfg.metric, lowp, lowp_scale)
-    p = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds, precision=precision,
-                  autotune=args.autotune)
+    peak = copy_peak_gbs(dev)
+    log(f"copy kernel: {peak:.1f} GB/s (read + write)")
 
-    tune_ms = None  # tuner time of the first call (0 on a cache hit)
-    for _ in range(args.warmup):
-        _, _, _, stw = fg.merge(m, p, stats=True)
-        tune_ms = stw["ms_tune"] if tune_ms is None else tune_ms
-    torch.cuda.synchronize()
-    beam_ms, stage_ms = [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        pg, deg, entry, st = fg.merge(m, p, stats=True)
-        beam_ms.append(st["ms_beam_kernel"])
-        stage_ms.append(st["ms_stage"])
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms_per_step = wall * 1e3 / args.steps
-    value = X.shape[0] / (ms_per_step / 1e3)
-    log(f"merge: {ms_per_step:.2f} ms/step, stages {np.mean(stage_ms, 0).round(2).tolist()} ms, "
-        f"beam kernel {np.mean(beam_ms):.2f} ms")
-
-    # Algorithmic bytes of one beam-kernel launch.  The distance count is
-    # measured with the largest visited cache, which re-scores almost no
-    # vertex, so it is (slightly above) the count of Algorithm 1.  That
-    # counting launch uses another lanes-per-distance (another kernel
-    # instance, the same count), so a kernel trace of this script lists the
-    # timed launches under their own name.
-    used_p = st["lanes_per_dist"]
-    alt_p = used_p * 2 if used_p * 2 <= min(64, X.shape[1] // 4) else max(1, used_p // 2)
-    if args.no_ndc_count:
-        st_big = st
-    else:
-        _, _, st_big = fg.cross_query(m, fg.params(k=cfg.k, L=st["L_used"], precision=precision,
-                                                   visited_slots=16384, waves_per_cu=8,
-                                                   lanes_per_dist=alt_p), stats=True)
-    be = {"fp32": 4, "bf16": 2, "fp8": 1}[precision]
-    d, k = X.shape[1], cfg.k
-    ndc, nexp, searches = st_big["ndc"], st_big["expansions"], st_big["searches"]
-    local = sum(int((a != 0xFFFFFFFF).sum()) for _, a, _ in graphs)
-    stride_mean = float(np.mean([a.shape[1] for _, a, _ in graphs]))
-    row_bytes = d * be + (4 if precision == "fp8" else 0)
-    alg_bytes = (ndc * row_bytes + nexp * stride_mean * 4
-                 + X.shape[0] * (d * 4 + stride_mean * 4 + k * 8) + local * d * 4)
-    if precision != "fp32":
-        alg_bytes += searches * min(cfg.L, 2 * cfg.k) * d * 4
-    kern_s = float(np.mean(beam_ms)) / 1e3
-    achieved = alg_bytes / kern_s / 1e9
-    traffic = measured_traffic(cfg.name, precision)
-    # Algorithmic bytes can exceed what HBM delivers (rows re-read by
-    # concurrent searches hit L2 and the memory-side cache), so frac may pass
-    # 1; traffic_frac is the measured HBM traffic over the same time.
-    traffic_frac = None if traffic is None else round(traffic / kern_s / 1e9 / HBM_PEAK_GBS, 4)
-    roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "traffic_frac": traffic_frac,
-            "kernel": "beam_kernel (stage-1 cross-query)", "kernel_ms": round(kern_s * 1e3, 3),
-            "algorithmic_bytes": int(alg_bytes), "ndc_per_search": round(ndc / max(1, searches), 2),
-            "expansions_per_search": round(nexp / max(1, searches), 2),
-            "ndc_source": "timed launch" if args.no_ndc_count else "counting launch, 16384 visited slots",
-            "launch": {"lanes_per_dist": st["lanes_per_dist"], "waves_per_cu": st["waves_per_cu"],
-                       "visited_slots": st["visited_slots"],
-                       "tune_ms_first_call": round(tune_ms if tune_ms is not None else st["ms_tune"], 1)},
-            "beam_sources_sha256": beam_source_hash()}
-
-    out = {"metric": METRIC, "value": round(value, 1), "unit": "vectors/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+    cfg = get_config(args.config)
+    head, X, graphs = measure(fg, cfg, forms, args, dev, peak, not args.no_parity, not args.no_recall)
+    lead = forms[0]
+    hf = head["forms"][lead]
+    out = {"metric": METRIC, "value": hf["value"], "unit": "vectors/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": hf["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-           "dtype": {"fp32": "f32", "bf16": "bf16 scoring, f32 re-rank",
-                     "fp8": "fp8-e4m3 scoring, f32 re-rank"}[precision],
-           "data": "synthetic (seeded; stands in for the paper's datasets)",
+           "dtype": hf["dtype"], "data": "synthetic (seeded; stands in for the paper's datasets)",
            "config": {"workload": cfg.name, "sizes": list(cfg.sizes), "dim": cfg.dim,
-                      "metric": cfg.metric, "r_in": cfg.r_in, "k": cfg.k, "L": st["L_used"],
-                      "rounds": cfg.rounds, "R": cfg.R, "precision": precision,
+                      "metric": cfg.metric, "r_in": cfg.r_in, "k": cfg.k, "L": hf["L_used"],
+                      "rounds": cfg.rounds, "R": cfg.R, "precision": lead, "forms": forms,
                       "parallelism": "1 GPU"},
-           "stages_ms": [round(x, 3) for x in np.mean(stage_ms, 0).tolist()],
-           "refine": {"proposals": st["proposals"], "rechecked": st["rechecked"], "repaired": st["repaired"],
-                      "repair_batches": st["repair_batches"], "repair_alone": st["repair_alone"],
-                      "attempts": st["refine_attempts"]},
-           "roofline": roof}
-    if quant_ms is not None:
-        out["quantize_ms"] = round(quant_ms, 3)
-
-    if not args.no_recall:
-        t0 = time.time()
-        Q = make_queries(cfg, args.queries)
-        ids, dist, _ = fg.cross_query(m, p)
-        fg.refine(m, p, ids, dist)
-        knn = fg.as_uint32(ids)
-        rng = np.random.default_rng(7)
-        nodes = np.sort(rng.choice(X.shape[0], min(args.queries, X.shape[0]), replace=False))
-        _, gd = exact_knn_fp64(X, X[nodes], cfg.k, cfg.metric, exclude=nodes)
-        knng_recall = tie_recall(X, X[nodes], knn[nodes], gd[:, -1], cfg.k, cfg.metric)
-        _, qd = exact_knn_fp64(X, Q, 10, cfg.metric)
-        sr = {}
-        for Ls in (16, 32, 64, 128):
-            found, _ = fg.search(Xd, pg, entry, torch.from_numpy(Q).to(dev), Ls, 10, cfg.metric)
-            sr[str(Ls)] = round(tie_recall(X, Q, fg.as_uint32(found), qd[:, -1], 10, cfg.metric), 5)
-        out["quality"] = {"knng_recall": round(knng_recall, 5), "knng_recall_nodes": len(nodes),
-                          "search_recall@10": sr, "search_L_headline": 64,
-                          "queries": int(Q.shape[0]), "input_reach": [round(r, 4) for r in reach]}
-        if precision != "fp32":
-            p32 = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds)
-            pg32, _, e32, _ = fg.merge(fg.Merge(Xd, gl, cfg.metric), p32)
-            found, _ = fg.search(Xd, pg32, e32, torch.from_numpy(Q).to(dev), 64, 10, cfg.metric)
-            r32 = tie_recall(X, Q, fg.as_uint32(found), qd[:, -1], 10, cfg.metric)
-            out["quality"]["fp32_search_recall@10_L64"] = round(r32, 5)
-            out["quality"]["recall_gap_pp_L64"] = round((r32 - sr["64"]) * 100, 3)
-        log(f"quality: {out['quality']} ({time.time() - t0:.1f}s)")
-
+           "stages_ms": hf["stages_ms"], "roofline": hf["roofline"], "copy_peak_gbs": round(peak, 1),
+           "forms": head["forms"]}
+    for key in ("input_build_s", "input_reach", "quality_setup"):
+        if key in head:
+            out[key] = head[key]
+    also = [] if args.also in ("", "none") else [a for a in args.also.split(",") if a]
+    out["also"] = {}
+    for name in also:
+        o, _, _ = measure(fg, get_config(name), forms, args, dev, peak, not args.no_parity,
+                          not args.no_recall)
+        out["also"][name] = o
     if not args.no_cpu_baseline:
         t0 = time.time()
-        out["cpu_baseline"] = cpu_baseline(cfg, X, graphs, args.cpu_nodes)
+        t_v = hf.get("oracle_stage1_ms_per_vertex")
+        out["cpu_baseline"] = cpu_baseline(cfg, X, graphs, None if t_v is None else t_v / 1e3,
+                                           args.parity_nodes)
         log(f"cpu baseline: {out['cpu_baseline']} ({time.time() - t0:.1f}s)")
+    bad = []
+    for wl, fs in [(cfg.name, head["forms"])] + [(n, o["forms"]) for n, o in out["also"].items()]:
+        for form, f in fs.items():
+            par = f.get("parity", {})
+            if par.get("stage1", {}).get("mismatched_vertices", 0) or par.get("stage3_mismatched_vertices", 0) \
+                    or par.get("stage2_bad_vertices", 0) or par.get("stage2_indegree_recount_ok") is False:
+                bad.append(f"{wl}/{form}")
+    out["parity_ok"] = not bad
     print(json.dumps(out), flush=True)
+    if bad:
+        log(f"PARITY MISMATCH in {bad}")
+        sys.exit(3)
 
 
 if __name__ == "__main__":

@@ -22,6 +22,7 @@ _SRC = os.path.join(_HERE, "fgim_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 NONE = 0xFFFFFFFF
 METRICS = {"l2": 0, "ip": 1, "cos": 2}
+RULES = {"rng": 0, "alpha": 1, "tau": 2}   # stage-3 neighbour selection (Section 4.3.1)
 FLAG_NEW = 1
 
 
@@ -72,7 +73,12 @@ def lib() -> ctypes.CDLL:
                                     vp, vp, i32, i32, vp]
         L.oracle_prune.restype = i32
         L.oracle_prune.argtypes = [vp, u64, u32, i32, u64, u32, vp, vp, vp, u32, vp, vp, vp,
-                                   i32]
+                                   i32, i32, ctypes.c_float]
+        L.oracle_mips_to_l2.restype = i32
+        L.oracle_mips_to_l2.argtypes = [vp, u64, u64, u32, vp, u64, vp]
+        L.oracle_prune_rows.restype = i32
+        L.oracle_prune_rows.argtypes = [vp, u64, u32, i32, u64, u32, vp, vp, vp, u32, vp, u64,
+                                        vp, vp, vp, i32, i32, ctypes.c_float]
         L.oracle_merged_entry.restype = u64
         L.oracle_merged_entry.argtypes = [vp, u32]
         L.oracle_merge.restype = i32
@@ -215,8 +221,10 @@ def refine(X, subs, ids, dist, rounds: int, metric: str = "l2", k_rev: int = 0,
     return ids, dist, flags, T, {"proposals": int(st[0]), "repaired": int(st[1])}
 
 
-def prune(X, ids, dist, T, R: int, metric: str = "l2", threads: Optional[int] = None):
-    """Stage 3 (Algorithm 5): (out_ids [N, R], out_dist, deg)."""
+def prune(X, ids, dist, T, R: int, metric: str = "l2", threads: Optional[int] = None,
+          rule: str = "rng", param: float = 0.0):
+    """Stage 3 (Algorithm 5; rule "alpha" / "tau" swaps in alpha-RNG with
+    alpha = param or tau-MNG with tau = param): (out_ids [N, R], out_dist, deg)."""
     X = _f32(X)
     ids = np.ascontiguousarray(ids, dtype=np.uint32)
     dist = np.ascontiguousarray(dist, dtype=np.float32)
@@ -227,10 +235,43 @@ def prune(X, ids, dist, T, R: int, metric: str = "l2", threads: Optional[int] = 
     deg = np.empty(N, np.uint32)
     rc = lib().oracle_prune(_p(X), X.shape[1], X.shape[1], METRICS[metric], N, k, _p(ids),
                             _p(dist), _p(T), R, _p(oi), _p(od), _p(deg),
-                            threads or default_threads())
+                            threads or default_threads(), RULES[rule], float(param))
     if rc:
         raise ValueError("oracle_prune failed")
     return oi, od, deg
+
+
+def prune_rows(X, ids, dist, T, R: int, rows, metric: str = "l2", threads: Optional[int] = None,
+               rule: str = "rng", param: float = 0.0):
+    """Stage 3 (Algorithm 5) for the listed vertices of the full lists:
+    (out_ids [len(rows), R], out_dist, deg), row r as prune() gives rows[r]."""
+    X = _f32(X)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    dist = np.ascontiguousarray(dist, dtype=np.float32)
+    T = np.ascontiguousarray(T, dtype=np.uint32)
+    rows = np.ascontiguousarray(rows, dtype=np.uint64)
+    N, k = ids.shape
+    nr = rows.shape[0]
+    oi = np.empty((nr, R), np.uint32)
+    od = np.empty((nr, R), np.float32)
+    deg = np.empty(nr, np.uint32)
+    rc = lib().oracle_prune_rows(_p(X), X.shape[1], X.shape[1], METRICS[metric], N, k, _p(ids),
+                                 _p(dist), _p(T), R, _p(rows), nr, _p(oi), _p(od), _p(deg),
+                                 threads or default_threads(), RULES[rule], float(param))
+    if rc:
+        raise ValueError("oracle_prune_rows failed")
+    return oi, od, deg
+
+
+def mips_to_l2(X):
+    """MIPS -> L2 transform: (rows [n, d + 4] float32, M = max |x|^2)."""
+    X = _f32(X)
+    n, d = X.shape
+    out = np.empty((n, d + 4), np.float32)
+    M = ctypes.c_float()
+    if lib().oracle_mips_to_l2(_p(X), n, d, d, _p(out), d + 4, ctypes.byref(M)):
+        raise ValueError("oracle_mips_to_l2 failed")
+    return out, M.value
 
 
 def merged_entry(subs) -> int:

@@ -36,6 +36,11 @@
 #define FLAG_NEW 1u
 #define FLAG_REPLACED 2u
 
+/* neighbour-selection rules of stage 3 (Section 4.3.1) */
+#define ORC_SEL_RNG 0     /* Algorithm 5: delta(u,v) < delta(w,v) */
+#define ORC_SEL_ALPHA 1   /* alpha-RNG (Vamana's robust prune) */
+#define ORC_SEL_TAU 2     /* tau-MNG (tau-monotonic graph) */
+
 typedef struct {
     uint64_t off;          /* global id of local vertex 0 (phi_i offset) */
     uint32_t n;            /* |V_i| */
@@ -830,38 +835,84 @@ typedef struct {
     uint32_t* sel_ids;     /* N x R */
     float* sel_dist;
     uint32_t* sel_n;
+    int rule;              /* ORC_SEL_* */
+    float param;           /* alpha or tau */
 } prune_ctx;
 
-/* Neighbour selection: scan N(u) from the closest; keep v when T(v) = 1 or
- * delta(u, v) < delta(w, v) for every kept w (strict); stop at R kept. */
+/* The Euclidean distance behind delta: sqrt(delta) for squared L2, and
+ * sqrt(2 delta) for cosine on unit vectors (|a - b|^2 = 2 (1 - <a,b>)),
+ * with a negative rounding residue read as 0.  sqrtf is correctly rounded. */
+static float euclid_of(float d, int metric)
+{
+    float s = metric == ORC_COS ? 2.0f * d : d;
+    return sqrtf(s > 0.0f ? s : 0.0f);
+}
+
+/*
+ * Whether an already kept neighbour w, at delta(w, v) = dwv, leaves the
+ * candidate v, at delta(u, v) = duv, selectable (Section 4.3.1 names RNG
+ * and, as swap-ins, alpha-RNG and tau-MNG):
+ *  - RNG (Algorithm 5): duv < dwv.
+ *  - alpha-RNG: v survives w when |u - v| < alpha |w - v| (Vamana's robust
+ *    prune); on delta, which is the squared distance for L2 and half of it
+ *    for cosine, that is duv < alpha^2 dwv, with alpha^2 rounded to FP32
+ *    once and the product rounded once.
+ *  - tau-MNG: w occludes v when |w - v| < |u - v| - 3 tau (the
+ *    tau-monotonic graph's edge rule); v survives when
+ *    e(duv) < e(dwv) + 3 tau on the Euclidean distances e, strict as in
+ *    Algorithm 5, with 3 tau rounded to FP32 once.
+ */
+static int pair_keeps(const prune_ctx* c, float duv, float dwv)
+{
+    if (c->rule == ORC_SEL_ALPHA) {
+        float a2 = c->param * c->param;
+        float lim = a2 * dwv;
+        return duv < lim;
+    }
+    if (c->rule == ORC_SEL_TAU) {
+        float t = 3.0f * c->param;
+        float lim = euclid_of(dwv, c->metric) + t;
+        return euclid_of(duv, c->metric) < lim;
+    }
+    return duv < dwv;
+}
+
+/* Neighbour selection of vertex u: scan N(u) from the closest; keep v when
+ * T(v) = 1 or every kept w leaves v selectable (pair_keeps; Algorithm 5's
+ * rule is delta(u, v) < delta(w, v)); stop at R kept.  Writes the kept ids /
+ * distances to out_ids / out_dist (R slots) and returns their number. */
+static uint32_t select_one(const prune_ctx* c, uint64_t u, uint32_t* out_ids, float* out_dist)
+{
+    uint32_t ns = 0;
+    for (uint32_t s = 0; s < c->k && ns < c->R; ++s) {
+        uint32_t v = c->ids[u * c->k + s];
+        if (v == ORC_NONE) break;
+        float duv = c->dist[u * c->k + s];
+        int keep = c->T[v] == 1;
+        if (!keep) {
+            keep = 1;
+            for (uint32_t q = 0; q < ns; ++q) {
+                uint32_t w = out_ids[q];
+                float dwv = oracle_distance(c->X + (uint64_t)w * c->ld,
+                                            c->X + (uint64_t)v * c->ld, c->dim, c->metric);
+                if (!pair_keeps(c, duv, dwv)) { keep = 0; break; }
+            }
+        }
+        if (keep) {
+            out_ids[ns] = v;
+            out_dist[ns] = duv;
+            ++ns;
+        }
+    }
+    return ns;
+}
+
 static void select_range(void* p, uint64_t b, uint64_t e, int tid)
 {
     (void)tid;
     prune_ctx* c = (prune_ctx*)p;
-    for (uint64_t u = b; u < e; ++u) {
-        uint32_t ns = 0;
-        for (uint32_t s = 0; s < c->k && ns < c->R; ++s) {
-            uint32_t v = c->ids[u * c->k + s];
-            if (v == ORC_NONE) break;
-            float duv = c->dist[u * c->k + s];
-            int keep = c->T[v] == 1;
-            if (!keep) {
-                keep = 1;
-                for (uint32_t q = 0; q < ns; ++q) {
-                    uint32_t w = c->sel_ids[u * c->R + q];
-                    float dwv = oracle_distance(c->X + (uint64_t)w * c->ld,
-                                                c->X + (uint64_t)v * c->ld, c->dim, c->metric);
-                    if (!(duv < dwv)) { keep = 0; break; }
-                }
-            }
-            if (keep) {
-                c->sel_ids[u * c->R + ns] = v;
-                c->sel_dist[u * c->R + ns] = duv;
-                ++ns;
-            }
-        }
-        c->sel_n[u] = ns;
-    }
+    for (uint64_t u = b; u < e; ++u)
+        c->sel_n[u] = select_one(c, u, c->sel_ids + u * c->R, c->sel_dist + u * c->R);
 }
 
 /*
@@ -870,12 +921,22 @@ static void select_range(void* p, uint64_t b, uint64_t e, int tid)
  * id-unique union of u's selected neighbours and {v : u selected by v}.
  * Writes out_ids (N x R, NONE padded), out_dist (nullable) and out_deg.
  */
+static int rule_ok(int rule, float param, int metric)
+{
+    if (rule == ORC_SEL_RNG) return 1;
+    if (metric == ORC_IP) return 0;   /* not a metric: transform MIPS to L2 first */
+    if (rule == ORC_SEL_ALPHA) return param >= 1.0f;
+    if (rule == ORC_SEL_TAU) return param >= 0.0f;
+    return 0;
+}
+
 int oracle_prune(const float* X, uint64_t ld, uint32_t dim, int metric, uint64_t N,
                  uint32_t k, const uint32_t* ids, const float* dist, const uint32_t* T,
                  uint32_t R, uint32_t* out_ids, float* out_dist, uint32_t* out_deg,
-                 int threads)
+                 int threads, int rule, float param)
 {
     if (!X || !ids || !dist || !T || !out_ids || !out_deg || R == 0 || k == 0) return -1;
+    if (!rule_ok(rule, param, metric)) return -1;
     for (uint64_t i = 0; i < N * k; ++i)
         if (ids[i] != ORC_NONE && ids[i] >= N) return -1;
     uint32_t* sel_ids = (uint32_t*)malloc(sizeof(uint32_t) * N * R);
@@ -886,7 +947,7 @@ int oracle_prune(const float* X, uint64_t ld, uint32_t dim, int metric, uint64_t
         free(sel_ids); free(sel_dist); free(sel_n); free(roff);
         return -1;
     }
-    prune_ctx c = {X, ld, dim, metric, k, R, ids, dist, T, sel_ids, sel_dist, sel_n};
+    prune_ctx c = {X, ld, dim, metric, k, R, ids, dist, T, sel_ids, sel_dist, sel_n, rule, param};
     parallel_for(N, threads, select_range, &c);
 
     for (uint64_t u = 0; u < N; ++u)
@@ -937,6 +998,109 @@ int oracle_prune(const float* X, uint64_t ld, uint32_t dim, int metric, uint64_t
     return ok ? 0 : -1;
 }
 
+/* Stage 3 for the listed vertices only, on the full N x k lists: row r of
+ * out_ids / out_dist / out_deg is what oracle_prune writes for vertex
+ * rows[r].  Each listed u takes its own selection and the reverse of every
+ * selection that picks u; the vertices that can pick u are those whose list
+ * holds u, found through an inverted index of the lists.  Selections are
+ * computed for u and those vertices only, so a sample of a large graph costs
+ * a few selections per listed vertex. */
+typedef struct {
+    const prune_ctx* c;
+    const uint64_t* rows;
+    const uint64_t* in_off;   /* inverted index: lists holding v */
+    const uint32_t* in_src;
+    uint32_t* out_ids;
+    float* out_dist;
+    uint32_t* out_deg;
+    int* err;
+} prune_rows_ctx;
+
+static void prune_rows_range(void* p, uint64_t b, uint64_t e, int tid)
+{
+    prune_rows_ctx* r = (prune_rows_ctx*)p;
+    const prune_ctx* c = r->c;
+    uint32_t R = c->R;
+    uint32_t* sid = (uint32_t*)malloc(sizeof(uint32_t) * ((size_t)R + 1));
+    float* sdd = (float*)malloc(sizeof(float) * ((size_t)R + 1));
+    size_t ucap = 0;
+    ent_t* U = NULL;
+    if (!sid || !sdd) { r->err[tid] = 1; free(sid); free(sdd); return; }
+    for (uint64_t idx = b; idx < e; ++idx) {
+        uint64_t u = r->rows[idx];
+        uint64_t nin = r->in_off[u + 1] - r->in_off[u];
+        if (R + nin + 1 > ucap) {
+            ucap = R + nin + 1;
+            free(U);
+            U = (ent_t*)malloc(sizeof(ent_t) * ucap);
+            if (!U) { r->err[tid] = 1; break; }
+        }
+        size_t m = 0;
+        uint32_t ns = select_one(c, u, sid, sdd);
+        for (uint32_t q = 0; q < ns; ++q) U[m++] = (ent_t){sdd[q], sid[q], 0};
+        for (uint64_t t = r->in_off[u]; t < r->in_off[u + 1]; ++t) {
+            uint32_t v = r->in_src[t];
+            uint32_t nv = select_one(c, v, sid, sdd);
+            for (uint32_t q = 0; q < nv; ++q)
+                if (sid[q] == (uint32_t)u) U[m++] = (ent_t){sdd[q], v, 0};
+        }
+        qsort(U, m, sizeof(ent_t), ent_cmp);
+        uint32_t o = 0;
+        for (size_t t = 0; t < m && o < R; ++t) {
+            if (o && r->out_ids[idx * R + o - 1] == U[t].id) continue;
+            r->out_ids[idx * R + o] = U[t].id;
+            r->out_dist[idx * R + o] = U[t].d;
+            ++o;
+        }
+        r->out_deg[idx] = o;
+        for (; o < R; ++o) {
+            r->out_ids[idx * R + o] = ORC_NONE;
+            r->out_dist[idx * R + o] = INFINITY;
+        }
+    }
+    free(sid);
+    free(sdd);
+    free(U);
+}
+
+int oracle_prune_rows(const float* X, uint64_t ld, uint32_t dim, int metric, uint64_t N,
+                      uint32_t k, const uint32_t* ids, const float* dist, const uint32_t* T,
+                      uint32_t R, const uint64_t* rows, uint64_t nrows, uint32_t* out_ids,
+                      float* out_dist, uint32_t* out_deg, int threads, int rule, float param)
+{
+    if (!X || !ids || !dist || !T || !rows || !out_ids || !out_dist || !out_deg || R == 0 ||
+        k == 0)
+        return -1;
+    if (!rule_ok(rule, param, metric)) return -1;
+    for (uint64_t i = 0; i < N * k; ++i)
+        if (ids[i] != ORC_NONE && ids[i] >= N) return -1;
+    for (uint64_t i = 0; i < nrows; ++i)
+        if (rows[i] >= N) return -1;
+    uint64_t* in_off = (uint64_t*)calloc(N + 2, sizeof(uint64_t));
+    uint64_t* cur = (uint64_t*)malloc(sizeof(uint64_t) * (N + 1));
+    uint32_t* in_src = (uint32_t*)malloc(sizeof(uint32_t) * (N * k + 1));
+    if (!in_off || !cur || !in_src) { free(in_off); free(cur); free(in_src); return -1; }
+    for (uint64_t i = 0; i < N * k; ++i)
+        if (ids[i] != ORC_NONE) in_off[ids[i] + 1] += 1;
+    for (uint64_t v = 0; v < N; ++v) in_off[v + 1] += in_off[v];
+    memcpy(cur, in_off, sizeof(uint64_t) * (N + 1));
+    for (uint64_t u = 0; u < N; ++u)
+        for (uint32_t t = 0; t < k; ++t) {
+            uint32_t v = ids[u * k + t];
+            if (v != ORC_NONE) in_src[cur[v]++] = (uint32_t)u;
+        }
+    prune_ctx c = {X, ld, dim, metric, k, R, ids, dist, T, NULL, NULL, NULL, rule, param};
+    int err[256] = {0};
+    prune_rows_ctx rc = {&c, rows, in_off, in_src, out_ids, out_dist, out_deg, err};
+    parallel_for(nrows, threads, prune_rows_range, &rc);
+    int bad = 0;
+    for (int t = 0; t < 256; ++t) bad |= err[t];
+    free(in_off);
+    free(cur);
+    free(in_src);
+    return bad ? -1 : 0;
+}
+
 /* Entry of the merged graph: the entry point of the largest sub-index
  * (lowest index on ties), mapped to its global id. */
 uint64_t oracle_merged_entry(const oracle_sub* subs, uint32_t h)
@@ -969,13 +1133,51 @@ int oracle_merge(const float* X, uint64_t ld, uint32_t dim, int metric,
                       1, threads, NULL))
         goto out;
     if (oracle_prune(X, ld, dim, metric, N, k, ids, dist, T, R, out_ids, NULL, out_deg,
-                     threads))
+                     threads, ORC_SEL_RNG, 0.0f))
         goto out;
     *entry = oracle_merged_entry(subs, h);
     rc = 0;
 out:
     free(ids); free(dist); free(flags); free(T);
     return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* MIPS -> L2 (the standard transformation Section 4.3.1 points to).    */
+/* ------------------------------------------------------------------ */
+
+/*
+ * Appends one coordinate to every base vector so that squared L2 ranks
+ * like inner product: with n(x) = |x|^2 and M = max_x n(x),
+ * x' = (x, sqrt(M - n(x))) has |x'|^2 = M for every row, and a query
+ * q' = (q, 0) gives |q' - x'|^2 = |q|^2 + M - 2 <q, x>, which for a fixed q
+ * orders the rows as -<q, x> does.  n(x) is the canonical FP32 squared
+ * length (oracle_distance of x to the zero vector), sqrtf is correctly
+ * rounded.  Output rows have ld_out >= dim + 4 floats: x, the extra
+ * coordinate, then zeros up to dim + 4.  *max_norm2 receives M.
+ */
+int oracle_mips_to_l2(const float* X, uint64_t n, uint64_t ld, uint32_t dim, float* out,
+                      uint64_t ld_out, float* max_norm2)
+{
+    if (!X || !out || dim == 0 || ld_out < (uint64_t)dim + 4 || n == 0) return -1;
+    float* zero = (float*)calloc(dim, sizeof(float));
+    float* nrm = (float*)malloc(sizeof(float) * n);
+    if (!zero || !nrm) { free(zero); free(nrm); return -1; }
+    float M = 0.0f;
+    for (uint64_t i = 0; i < n; ++i) {
+        nrm[i] = oracle_distance(X + i * ld, zero, dim, ORC_L2);
+        if (nrm[i] > M) M = nrm[i];
+    }
+    for (uint64_t i = 0; i < n; ++i) {
+        float* o = out + i * ld_out;
+        for (uint32_t t = 0; t < dim; ++t) o[t] = X[i * ld + t];
+        o[dim] = sqrtf(M - nrm[i]);
+        for (uint64_t t = (uint64_t)dim + 1; t < ld_out; ++t) o[t] = 0.0f;
+    }
+    if (max_norm2) *max_norm2 = M;
+    free(zero);
+    free(nrm);
+    return 0;
 }
 
 /* ------------------------------------------------------------------ */

@@ -7,7 +7,7 @@ import torch
 
 import oracle
 from helpers import NONE
-from wl import to_gpu, workload
+from wl import CFG5_SMALL, to_gpu, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -31,6 +31,7 @@ CASES = [
     ("cfg2", (2500, 2000)),
     ("cfg3", (300, 500, 700, 150, 900, 400, 1200, 650)),
     ("cfg4", (1200, 1000)),
+    ("cfg5", CFG5_SMALL),
 ]
 
 
@@ -148,7 +149,8 @@ def test_quantize_matches_oracle(prec):
 
 @pytest.mark.parametrize("prec", ["bf16", "fp8"])
 @pytest.mark.parametrize("name,sizes", [("cfg4", (1200, 1000)), ("cfg2", (2500, 2000)),
-                                        ("cfg3", (300, 500, 700, 150, 900, 400, 1200, 650))])
+                                        ("cfg3", (300, 500, 700, 150, 900, 400, 1200, 650)),
+                                        ("cfg5", CFG5_SMALL)])
 def test_precision_form_stage1_matches_oracle(prec, name, sizes):
     # The low-precision beam scores the FP32 query against decoded rows
     # (BF16 exactly, FP8 as scale * decode in one FP32 rounding) in the

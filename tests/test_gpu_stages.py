@@ -8,7 +8,7 @@ import torch
 
 import oracle
 from helpers import NONE, golden, line_points, pad_adj, pad_ids
-from wl import to_gpu, workload
+from wl import CFG5_SMALL, to_gpu, workload
 
 pytestmark = pytest.mark.gpu
 
@@ -20,6 +20,7 @@ CASES = [
     ("cfg2", (2500, 2000)),
     ("cfg3", (300, 500, 700, 150, 900, 400, 1200, 650)),
     ("cfg4", (1200, 1000)),
+    ("cfg5", CFG5_SMALL),
 ]
 IDS = [c[0] for c in CASES]
 
@@ -190,3 +191,22 @@ def test_hand_example_on_gpu():
     assert _u32(pg).tolist() == pad_ids(g["stage3"]["ids"], g["R"]).tolist()
     pg2, deg2, entry, _ = fg.merge(m, p)
     assert torch.equal(pg, pg2) and entry == g["entry"]
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_precision_form_merge_matches_oracle(prec):
+    # cfg5's form at test size: 20 uneven sub-indexes, low-precision beam with
+    # the FP32 re-rank of 64 per search, then FP32 refinement and prune.  The
+    # oracle runs the same stages on its own decoded copy.
+    cfg, X, graphs, _ = workload("cfg5", CFG5_SMALL)
+    deq = oracle.quantize_bf16(X)[1] if prec == "bf16" else oracle.quantize_fp8(X)[2]
+    rerank = min(cfg.L, 2 * cfg.k)
+    m = to_gpu(X, graphs, cfg.metric)
+    p = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds, precision=prec)
+    pg, deg, entry, st = fg.merge(m, p, stats=True)
+    oi, od, _ = oracle.cross_query(X, graphs, cfg.k, cfg.L, cfg.metric, Xs=deq, rerank=rerank)
+    i2, d2, _, T, _ = oracle.refine(X, graphs, oi, od, cfg.rounds, cfg.metric)
+    pi, pd, pdeg = oracle.prune(X, i2, d2, T, cfg.R, cfg.metric)
+    assert (_u32(pg) == pi).all() and (_u32(deg) == pdeg).all()
+    assert entry == oracle.merged_entry(graphs)
+    assert st["searches"] == X.shape[0] * (len(graphs) - 1)

@@ -395,3 +395,135 @@ def test_recall_of_the_exact_answer_is_one_on_float_data(metric):
     bi, bd = oracle.bruteforce(X, X[nodes], 10, metric, exclude=nodes)
     assert (ki == bi.astype(np.int64)).all()
     assert tie_recall(X, X[nodes], bi, kd[:, -1], 10, metric) == 1.0
+
+
+def test_prune_rows_equals_full_prune_on_its_rows():
+    # Algorithm 5 for a sample of vertices (selection of u and of every
+    # vertex whose list holds u, then the reverse fill of u) equals the
+    # rows of the full prune, including vertices that only reverse edges
+    # fill and the degree bound R < k.
+    cfg, X, subs = _cfg_small()
+    ids, dd, _ = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric)
+    i2, d2, _, T, _ = oracle.refine(X, subs, ids, dd, cfg.rounds, cfg.metric)
+    rows = np.array([0, 1, 17, 1499, 1500, 2999, 2000, 2001, 777], np.uint64)
+    for R in (cfg.R, 8):
+        fi, fd, fdeg = oracle.prune(X, i2, d2, T, R, cfg.metric)
+        ri, rd, rdeg = oracle.prune_rows(X, i2, d2, T, R, rows, cfg.metric)
+        r = rows.astype(np.int64)
+        assert (ri == fi[r]).all() and (rdeg == fdeg[r]).all()
+        assert (rd.view(np.uint32) == fd[r].view(np.uint32)).all()
+
+
+@pytest.mark.parametrize("metric", ["l2", "ip", "cos"])
+def test_screened_ground_truth_equals_oracle_bruteforce(metric):
+    # The FP32-screened ground truth (shortlist proved complete by the FP32
+    # error bound, else widened, else a direct FP64 pass) returns the
+    # oracle's FP64 brute-force answer; a shortlist of one row forces both
+    # fallbacks and still gives the same answer.
+    import torch
+    from workloads.evaluate import exact_knn_screened
+    rng = np.random.default_rng(12)
+    X = rng.normal(size=(3000, 64)).astype(np.float32)
+    Q = rng.normal(size=(200, 64)).astype(np.float32)
+    if metric != "l2":
+        X /= np.linalg.norm(X, axis=1, keepdims=True)
+        Q /= np.linalg.norm(Q, axis=1, keepdims=True)
+    oi, od = oracle.bruteforce(X, Q, 10, metric)
+    for margin, widen in ((48, 16), (-9, 1)):
+        gi, gd, fb = exact_knn_screened(X, Q, 10, metric, Xdev=torch.from_numpy(X), margin=margin,
+                                        widen=widen, block=64)
+        assert (gi == oi.astype(np.int64)).all(), margin
+        assert np.allclose(gd, od, rtol=1e-12, atol=1e-12)
+        if margin < 0:
+            assert fb["longer_shortlist"] == 200 and fb["direct_pass"] == 200
+    nodes = np.arange(0, 3000, 40)
+    gi, gd, _ = exact_knn_screened(X, X[nodes], 10, metric, exclude=nodes, Xdev=torch.from_numpy(X))
+    bi, bd = oracle.bruteforce(X, X[nodes], 10, metric, exclude=nodes)
+    assert (gi == bi.astype(np.int64)).all()
+
+
+def _line_knng(n, k, spacing=3):
+    X = line_points(np.arange(n) * spacing)
+    gi, gd = oracle.bruteforce(X, X, k, exclude=np.arange(n))
+    return X, gi, gd.astype(np.float32)
+
+
+def _sel_offsets(oi, u, spacing=3):
+    return sorted(int(v) - u for v in oi[u] if v != NONE)
+
+
+def test_alpha_rng_on_a_line():
+    # Points 3i on a line, exact 16-NN (8 per side inside), T = 2 so the T = 1
+    # exemption never applies.  alpha-RNG keeps v at j hops past a kept w at
+    # 1 hop on the same side when |u - v| < alpha |w - v|: 3j < 1.25 * 3(j - 1)
+    # holds first for j = 6 (j = 5 is the tie 15 = 15, which strict < drops);
+    # after that the next survivor would need j > 30.  A neighbour on the other
+    # side is always farther from v than u is.  alpha = 1.25 is exact in
+    # binary, so the hand result is exact.  The selection stops at R = 8, the
+    # reverse fill adds the mirror edges.
+    n, k = 40, 16
+    X, gi, gd = _line_knng(n, k)
+    T = np.full(n, 2, np.uint32)
+    sel, _, _ = oracle.prune(X, gi, gd, T, 8, rule="alpha", param=1.25)
+    assert _sel_offsets(sel, 20) == [-6, -1, 1, 6]
+    assert _sel_offsets(sel, 0) == [1, 6]
+    # alpha = 1 is Algorithm 5's rule exactly (alpha^2 * delta = delta)
+    a1, _, _ = oracle.prune(X, gi, gd, T, 8, rule="alpha", param=1.0)
+    r1, _, _ = oracle.prune(X, gi, gd, T, 8)
+    assert (a1 == r1).all() and _sel_offsets(r1, 20) == [-1, 1]
+
+
+def test_tau_mng_on_a_line():
+    # tau-MNG: w occludes v when |w - v| < |u - v| - 3 tau.  On the same line
+    # v at j hops survives the kept w at i hops iff 3j < 3(j - i) + 3 tau, i.e.
+    # i < tau.  tau = 1: only the first hop per side (the path graph, like
+    # RNG); tau = 1.5: hops 1 and 2 survive hop 1, hop 3 is occluded by hop 2,
+    # and so is every later one.  Distances are perfect squares, so every
+    # square root is exact.
+    n, k = 40, 16
+    X, gi, gd = _line_knng(n, k)
+    T = np.full(n, 2, np.uint32)
+    t1, _, _ = oracle.prune(X, gi, gd, T, 8, rule="tau", param=1.0)
+    assert _sel_offsets(t1, 20) == [-1, 1]
+    t15, _, _ = oracle.prune(X, gi, gd, T, 8, rule="tau", param=1.5)
+    assert _sel_offsets(t15, 20) == [-2, -1, 1, 2]
+    # a tau larger than every distance occludes nothing: the first R of the
+    # list, then the reverse fill truncated to R
+    big, _, _ = oracle.prune(X, gi, gd, T, 16, rule="tau", param=1000.0)
+    assert sorted(big[20].tolist()) == sorted(gi[20].tolist())
+
+
+def test_selection_rules_keep_the_only_in_edge_and_reject_inner_product():
+    n, k = 30, 6
+    X, gi, gd = _line_knng(n, k)
+    T = np.full(n, 2, np.uint32)
+    T[14] = 1   # 14 is occluded in the lists of 11 and 12 under every rule here
+    for rule, param in (("alpha", 1.2), ("tau", 0.5)):
+        oi, _, _ = oracle.prune(X, gi, gd, T, 8, rule=rule, param=param)
+        assert 14 in oi[11].tolist() and 14 in oi[12].tolist()
+    with pytest.raises(ValueError):
+        oracle.prune(X, gi, gd, T, 8, metric="ip", rule="alpha", param=1.2)
+    with pytest.raises(ValueError):
+        oracle.prune(X, gi, gd, T, 8, rule="alpha", param=0.9)
+
+
+def test_mips_to_l2_transform():
+    # x' = (x, sqrt(M - |x|^2)): every row has squared length M (up to FP32
+    # rounding of the extra coordinate), the longest row gets 0, and with
+    # q' = (q, 0) squared L2 equals |q|^2 + M - 2<q, x>, so the exact L2 k-NN
+    # on the transformed rows are the exact inner-product k-NN.
+    rng = np.random.default_rng(21)
+    X = (rng.normal(size=(3000, 32)) * rng.uniform(0.2, 3.0, (3000, 1))).astype(np.float32)
+    Q = rng.normal(size=(100, 32)).astype(np.float32)
+    Xt, M = oracle.mips_to_l2(X)
+    assert Xt.shape == (3000, 36) and (Xt[:, 33:] == 0).all() and (Xt[:, :32] == X).all()
+    n2 = (X.astype(np.float64) ** 2).sum(1)
+    assert M == pytest.approx(n2.max(), rel=1e-5)
+    assert Xt[np.argmax(n2), 32] == 0.0
+    assert np.allclose((Xt.astype(np.float64) ** 2).sum(1), M, rtol=2e-6)
+    Qt = np.zeros((100, 36), np.float32)
+    Qt[:, :32] = Q
+    li, _ = oracle.bruteforce(Xt, Qt, 10, "l2")
+    ii, _ = oracle.bruteforce(X, Q, 10, "ip")
+    agree = (li == ii).mean()
+    assert agree > 0.99, agree

@@ -6,6 +6,11 @@ import torch
 
 from workloads import build_input_pg, get_config, make_queries, make_vectors, split_sizes
 
+# cfg5's parameter set (h = 20 uneven sub-indexes, d = 128, R_in = 48, k = 32,
+# L = 96: two pool registers, R = 48) at a size the oracle finishes in seconds
+CFG5_SMALL = (900, 700, 650, 800, 120, 60, 300, 210, 95, 150, 400, 70, 250, 180, 110, 330, 90,
+              140, 75, 170)
+
 
 @functools.lru_cache(maxsize=None)
 def workload(name, sizes=None, device=None):

@@ -72,6 +72,70 @@ def exact_knn_fp64(X: np.ndarray, Q: np.ndarray, k: int, metric: str = "l2",
     return ids, dd
 
 
+def exact_knn_screened(X: np.ndarray, Q: np.ndarray, k: int, metric: str = "l2",
+                       exclude: np.ndarray | None = None, Xdev: torch.Tensor | None = None,
+                       block: int = 1024, margin: int = 48, widen: int = 16):
+    """exact_knn_fp64 with the shortlist screened in FP32 on the GPU (torch
+    matmul: evaluation arithmetic, not the merge).  Every shortlist is
+    re-ranked by the direct FP64 form on the CPU, and its completeness is
+    proved per query: an FP32 Gram-form distance of d products is within
+    B = 4 gamma_d (|q|^2 + max|x|^2) of the exact value (gamma_d =
+    d u / (1 - d u), u = 2^-24, covering any summation order, doubled), so
+    when the shortlist's last FP32 distance minus B exceeds the direct k-th
+    distance, no row outside it can be among the k nearest.  Queries that
+    fail the test get a 16x longer shortlist, then the direct FP64 pass over
+    every row.  Returns what exact_knn_fp64 returns, and the count of
+    queries that needed each fallback.  margin and widen set the two shortlist
+    lengths, k + margin and widen (k + margin)."""
+    dev = Xdev.device if Xdev is not None else torch.device("cuda")
+    Xg = Xdev if Xdev is not None else torch.from_numpy(np.ascontiguousarray(X)).to(dev)
+    n, d = Xg.shape
+    sqx = (Xg * Xg).sum(1)
+    sqmax = float((torch.from_numpy(np.ascontiguousarray(X)).to(torch.float64) ** 2).sum(1).max())
+    u = 2.0 ** -24
+    gamma = d * u / (1.0 - d * u)
+    nq = Q.shape[0]
+    ids = np.empty((nq, k), np.int64)
+    dd = np.empty((nq, k), np.float64)
+    fallback = [0, 0]
+    for s in range(0, nq, block):
+        e = min(nq, s + block)
+        Qg = torch.from_numpy(np.ascontiguousarray(Q[s:e])).to(dev)
+        G = Qg @ Xg.T
+        if metric == "l2":
+            D = (Qg * Qg).sum(1)[:, None] + sqx[None, :] - 2.0 * G
+        elif metric == "ip":
+            D = -G
+        else:
+            D = 1.0 - G
+        if exclude is not None:
+            ex = torch.from_numpy(np.asarray(exclude[s:e], np.int64)).to(dev)
+            D[torch.arange(e - s, device=dev), ex] = float("inf")
+        qsq = (Q[s:e].astype(np.float64) ** 2).sum(1)
+        bound = 4.0 * gamma * (qsq + sqmax)
+        todo = np.arange(e - s)
+        for tier, m in enumerate((min(n, k + margin), min(n, widen * (k + margin)))):
+            v, i = torch.topk(D[torch.from_numpy(todo).to(dev)], m, dim=1, largest=False, sorted=True)
+            cand = i.cpu().numpy()
+            last = v[:, -1].double().cpu().numpy()
+            dc = dist64_rows(X, Q[s + todo], cand.astype(np.uint32), metric)
+            if exclude is not None:
+                dc[cand == np.asarray(exclude, np.int64)[s + todo][:, None]] = np.inf
+            order = np.lexsort((cand, dc), axis=1)
+            cs = np.take_along_axis(cand, order, 1)[:, :k]
+            ds = np.take_along_axis(dc, order, 1)[:, :k]
+            ok = (m >= n) | (last - bound[todo] > ds[:, -1])
+            ids[s + todo[ok]], dd[s + todo[ok]] = cs[ok], ds[ok]
+            todo = todo[~ok]
+            if todo.size == 0:
+                break
+            fallback[tier] += int(todo.size)
+        for r in todo:
+            ex = None if exclude is None else int(exclude[s + r])
+            ids[s + r], dd[s + r] = _direct_knn_one(X, Q[s + r], k, metric, ex)
+    return ids, dd, {"longer_shortlist": fallback[0], "direct_pass": fallback[1]}
+
+
 def _direct_knn_one(X: np.ndarray, q: np.ndarray, k: int, metric: str, exclude=None,
                     chunk: int = 1 << 18):
     """Exact k-NN of one query by the direct FP64 form over every base row,
