@@ -6,7 +6,7 @@
  * graphs G_i = (V_i, E_i), built over disjoint vector sets X_i with one
  * distance delta, into one graph over X = U X_i (problem definition
  * "Merging Graph-based Indexes for ANNS", Section 2.1).  It runs in three
- * stages (Section 3.2): PGs -> k-NNG by cross-querying (Section 4.1,
+ * stages (Section 3.3): PGs -> k-NNG by cross-querying (Section 4.1,
  * Algorithm 2), k-NNG refinement with indegree repair (Section 4.2,
  * Algorithms 3 and 4) and k-NNG -> PG by neighbour selection plus reverse
  * edges (Section 4.3, Algorithm 5).
@@ -98,6 +98,13 @@ typedef struct {
      * library quantises into scratch inside the call. */
     const void* base_lp;
     const float* base_lp_scale; /* device, n_total FP8 scales (FP8 only) */
+    /* Validity of the ID mapping phi (Section 4.1.3; deletions and
+     * overlapping copies, Exp. 8): device, n_total bytes, 1 = retained,
+     * 0 = deleted or a duplicate to drop; NULL = every vertex retained.
+     * A dropped vertex gets an empty row (FGIM_NONE, +inf, degree 0) and is
+     * never a neighbour in any output; the cross-query searches still route
+     * through it, since it is part of its input graph. */
+    const uint8_t* valid;
 } fgim_dataset;
 
 typedef struct {
@@ -117,7 +124,27 @@ typedef struct {
     uint32_t waves_per_cu;     /* resident waves per compute unit of the beam kernel */
     uint32_t visited_slots;    /* entries of the per-wave LDS visited cache (power of 2) */
     uint32_t flags;            /* FGIM_FLAG_* */
+    /* Neighbour-selection rule of stage 3 (Section 4.3.1 names RNG and, as
+     * swap-ins, alpha-RNG and tau-MNG); FGIM_SELECT_RNG is Algorithm 5. */
+    uint32_t select_rule;      /* FGIM_SELECT_* */
+    float select_param;        /* alpha (>= 1) or tau (>= 0); unused by RNG */
 } fgim_params;
+
+/* Selection rules: whether a kept neighbour w, at delta(w, v) from the
+ * candidate v, leaves v selectable for u (delta(u, v) from u).  A v with
+ * indegree T(v) = 1 is kept under every rule.
+ *  RNG:   delta(u,v) < delta(w,v).
+ *  ALPHA: |u-v| < alpha |w-v| on Euclidean distances (Vamana's robust
+ *         prune); on delta (squared L2, or half of it for cosine on unit
+ *         vectors) delta(u,v) < fl(fl(alpha * alpha) * delta(w,v)).
+ *  TAU:   w occludes v when |w-v| < |u-v| - 3 tau (the tau-monotonic
+ *         graph's rule); v survives when e(u,v) < fl(e(w,v) + fl(3 tau)),
+ *         e = sqrt(delta) (L2) or sqrt(2 delta) (cosine), correctly rounded.
+ * ALPHA and TAU need a metric distance: L2 or cosine (for inner product,
+ * transform the data with fgim_mips_to_l2 and merge under L2). */
+#define FGIM_SELECT_RNG 0u
+#define FGIM_SELECT_ALPHA 1u
+#define FGIM_SELECT_TAU 2u
 
 #define FGIM_FLAG_NO_REPAIR 1u     /* refinement without indegree repair (test hook) */
 #define FGIM_FLAG_NO_GRAPH_CAPTURE 2u /* run refinement rounds eagerly, not as a hipGraph */
@@ -232,9 +259,12 @@ fgim_status fgim_prune(const fgim_dataset* data, const fgim_params* params,
                        void* stream);
 
 /*
- * The three stages in one call (Section 3.2).  Outputs: pg_ids, pg_deg as
+ * The three stages in one call (Section 3.3).  Outputs: pg_ids, pg_deg as
  * fgim_prune; *entry (host) = global id of the merged graph's entry point,
- * the entry of the largest sub-index (lowest index on ties).  Synchronises.
+ * the entry of the largest sub-index (lowest index on ties).  With validity
+ * flags, when that entry is dropped: the smallest retained id of the same
+ * sub-index; a sub-index with no retained vertex is passed over for the next
+ * largest; FGIM_NONE when nothing is retained.  Synchronises.
  */
 fgim_status fgim_merge(const fgim_dataset* data, const fgim_params* params,
                        uint32_t* pg_ids, uint32_t* pg_deg, uint32_t* entry,
@@ -261,6 +291,23 @@ fgim_status fgim_search(const float* base, uint64_t n, uint32_t dim, uint64_t ld
 fgim_status fgim_quantize(const float* base, uint64_t n, uint32_t dim, uint64_t ld,
                           fgim_precision precision, void* codes, float* scales,
                           void* stream);
+
+/*
+ * The standard transformation of maximum-inner-product search to L2 that
+ * Section 4.3.1 points to, so that the distance-based selection rules apply
+ * to inner-product data: with n(x) = |x|^2 (canonical FP32 sum) and
+ * M = max n(x), row x becomes x' = (x, sqrt(M - n(x)), 0, 0, 0): every x'
+ * has squared length M, and a query padded as q' = (q, 0, 0, 0, 0) gives
+ * |q' - x'|^2 = |q|^2 + M - 2 <q, x>, which orders rows as -<q, x> does.
+ * Merge the transformed rows under FGIM_L2.
+ * Input base (device, n rows of ld floats, dim a multiple of 4); output out
+ * (device, n rows of ld_out >= dim + 4 floats, 16-byte aligned; only the
+ * first dim + 4 floats of a row are written); *max_norm2 (device, 1 float)
+ * receives M.  The square root is correctly rounded.
+ * Errors: FGIM_ERR_INVALID_ARG.
+ */
+fgim_status fgim_mips_to_l2(const float* base, uint64_t n, uint32_t dim, uint64_t ld, float* out,
+                            uint64_t ld_out, float* max_norm2, void* stream);
 
 /* ceil((k - min_local) / (h - 1)), at least 1: the smallest L for which
  * every vertex still collects k candidates (minimum querying strategy,

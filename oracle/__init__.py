@@ -63,7 +63,7 @@ def lib() -> ctypes.CDLL:
                                         vp, vp, vp, vp]
         L.oracle_cross_query.restype = i32
         L.oracle_cross_query.argtypes = [vp, vp, u64, u32, i32, vp, u32, u32, u32, u32,
-                                         vp, u64, vp, vp, i32, vp]
+                                         vp, u64, vp, vp, i32, vp, vp]
         L.oracle_min_L.restype = u32
         L.oracle_min_L.argtypes = [u32, u32, u32]
         L.oracle_repair.restype = i32
@@ -80,10 +80,10 @@ def lib() -> ctypes.CDLL:
         L.oracle_prune_rows.argtypes = [vp, u64, u32, i32, u64, u32, vp, vp, vp, u32, vp, u64,
                                         vp, vp, vp, i32, i32, ctypes.c_float]
         L.oracle_merged_entry.restype = u64
-        L.oracle_merged_entry.argtypes = [vp, u32]
+        L.oracle_merged_entry.argtypes = [vp, u32, vp]
         L.oracle_merge.restype = i32
         L.oracle_merge.argtypes = [vp, u64, u32, i32, vp, u32, u32, u32, u32, u32, u32, vp,
-                                   vp, vp, i32]
+                                   vp, vp, i32, vp]
         L.oracle_bruteforce.restype = i32
         L.oracle_bruteforce.argtypes = [vp, u64, u64, u32, i32, vp, u64, u64, u32, vp, vp,
                                         vp, i32]
@@ -153,10 +153,21 @@ def knn_search(q, Xj, adj, entry: int, L: int, metric: str = "l2"):
     return ids[:n].copy(), dd[:n].copy(), ndc.value, nexp.value
 
 
+def _valid(valid, n):
+    if valid is None:
+        return None
+    v = np.ascontiguousarray(valid, dtype=np.uint8)
+    if v.shape != (n,):
+        raise ValueError(f"valid must have {n} flags")
+    return v
+
+
 def cross_query(X, subs, k: int, L: int, metric: str = "l2", nodes=None,
-                Xs=None, rerank: int = 0, threads: Optional[int] = None):
-    """Stage 1 (Algorithm 2) for `nodes` (all when None): (ids, dists, stats)."""
+                Xs=None, rerank: int = 0, threads: Optional[int] = None, valid=None):
+    """Stage 1 (Algorithm 2) for `nodes` (all when None): (ids, dists, stats).
+    valid (uint8 [N], optional): phi's validity flag of every global id."""
     X = _f32(X)
+    vf = _valid(valid, X.shape[0])
     Xs_ = None if Xs is None else _f32(Xs)
     arr, keep = _subs(subs)
     if nodes is None:
@@ -172,7 +183,8 @@ def cross_query(X, subs, k: int, L: int, metric: str = "l2", nodes=None,
     rc = lib().oracle_cross_query(_p(X), None if Xs_ is None else _p(Xs_), X.shape[1],
                                   X.shape[1], METRICS[metric], ctypes.addressof(arr),
                                   len(subs), k, L, rerank, nptr, nn, _p(ids), _p(dd),
-                                  threads or default_threads(), _p(st))
+                                  threads or default_threads(), _p(st),
+                                  None if vf is None else _p(vf))
     if rc:
         raise ValueError("oracle_cross_query failed")
     return ids, dd, {"ndc": int(st[0]), "expansions": int(st[1])}
@@ -274,23 +286,28 @@ def mips_to_l2(X):
     return out, M.value
 
 
-def merged_entry(subs) -> int:
+def merged_entry(subs, valid=None) -> int:
     arr, keep = _subs(subs)
-    return int(lib().oracle_merged_entry(ctypes.addressof(arr), len(subs)))
+    n = sum(int(np.asarray(a).shape[0]) for _, a, _ in subs)
+    vf = _valid(valid, n)
+    return int(lib().oracle_merged_entry(ctypes.addressof(arr), len(subs),
+                                         None if vf is None else _p(vf)))
 
 
 def merge(X, subs, k: int, L: int, rounds: int, R: int, metric: str = "l2",
-          k_rev: int = 0, threads: Optional[int] = None):
-    """All three stages: (pg_ids [N, R], deg, entry)."""
+          k_rev: int = 0, threads: Optional[int] = None, valid=None):
+    """All three stages: (pg_ids [N, R], deg, entry).  valid: as cross_query."""
     X = _f32(X)
     arr, keep = _subs(subs)
     N = X.shape[0]
+    vf = _valid(valid, N)
     oi = np.empty((N, R), np.uint32)
     deg = np.empty(N, np.uint32)
     ent = ctypes.c_uint64()
     rc = lib().oracle_merge(_p(X), X.shape[1], X.shape[1], METRICS[metric],
                             ctypes.addressof(arr), len(subs), k, L, rounds, k_rev, R,
-                            _p(oi), _p(deg), ctypes.byref(ent), threads or default_threads())
+                            _p(oi), _p(deg), ctypes.byref(ent), threads or default_threads(),
+                            None if vf is None else _p(vf))
     if rc:
         raise ValueError("oracle_merge failed")
     return oi, deg, ent.value

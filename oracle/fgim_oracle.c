@@ -274,6 +274,7 @@ typedef struct {
     uint64_t* ndc_t;      /* per thread */
     uint64_t* exp_t;
     int* err_t;
+    const uint8_t* valid; /* phi's validity flag per global id (NULL: all valid) */
 } cq_ctx;
 
 /*
@@ -283,6 +284,13 @@ typedef struct {
  * and cut to k.  When the beam scores rows of a low-precision copy (Xs !=
  * X), each search's first `rerank` results are re-scored on the FP32 rows
  * before they enter the union.
+ *
+ * phi's validity (Section 4.1.3): phi maps only retained vertices.  An
+ * invalid u gets an empty list; an invalid vertex is never a candidate (not
+ * in C+, not among a search's results), but the searches still route
+ * through it, since it is part of G_j's structure.  A search's results are
+ * the valid entries of its final pool, in pool order; with a low-precision
+ * copy the first `rerank` of them are re-scored.
  */
 static void cq_range(void* p, uint64_t b, uint64_t e, int tid)
 {
@@ -305,6 +313,13 @@ static void cq_range(void* p, uint64_t b, uint64_t e, int tid)
         uint64_t u = c->nodes ? c->nodes[idx] : idx;
         uint32_t gi = sub_of(c->subs, c->h, u);
         if (gi >= c->h) { c->err_t[tid] = 1; continue; }
+        if (c->valid && !c->valid[u]) {
+            for (uint32_t t = 0; t < c->k; ++t) {
+                c->out_ids[idx * c->k + t] = ORC_NONE;
+                c->out_dist[idx * c->k + t] = INFINITY;
+            }
+            continue;
+        }
         const oracle_sub* si = &c->subs[gi];
         const float* xu = c->X + u * c->ld;
         uint64_t lu = u - si->off;
@@ -313,6 +328,7 @@ static void cq_range(void* p, uint64_t b, uint64_t e, int tid)
             uint32_t v = si->adj[lu * si->stride + t];
             if (v == ORC_NONE) continue;
             uint64_t gv = si->off + v;
+            if (c->valid && !c->valid[gv]) continue;
             U[nu++] = (ent_t){oracle_distance(xu, c->X + gv * c->ld, c->dim, c->metric),
                               (uint32_t)gv, FLAG_NEW};
         }
@@ -323,14 +339,16 @@ static void cq_range(void* p, uint64_t b, uint64_t e, int tid)
             uint32_t cnt = knn_search(xu, Xj, c->ld, c->dim, c->metric, sj->adj,
                                       sj->stride, sj->entry, c->L, &ws,
                                       &c->ndc_t[tid], &c->exp_t[tid]);
-            uint32_t take = cnt;
+            uint32_t take = cnt, taken = 0;
             if (c->Xs != c->X && c->rerank < take) take = c->rerank;
-            for (uint32_t t = 0; t < take; ++t) {
+            for (uint32_t t = 0; t < cnt && taken < take; ++t) {
                 uint64_t gv = sj->off + ws.pool[t].id;
+                if (c->valid && !c->valid[gv]) continue;
                 float dv = ws.pool[t].d;
                 if (c->Xs != c->X)
                     dv = oracle_distance(xu, c->X + gv * c->ld, c->dim, c->metric);
                 U[nu++] = (ent_t){dv, (uint32_t)gv, FLAG_NEW};
+                ++taken;
             }
         }
         qsort(U, nu, sizeof(ent_t), ent_cmp);
@@ -353,7 +371,7 @@ int oracle_cross_query(const float* X, const float* Xs, uint64_t ld, uint32_t di
                        int metric, const oracle_sub* subs, uint32_t h, uint32_t k,
                        uint32_t L, uint32_t rerank, const uint64_t* nodes,
                        uint64_t n_nodes, uint32_t* out_ids, float* out_dist,
-                       int threads, uint64_t* stats)
+                       int threads, uint64_t* stats, const uint8_t* valid)
 {
     if (!X || !subs || h < 1 || k == 0 || L == 0 || dim == 0 || dim > 4096) return -1;
     for (uint32_t i = 0; i < h; ++i)
@@ -362,7 +380,7 @@ int oracle_cross_query(const float* X, const float* Xs, uint64_t ld, uint32_t di
     uint64_t ndc[256] = {0}, ex[256] = {0};
     int err[256] = {0};
     cq_ctx c = {X, Xs ? Xs : X, ld, dim, metric, subs, h, k, L, rerank ? rerank : L,
-                nodes, out_ids, out_dist, ndc, ex, err};
+                nodes, out_ids, out_dist, ndc, ex, err, valid};
     parallel_for(n_nodes, threads, cq_range, &c);
     uint64_t a = 0, bsum = 0;
     int bad = 0;
@@ -1102,20 +1120,34 @@ int oracle_prune_rows(const float* X, uint64_t ld, uint32_t dim, int metric, uin
 }
 
 /* Entry of the merged graph: the entry point of the largest sub-index
- * (lowest index on ties), mapped to its global id. */
-uint64_t oracle_merged_entry(const oracle_sub* subs, uint32_t h)
+ * (lowest index on ties), mapped to its global id.  With validity flags
+ * (nullable): when that entry is invalid, the smallest valid global id of
+ * the same sub-index; sub-indexes without a valid vertex are passed over
+ * (next largest, lowest index on ties); ORC_NONE when no vertex is valid. */
+uint64_t oracle_merged_entry(const oracle_sub* subs, uint32_t h, const uint8_t* valid)
 {
-    uint32_t best = 0;
-    for (uint32_t i = 1; i < h; ++i)
-        if (subs[i].n > subs[best].n) best = i;
-    return subs[best].off + subs[best].entry;
+    uint8_t* used = (uint8_t*)calloc(h ? h : 1, 1);
+    uint64_t out = ORC_NONE;
+    for (uint32_t round = 0; round < h && used; ++round) {
+        uint32_t best = h;
+        for (uint32_t i = 0; i < h; ++i)
+            if (!used[i] && (best == h || subs[i].n > subs[best].n)) best = i;
+        used[best] = 1;
+        uint64_t e = subs[best].off + subs[best].entry;
+        if (!valid || valid[e]) { out = e; break; }
+        for (uint64_t g = subs[best].off; g < subs[best].off + subs[best].n; ++g)
+            if (valid[g]) { out = g; break; }
+        if (out != ORC_NONE) break;
+    }
+    free(used);
+    return out;
 }
 
 /* All three stages.  out_ids N x R, out_deg N, *entry. */
 int oracle_merge(const float* X, uint64_t ld, uint32_t dim, int metric,
                  const oracle_sub* subs, uint32_t h, uint32_t k, uint32_t L,
                  uint32_t rounds, uint32_t k_rev, uint32_t R, uint32_t* out_ids,
-                 uint32_t* out_deg, uint64_t* entry, int threads)
+                 uint32_t* out_deg, uint64_t* entry, int threads, const uint8_t* valid)
 {
     uint64_t N = 0;
     for (uint32_t i = 0; i < h; ++i) N += subs[i].n;
@@ -1126,7 +1158,7 @@ int oracle_merge(const float* X, uint64_t ld, uint32_t dim, int metric,
     int rc = -1;
     if (!ids || !dist || !flags || !T) goto out;
     if (oracle_cross_query(X, NULL, ld, dim, metric, subs, h, k, L, 0, NULL, N, ids, dist,
-                           threads, NULL))
+                           threads, NULL, valid))
         goto out;
     for (uint64_t i = 0; i < N * k; ++i) flags[i] = ids[i] == ORC_NONE ? 0 : FLAG_NEW;
     if (oracle_refine(X, ld, dim, metric, subs, h, N, k, rounds, k_rev, ids, dist, flags, T,
@@ -1135,7 +1167,7 @@ int oracle_merge(const float* X, uint64_t ld, uint32_t dim, int metric,
     if (oracle_prune(X, ld, dim, metric, N, k, ids, dist, T, R, out_ids, NULL, out_deg,
                      threads, ORC_SEL_RNG, 0.0f))
         goto out;
-    *entry = oracle_merged_entry(subs, h);
+    *entry = oracle_merged_entry(subs, h, valid);
     rc = 0;
 out:
     free(ids); free(dist); free(flags); free(T);

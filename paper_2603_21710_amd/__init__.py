@@ -26,13 +26,14 @@ FGIM_FLAG_NO_GRAPH_CAPTURE = 2
 FGIM_FLAG_NO_MFMA_SCREEN = 4
 FGIM_FLAG_MIN_BUFFERS = 8
 METRICS = {"l2": FGIM_L2, "ip": FGIM_IP, "cos": FGIM_COSINE}
+SELECT_RULES = {"rng": 0, "alpha": 1, "tau": 2}
 PRECISIONS = {"fp32": FGIM_FP32, "bf16": FGIM_BF16, "fp8": FGIM_FP8_E4M3}
 
 STATUS = {0: "FGIM_OK", 1: "FGIM_ERR_INVALID_ARG", 2: "FGIM_ERR_GRAPH",
           3: "FGIM_ERR_OUT_OF_MEMORY", 4: "FGIM_ERR_DEVICE", 5: "FGIM_ERR_UNSUPPORTED"}
 
 EXPORTS = ["fgim_cross_query", "fgim_cross_query_noalloc", "fgim_refine", "fgim_repair", "fgim_prune",
-           "fgim_merge", "fgim_search",
+           "fgim_merge", "fgim_search", "fgim_mips_to_l2",
            "fgim_quantize", "fgim_min_beam_width", "fgim_release_scratch", "fgim_status_string",
            "fgim_last_error"]
 
@@ -54,7 +55,8 @@ class Dataset(ctypes.Structure):
     _fields_ = [("base", ctypes.c_void_p), ("n_total", ctypes.c_uint64),
                 ("dim", ctypes.c_uint32), ("ld", ctypes.c_uint64), ("metric", ctypes.c_int),
                 ("subs", ctypes.c_void_p), ("h", ctypes.c_uint32),
-                ("base_lp", ctypes.c_void_p), ("base_lp_scale", ctypes.c_void_p)]
+                ("base_lp", ctypes.c_void_p), ("base_lp_scale", ctypes.c_void_p),
+                ("valid", ctypes.c_void_p)]
 
 
 class Params(ctypes.Structure):
@@ -63,7 +65,8 @@ class Params(ctypes.Structure):
                 ("rerank", ctypes.c_uint32), ("k_rev", ctypes.c_uint32),
                 ("autotune", ctypes.c_int), ("lanes_per_dist", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("visited_slots", ctypes.c_uint32),
-                ("flags", ctypes.c_uint32)]
+                ("flags", ctypes.c_uint32), ("select_rule", ctypes.c_uint32),
+                ("select_param", ctypes.c_float)]
 
 
 class Stats(ctypes.Structure):
@@ -103,6 +106,7 @@ def lib() -> ctypes.CDLL:
             "fgim_search": [vp, u64, u32, u64, i32, vp, u32, u32, vp, u64, u64, u32, u32, vp,
                             vp, vp],
             "fgim_quantize": [vp, u64, u32, u64, i32, vp, vp, vp],
+            "fgim_mips_to_l2": [vp, u64, u32, u64, vp, u64, vp, vp],
             "fgim_repair": [vp, vp, u64, u32, vp, vp, vp],
         }.items():
             fn = getattr(L, name)
@@ -143,12 +147,18 @@ def _need_cuda(t: torch.Tensor, name: str, dtype=None) -> None:
 class Merge:
     """Inputs of one merge: base vectors X (float32 [N, d], CUDA) and h input
     graphs as (adj int32/uint32 [n_i, R_in] local ids, entry) in global-id
-    order; sub-index i owns rows [off_i, off_i + n_i)."""
+    order; sub-index i owns rows [off_i, off_i + n_i).  valid (uint8 [N],
+    CUDA, optional): the ID mapping's validity flags (0 = dropped)."""
 
     def __init__(self, X: torch.Tensor, graphs: Sequence[Tuple[torch.Tensor, int]],
                  metric: str = "l2", lowp: Optional[torch.Tensor] = None,
-                 lowp_scale: Optional[torch.Tensor] = None):
+                 lowp_scale: Optional[torch.Tensor] = None, valid: Optional[torch.Tensor] = None):
         _need_cuda(X, "X", torch.float32)
+        if valid is not None:
+            _need_cuda(valid, "valid", torch.uint8)
+            if valid.shape != (X.shape[0],) or not valid.is_contiguous():
+                raise ValueError(f"valid must be a contiguous uint8 tensor of {X.shape[0]} flags")
+        self.valid = valid
         if X.dim() != 2 or X.stride(1) != 1:
             raise ValueError("X must be a row-major 2-D tensor")
         self.X = X
@@ -167,7 +177,8 @@ class Merge:
         self._subs = subs
         self.lowp, self.lowp_scale = lowp, lowp_scale
         self.data = Dataset(X.data_ptr(), X.shape[0], X.shape[1], X.stride(0), METRICS[metric],
-                            ctypes.addressof(subs), len(graphs), _ptr(lowp), _ptr(lowp_scale))
+                            ctypes.addressof(subs), len(graphs), _ptr(lowp), _ptr(lowp_scale),
+                            _ptr(valid))
 
     @property
     def n(self) -> int:
@@ -176,9 +187,11 @@ class Merge:
 
 def params(k: int, L: int, R: int = 0, rounds: int = 0, precision: str = "fp32",
            rerank: int = 0, k_rev: int = 0, autotune: bool = False, lanes_per_dist: int = 0,
-           waves_per_cu: int = 0, visited_slots: int = 0, flags: int = 0) -> Params:
+           waves_per_cu: int = 0, visited_slots: int = 0, flags: int = 0, select_rule: str = "rng",
+           select_param: float = 0.0) -> Params:
     return Params(k, L, R, rounds, PRECISIONS[precision], rerank, k_rev, int(autotune),
-                  lanes_per_dist, waves_per_cu, visited_slots, flags)
+                  lanes_per_dist, waves_per_cu, visited_slots, flags, SELECT_RULES[select_rule],
+                  float(select_param))
 
 
 def cross_query(m: Merge, p: Params, stats: bool = False):
@@ -289,6 +302,17 @@ def quantize(X: torch.Tensor, precision: str):
     _check(lib().fgim_quantize(X.data_ptr(), n, d, X.stride(0), PRECISIONS[precision],
                                codes.data_ptr(), _ptr(scales), _stream()))
     return codes, scales
+
+
+def mips_to_l2(X: torch.Tensor):
+    """MIPS -> L2 transform: (rows float32 [n, d + 4] CUDA, M float32 [1] CUDA)."""
+    _need_cuda(X, "X", torch.float32)
+    n, d = X.shape
+    out = torch.empty((n, d + 4), dtype=torch.float32, device=X.device)
+    M = torch.empty(1, dtype=torch.float32, device=X.device)
+    _check(lib().fgim_mips_to_l2(X.data_ptr(), n, d, X.stride(0), out.data_ptr(), d + 4, M.data_ptr(),
+                                 _stream()))
+    return out, M
 
 
 def min_beam_width(k: int, min_local: int, h: int) -> int:

@@ -285,6 +285,72 @@ __global__ void __launch_bounds__(256) quantize_fp8_kernel(const float* X, uint6
   }
 }
 
+// MIPS -> L2, first pass, one wavefront per row: n(x) = the canonical FP32
+// squared length (chunks of 4 summed with fused multiply-adds from +0,
+// padded to Np chunks and added by the stride tree; lane l owns chunks
+// l, l + P, ...), parked in the row's extra output slot and folded into the
+// maximum (non-negative floats order like their bit patterns).
+__global__ void __launch_bounds__(256) mips_norm_kernel(const float* X, uint64_t n, uint32_t nc, uint32_t Np,
+                                                        uint64_t ld, float* out, uint64_t ld_out, uint32_t dim,
+                                                        uint32_t* max_bits) {
+  const uint32_t wave = threadIdx.x / 64;
+  const uint32_t lane = static_cast<uint32_t>(lane_id());
+  const uint32_t P = Np < 64 ? Np : 64;
+  const uint32_t M = Np / P;  // <= 16 for dim <= 4096
+  uint32_t mx = 0;
+  for (uint64_t row = blockIdx.x * 4ull + wave; row < n; row += gridDim.x * 4ull) {
+    float s[16];
+#pragma unroll
+    for (uint32_t i = 0; i < 16; ++i) {
+      s[i] = 0.0f;
+      const uint32_t c = lane + i * P;
+      if (i < M && lane < P && c < nc) {
+        const float4 x = *reinterpret_cast<const float4*>(X + row * ld + 4ull * c);
+        s[i] = __builtin_fmaf(x.x, x.x, s[i]);
+        s[i] = __builtin_fmaf(x.y, x.y, s[i]);
+        s[i] = __builtin_fmaf(x.z, x.z, s[i]);
+        s[i] = __builtin_fmaf(x.w, x.w, s[i]);
+      }
+    }
+#pragma unroll
+    for (uint32_t st = 8; st >= 1; st /= 2) {
+      if (st < M) {
+#pragma unroll
+        for (uint32_t i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
+      }
+    }
+    float r = s[0];
+#pragma unroll
+    for (uint32_t st = 32; st >= 1; st /= 2)
+      if (st < P) r = r + __shfl_xor(r, static_cast<int>(st), 64);
+    r = r + 0.0f;
+    if (lane == 0) out[row * ld_out + dim] = r;
+    const uint32_t b = __float_as_uint(r);
+    mx = b > mx ? b : mx;
+  }
+  if (lane == 0) atomicMax(max_bits, mx);
+}
+
+// second pass: x' = (x, sqrt(M - n(x)), 0, 0, 0), one float4 per thread step
+__global__ void __launch_bounds__(256) mips_write_kernel(const float* X, uint64_t n, uint32_t dim, uint64_t ld,
+                                                         float* out, uint64_t ld_out, const float* max_norm2) {
+  const uint32_t per_row = dim / 4 + 1;
+  const float Mx = *max_norm2;
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n * per_row;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t row = i / per_row;
+    const uint32_t c = static_cast<uint32_t>(i - row * per_row);
+    float4 v;
+    if (c < dim / 4) {
+      v = *reinterpret_cast<const float4*>(X + row * ld + 4ull * c);
+    } else {
+      const float n2 = out[row * ld_out + dim];
+      v = make_float4(__builtin_sqrtf(Mx - n2), 0.0f, 0.0f, 0.0f);
+    }
+    *reinterpret_cast<float4*>(out + row * ld_out + 4ull * c) = v;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // host helpers
 
@@ -456,6 +522,7 @@ fgim_status cross_query_run(const fgim_dataset* d, const fgim_params* p, uint32_
   a.counter = hdr;
   a.err = hdr + 1;
   a.search_mode = 0;
+  a.valid = d->valid;
   const int fmt = p->precision == FGIM_FP32 ? kF32 : (p->precision == FGIM_BF16 ? kBF16 : kFP8);
   const bool l2 = d->metric == FGIM_L2;
 
@@ -661,6 +728,30 @@ fgim_status fgim_search(const float* base, uint64_t n, uint32_t dim, uint64_t ld
   HIP_TRY(hipMemcpyAsync(&herr, hdr + 1, 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipStreamSynchronize(s));
   if (herr) return fail(FGIM_ERR_GRAPH, "the graph holds an out-of-range id, a self-loop or a duplicate");
+  return FGIM_OK;
+}
+
+fgim_status fgim_mips_to_l2(const float* base, uint64_t n, uint32_t dim, uint64_t ld, float* out, uint64_t ld_out,
+                            float* max_norm2, void* stream) {
+  g_last_error.clear();
+  FGIM_TRY(check_rows(base, n, dim, ld));
+  if (!out || !max_norm2) return fail(FGIM_ERR_INVALID_ARG, "output is NULL");
+  if (ld_out < static_cast<uint64_t>(dim) + 4 || ld_out % 4 || reinterpret_cast<uintptr_t>(out) % 16)
+    return fail(FGIM_ERR_INVALID_ARG, "out rows need ld_out >= dim + 4, a multiple of 4, and 16-byte alignment");
+  const uint64_t lo = reinterpret_cast<uintptr_t>(out), hi = lo + 4 * (n * ld_out);
+  const uint64_t blo = reinterpret_cast<uintptr_t>(base), bhi = blo + 4 * (n * ld);
+  if (lo < bhi && blo < hi) return fail(FGIM_ERR_INVALID_ARG, "out overlaps base");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const uint32_t nc = dim / 4;
+  HIP_TRY(fill_u32(reinterpret_cast<uint32_t*>(max_norm2), 0u, 1, s));
+  const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>((n + 3) / 4, 65536));
+  hipLaunchKernelGGL(mips_norm_kernel, dim3(blocks), dim3(256), 0, s, base, n, nc, ceil_pow2(nc), ld, out, ld_out,
+                     dim, reinterpret_cast<uint32_t*>(max_norm2));
+  HIP_TRY(hipGetLastError());
+  const uint64_t items = n * (dim / 4 + 1);
+  hipLaunchKernelGGL(mips_write_kernel, dim3(static_cast<uint32_t>(std::min<uint64_t>((items + 255) / 256, 65536))),
+                     dim3(256), 0, s, base, n, dim, ld, out, ld_out, max_norm2);
+  HIP_TRY(hipGetLastError());
   return FGIM_OK;
 }
 

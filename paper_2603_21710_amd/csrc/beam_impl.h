@@ -67,6 +67,7 @@ struct BeamArgs {
   int search_mode;         // 1: items are rows of Q searched in subs[0]
   const float* Q;
   uint64_t ldq;
+  const uint8_t* valid;    // phi's validity flag per global id (null: all valid)
 };
 
 struct WaveLds {
@@ -380,6 +381,14 @@ __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
     // ---- stage 1 item: global vertex u ----
     const uint64_t u = static_cast<uint64_t>(item) * a.item_stride;
     const uint64_t orow = a.compact_out ? item : u;
+    if (a.valid && !a.valid[u]) {
+      // phi drops u: no list, no searches
+      for (uint32_t e = lane_id(); e < a.k; e += 64) {
+        a.out_ids[orow * a.k + e] = kNone;
+        a.out_dist[orow * a.k + e] = __builtin_inff();
+      }
+      continue;
+    }
     uint32_t gi = 0;
     for (uint32_t i = 0; i < a.h; ++i)
       if (u >= a.subs[i].off) gi = i;
@@ -387,12 +396,12 @@ __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
     load_query<L2, MMAX>(q, a.X + u * a.ld, a);
     topk.clear();
 
-    // local candidates C+(u): out-neighbours in G_i, scored on FP32 rows
+    // local candidates C+(u): valid out-neighbours in G_i, scored on FP32 rows
     const uint64_t lu = u - si.off;
     for (uint32_t t0 = 0; t0 < si.stride; t0 += 64) {
       const uint32_t t = t0 + lane_id();
       const uint32_t v = t < si.stride ? si.adj[lu * si.stride + t] : kNone;
-      const bool valid = v != kNone;
+      const bool valid = v != kNone && (!a.valid || a.valid[si.off + v]);
       const uint64_t nm = ballot(valid);
       const int m = popc64(nm);
       if (m == 0) continue;
@@ -420,22 +429,29 @@ __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
       }
       nsearch += 1;
       if (FMT == kF32) {
-        // FP32 keys: fold the search's first min(L, k) entries as global ids
+        // FP32 keys: fold the search's results as global ids -- its first
+        // min(L, k) entries, or with validity flags every valid entry (the
+        // running top-k keeps the best k either way)
+        const uint32_t lim = a.valid ? a.L : a.k;
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
           const uint32_t e = r * 64 + lane_id();
           uint64_t ck = pool.key[r];
-          if (e >= a.k || ck == kSentinel) ck = kSentinel;
+          if (e >= lim || ck == kSentinel || (a.valid && !a.valid[sj.off + key_id(ck)])) ck = kSentinel;
           else ck = (ck & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(sj.off + key_id(ck));
           topk.insert_batch(ck, a.k);
         }
       } else {
-        // low-precision keys: re-score the first `rerank` entries on FP32 rows
+        // low-precision keys: re-score the first `rerank` (valid) entries on
+        // FP32 rows
+        uint32_t seen = 0;  // valid entries in the earlier registers
 #pragma unroll
         for (int r = 0; r < NR; ++r) {
-          const uint32_t e = r * 64 + lane_id();
           const uint64_t pk = pool.key[r];
-          const bool take = e < a.rerank && pk != kSentinel;
+          const bool ok = pk != kSentinel && (!a.valid || a.valid[sj.off + key_id(pk)]);
+          const uint64_t vm = ballot(ok);
+          const bool take = ok && seen + static_cast<uint32_t>(mbcnt(vm)) < a.rerank;
+          seen += static_cast<uint32_t>(popc64(vm));
           const uint64_t nm = ballot(take);
           const int m = popc64(nm);
           if (m == 0) continue;

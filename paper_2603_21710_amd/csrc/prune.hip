@@ -41,7 +41,35 @@ struct SelectArgs {
   const float* qerr2;  // squared norm of every row's BF16 rounding residual
   uint32_t dpad;       // dim rounded up to 32
   uint32_t wave_smem;  // LDS bytes per wavefront
+  // selection rule (FGIM_SELECT_*) and its FP32 constants: alpha^2 or 3 tau
+  uint32_t rule;
+  float a2, t3;
 };
+
+// The Euclidean distance behind delta: sqrt(delta) for squared L2 and
+// sqrt(2 delta) for cosine on unit vectors, a negative rounding residue read
+// as 0.  The square root is correctly rounded (HIP's default for sqrtf).
+FGIM_DEV float euclid_of(float d, int metric) {
+  const float s = metric == kCos ? 2.0f * d : d;
+  return __builtin_sqrtf(s > 0.0f ? s : 0.0f);
+}
+
+// Whether a kept w at delta(w, v) = dwv leaves v, at delta(u, v) = duv,
+// selectable: RNG (Algorithm 5) duv < dwv; alpha-RNG duv < alpha^2 dwv;
+// tau-MNG e(duv) < e(dwv) + 3 tau.  Each is non-decreasing in dwv, so a
+// screen that brackets dwv in [lo, hi] decides the pair when the rule gives
+// the same answer at both ends.
+FGIM_DEV bool pair_keeps(const SelectArgs& a, float duv, float dwv) {
+  if (a.rule == FGIM_SELECT_ALPHA) {
+    const float lim = a.a2 * dwv;
+    return duv < lim;
+  }
+  if (a.rule == FGIM_SELECT_TAU) {
+    const float lim = euclid_of(dwv, a.metric) + a.t3;
+    return euclid_of(duv, a.metric) < lim;
+  }
+  return duv < dwv;
+}
 
 template <int MMAX>
 __global__ void __launch_bounds__(256) select_kernel(SelectArgs a) {
@@ -101,7 +129,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelectArgs a) {
           const bool valid = act && q < pp;
           const float* rw = a.stage_rows ? rows + q * d : a.X + static_cast<uint64_t>(vid[q]) * a.ld;
           const float dwv = pair_distance_x<MMAX>(x, rw, a.metric, a.nc, P, M, l, valid);
-          if (valid && !(dup < dwv)) {
+          if (valid && !pair_keeps(a, dup, dwv)) {
             if (q < 64) m0 |= 1ull << q;
             else m1 |= 1ull << (q - 64);
           }
@@ -264,8 +292,9 @@ __global__ void __launch_bounds__(128) select_mfma_kernel(SelectArgs a) {
             float dt, err;
             screen_estimate(acc[t][r], nrm[i], nrm[j], qe[i], qe[j], gam, a.metric, &dt, &err);
             const float dup = vd[i];
-            if (dt + err < dup) atomicOr(reinterpret_cast<unsigned long long*>(&occl[i]), 1ull << j);
-            else if (!(dt - err > dup)) atomicOr(reinterpret_cast<unsigned long long*>(&unc[i]), 1ull << j);
+            // the exact delta(w_j, v_i) lies in [dt - err, dt + err]
+            if (!pair_keeps(a, dup, dt + err)) atomicOr(reinterpret_cast<unsigned long long*>(&occl[i]), 1ull << j);
+            else if (!pair_keeps(a, dup, dt - err)) atomicOr(reinterpret_cast<unsigned long long*>(&unc[i]), 1ull << j);
           }
         }
       }
@@ -301,7 +330,7 @@ __global__ void __launch_bounds__(128) select_mfma_kernel(SelectArgs a) {
       }
       const float dd = pair_distance<MMAX>(a.X + static_cast<uint64_t>(vid[i]) * a.ld,
                                            a.X + static_cast<uint64_t>(vid[j]) * a.ld, a.metric, a.nc, P, M, l, act);
-      if (act && l == 0 && !(vd[i] < dd)) atomicOr(reinterpret_cast<unsigned long long*>(&occl[i]), 1ull << j);
+      if (act && l == 0 && !pair_keeps(a, vd[i], dd)) atomicOr(reinterpret_cast<unsigned long long*>(&occl[i]), 1ull << j);
     }
     wave_lds_sync();
     if (lane == 0) {
@@ -401,6 +430,14 @@ fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32
   if (p->R == 0 || p->R > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "R = %u out of 1..%u", p->R, FGIM_MAX_K);
   const uint64_t N = d->n_total, k = p->k, R = p->R;
   if (N * std::max(k, R) >= 0xFFFFFFFFull) return fail(FGIM_ERR_UNSUPPORTED, "N x max(k, R) exceeds 32-bit offsets");
+  if (p->select_rule > FGIM_SELECT_TAU) return fail(FGIM_ERR_INVALID_ARG, "unknown select_rule %u", p->select_rule);
+  if (p->select_rule != FGIM_SELECT_RNG && d->metric == FGIM_IP)
+    return fail(FGIM_ERR_INVALID_ARG, "alpha-RNG and tau-MNG need a metric distance (L2 or cosine); "
+                                      "transform inner-product data with fgim_mips_to_l2");
+  if (p->select_rule == FGIM_SELECT_ALPHA && !(p->select_param >= 1.0f))
+    return fail(FGIM_ERR_INVALID_ARG, "alpha = %g must be >= 1", static_cast<double>(p->select_param));
+  if (p->select_rule == FGIM_SELECT_TAU && !(p->select_param >= 0.0f && p->select_param < 1e30f))
+    return fail(FGIM_ERR_INVALID_ARG, "tau = %g must be finite and >= 0", static_cast<double>(p->select_param));
   const uint32_t nc = d->dim / 4, Nch = pow2_ceil(nc);
   const uint32_t P = std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, Nch), Nch / 4));
   const uint32_t M = Nch / P;
@@ -432,8 +469,11 @@ fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32
     if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n_total or an entry after a free slot");
   }
 
+  const float alpha = p->select_param;
+  const float a2 = alpha * alpha;                 // rounded once, as the rule states
+  const float t3 = 3.0f * p->select_param;
   SelectArgs sa{d->base, d->ld, nc, d->metric, N, p->k, p->R, ids, dist, T, sel_ids, sel_dist, sel_n, P, M, stage,
-                nullptr, nullptr, 0, 0};
+                nullptr, nullptr, 0, 0, p->select_rule, a2, t3};
   const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));
   const uint32_t dpad = (d->dim + 31) / 32 * 32;
   const bool use_mfma = k <= kSelMfmaMaxK && !(p->flags & FGIM_FLAG_NO_MFMA_SCREEN);
@@ -482,6 +522,58 @@ fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32
   return FGIM_OK;
 }
 
+// smallest retained global id in [lo, hi) (FGIM_NONE when none): atomicMin
+__global__ void first_valid_kernel(const uint8_t* valid, uint64_t lo, uint64_t hi, uint32_t* out) {
+  uint32_t best = kNone;
+  for (uint64_t g = lo + blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; g < hi;
+       g += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    if (valid[g] && static_cast<uint32_t>(g) < best) {
+      best = static_cast<uint32_t>(g);
+      break;
+    }
+  if (best != kNone) atomicMin(out, best);
+}
+
+// The merged graph's entry: the entry of the largest sub-index (lowest
+// index on ties); with validity flags, the smallest retained id of that
+// sub-index when its entry is dropped, passing over sub-indexes with no
+// retained vertex.  `word` is a device word of scratch.
+fgim_status merged_entry(const fgim_dataset* d, uint32_t* word, uint32_t* entry, hipStream_t s) {
+  std::vector<uint32_t> order(d->h);
+  for (uint32_t i = 0; i < d->h; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [d](uint32_t x, uint32_t y) { return d->subs[x].n > d->subs[y].n; });
+  if (!d->valid) {
+    *entry = static_cast<uint32_t>(d->subs[order[0]].row_offset + d->subs[order[0]].entry);
+    return FGIM_OK;
+  }
+  for (uint32_t i : order) {
+    const fgim_subindex& sb = d->subs[i];
+    const uint64_t e = sb.row_offset + sb.entry;
+    uint8_t ve = 0;
+    HIP_TRY(hipMemcpyAsync(&ve, d->valid + e, 1, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (ve) {
+      *entry = static_cast<uint32_t>(e);
+      return FGIM_OK;
+    }
+    HIP_TRY(fill_u32(word, kNone, 1, s));
+    const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>((sb.n + 255) / 256, 4096));
+    hipLaunchKernelGGL(first_valid_kernel, dim3(blocks), dim3(256), 0, s, d->valid, sb.row_offset,
+                       sb.row_offset + sb.n, word);
+    HIP_TRY(hipGetLastError());
+    uint32_t hv = kNone;
+    HIP_TRY(hipMemcpyAsync(&hv, word, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (hv != kNone) {
+      *entry = hv;
+      return FGIM_OK;
+    }
+  }
+  *entry = kNone;
+  return FGIM_OK;
+}
+
 fgim_status cross_query_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist,
                              fgim_stats* stats, hipStream_t s, uint32_t* L_used);
 fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist, uint32_t* T_out,
@@ -513,9 +605,11 @@ fgim_status fgim_merge(const fgim_dataset* data, const fgim_params* params, uint
   uint32_t *ids = nullptr, *T = nullptr;
   float* dist = nullptr;
   if (k == 0 || k > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "k = %u out of 1..%u", params->k, FGIM_MAX_K);
+  uint32_t* word = nullptr;
   FGIM_TRY(scr.get(&ids, N * k));
   FGIM_TRY(scr.get(&dist, N * k));
   FGIM_TRY(scr.get(&T, N));
+  FGIM_TRY(scr.get(&word, 1));
   hipEvent_t ev[4] = {};
   for (auto& e : ev) HIP_TRY(hipEventCreate(&e));
   HIP_TRY(hipEventRecord(ev[0], s));
@@ -526,11 +620,8 @@ fgim_status fgim_merge(const fgim_dataset* data, const fgim_params* params, uint
   HIP_TRY(hipEventRecord(ev[2], s));
   FGIM_TRY(prune_impl(data, params, ids, dist, T, pg_ids, pg_deg, s, true));
   HIP_TRY(hipEventRecord(ev[3], s));
+  FGIM_TRY(merged_entry(data, word, entry, s));
   HIP_TRY(hipEventSynchronize(ev[3]));
-  uint32_t best = 0;
-  for (uint32_t i = 1; i < data->h; ++i)
-    if (data->subs[i].n > data->subs[best].n) best = i;
-  *entry = static_cast<uint32_t>(data->subs[best].row_offset + data->subs[best].entry);
   if (stats) {
     *stats = st1;
     for (int i = 0; i < 3; ++i) {

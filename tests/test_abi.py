@@ -37,7 +37,7 @@ def test_min_beam_width():
 def _dataset(n=100, dim=32, ld=None, subs=None, metric=0, base=0x10000):
     subs = subs if subs is not None else [(0, 60, 8, 0x20000, 0), (60, 40, 8, 0x30000, 3)]
     arr = (fg.Subindex * len(subs))(*[fg.Subindex(*s) for s in subs])
-    d = fg.Dataset(base, n, dim, ld or dim, metric, ctypes.addressof(arr), len(subs), None, None)
+    d = fg.Dataset(base, n, dim, ld or dim, metric, ctypes.addressof(arr), len(subs), None, None, None)
     return d, arr
 
 
@@ -99,3 +99,24 @@ def test_noalloc_limits_rejected_on_host(pk, lowp):
     rc = fg.lib().fgim_cross_query_noalloc(ctypes.byref(d), ctypes.byref(p), 0x40000, 0x50000, None)
     assert rc == 1, fg.lib().fgim_last_error()
     assert b"noalloc" in fg.lib().fgim_last_error()
+
+
+@pytest.mark.parametrize("metric,rule,param", [(1, "alpha", 1.2), (1, "tau", 0.1), (0, "alpha", 0.9),
+                                               (0, "tau", -1.0), (2, "alpha", float("nan"))])
+def test_selection_rule_arguments_rejected_on_host(metric, rule, param):
+    d, keep = _dataset(metric=metric)
+    p = fg.params(k=8, L=16, R=8, select_rule=rule, select_param=param)
+    rc = fg.lib().fgim_prune(ctypes.byref(d), ctypes.byref(p), 0x40000, 0x50000, 0x60000, 0x70000, 0x80000, None)
+    assert rc == 1, fg.lib().fgim_last_error()
+
+
+@pytest.mark.parametrize("args", [
+    (0x10000, 100, 32, 32, 0x20000, 35, 0x30000),   # ld_out < dim + 4
+    (0x10000, 100, 32, 32, 0x20004, 36, 0x30000),   # misaligned output
+    (0x10000, 100, 32, 32, None, 36, 0x30000),      # no output
+    (0x10000, 100, 32, 32, 0x10000, 36, 0x30000),   # output overlaps the input
+    (0x10000, 100, 30, 32, 0x20000, 36, 0x30000),   # dim not a multiple of 4
+])
+def test_mips_to_l2_bad_arguments_rejected_on_host(args):
+    rc = fg.lib().fgim_mips_to_l2(*args, None)
+    assert rc in (1, 5), fg.lib().fgim_last_error()

@@ -527,3 +527,120 @@ def test_mips_to_l2_transform():
     ii, _ = oracle.bruteforce(X, Q, 10, "ip")
     agree = (li == ii).mean()
     assert agree > 0.99, agree
+
+
+def _complete_valid_subs(sizes, valid):
+    """Complete input graphs over all vertices, and the same graphs over only
+    the valid vertices (local ids renumbered in order)."""
+    full, comp, off, coff = [], [], 0, 0
+    for n in sizes:
+        full.append((off, np.array([[j for j in range(n) if j != i] for i in range(n)], np.uint32), 0))
+        keep = [i for i in range(n) if valid[off + i]]
+        m = len(keep)
+        adj = np.full((max(m, 1), max(m - 1, 1)), NONE, np.uint32)
+        for a in range(m):
+            row = [b for b in range(m) if b != a]
+            adj[a, :len(row)] = row
+        comp.append((coff, adj, 0))
+        off += n
+        coff += m
+    return full, comp
+
+
+def test_validity_all_ones_is_no_mask():
+    cfg, X, subs = _cfg_small(sizes=(700, 500, 300))
+    ones = np.ones(X.shape[0], np.uint8)
+    a, ad, _ = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric)
+    b, bd, _ = oracle.cross_query(X, subs, cfg.k, cfg.L, cfg.metric, valid=ones)
+    assert (a == b).all() and (ad == bd).all()
+    m1 = oracle.merge(X, subs, cfg.k, cfg.L, cfg.rounds, cfg.R, cfg.metric)
+    m2 = oracle.merge(X, subs, cfg.k, cfg.L, cfg.rounds, cfg.R, cfg.metric, valid=ones)
+    assert (m1[0] == m2[0]).all() and m1[2] == m2[2]
+
+
+def test_deleted_vertices_equal_removed_vertices_on_complete_graphs():
+    # phi keeps only valid vertices (Section 4.1.3).  With complete input
+    # graphs and L >= every graph, each search returns its whole graph, so
+    # merging with some vertices marked invalid must give, up to the
+    # order-preserving renumbering, the merge of the data without them:
+    # stage 1 is then the exact k-NN among valid vertices, and refinement
+    # and prune see the same lists.
+    rng = np.random.default_rng(17)
+    sizes = (40, 55, 30)
+    X = rng.integers(0, 256, (sum(sizes), 8)).astype(np.float32)
+    valid = (rng.random(sum(sizes)) > 0.3).astype(np.uint8)
+    full, comp = _complete_valid_subs(sizes, valid)
+    keep = np.nonzero(valid)[0]
+    k, L, R = 8, 64, 10
+    ids, dd, _ = oracle.cross_query(X, full, k, L, valid=valid)
+    assert (ids[valid == 0] == NONE).all()
+    gi, gd = oracle.bruteforce(X[keep], X[keep], k, exclude=np.arange(len(keep)))
+    assert (ids[keep] == keep[gi]).all() and (dd[keep].astype(np.float64) == gd).all()
+    pg, deg, _ = oracle.merge(X, full, k, L, 2, R, valid=valid)
+    cpg, cdeg, _ = oracle.merge(X[keep], comp, k, L, 2, R)
+    mapped = np.where(cpg == NONE, NONE, keep[np.minimum(cpg, len(keep) - 1)]).astype(np.uint32)
+    assert (pg[keep] == mapped).all() and (deg[keep] == cdeg).all()
+    assert (pg[valid == 0] == NONE).all() and (deg[valid == 0] == 0).all()
+
+
+def test_deletion_and_overlap_invariants():
+    # A deletion (random 30 % of one sub-index) and an overlap (a second copy
+    # of vertices of another sub-index, marked invalid in one of them): no
+    # invalid vertex is a neighbour anywhere, invalid rows are empty, the
+    # merged entry is valid.
+    cfg, X, subs = _cfg_small(sizes=(900, 600))
+    rng = np.random.default_rng(3)
+    valid = np.ones(X.shape[0], np.uint8)
+    valid[rng.choice(900, 270, replace=False)] = 0
+    valid[900:1000] = 0
+    pg, deg, ent = oracle.merge(X, subs, cfg.k, cfg.L, cfg.rounds, cfg.R, cfg.metric, valid=valid)
+    used = pg[pg != NONE]
+    assert valid[used].all()
+    assert (deg[valid == 0] == 0).all() and (deg[valid == 1] >= 1).all()
+    assert valid[ent] == 1
+
+
+def test_merged_entry_with_invalid_entries():
+    def subs(sizes, entries):
+        out, off = [], 0
+        for n, e in zip(sizes, entries):
+            out.append((off, np.zeros((n, 1), np.uint32), e))
+            off += n
+        return out
+    s = subs((30, 70, 50), (4, 9, 2))
+    valid = np.ones(150, np.uint8)
+    assert oracle.merged_entry(s, valid) == 39
+    valid[39] = 0
+    valid[30:35] = 0
+    assert oracle.merged_entry(s, valid) == 35          # smallest valid id of sub-index 1
+    valid[30:100] = 0
+    assert oracle.merged_entry(s, valid) == 102          # next largest: sub-index 2's entry
+    valid[:] = 0
+    assert oracle.merged_entry(s, valid) == NONE
+
+
+def test_rerank_takes_the_first_valid_results():
+    # low-precision copy and validity together: each search's first `rerank`
+    # valid results, re-scored on the FP32 rows
+    cfg, X, subs = _cfg_small("cfg1ov", sizes=(500, 400, 300))
+    rng = np.random.default_rng(32)
+    Xs = (X + rng.normal(0, 0.5, X.shape)).astype(np.float32)
+    valid = (rng.random(X.shape[0]) > 0.4).astype(np.uint8)
+    nodes = np.nonzero(valid)[0][::19].astype(np.uint64)
+    k, L, rr = 16, 32, 10
+    ids, dd, _ = oracle.cross_query(X, subs, k, L, "l2", nodes=nodes, Xs=Xs, rerank=rr, valid=valid)
+    offs = [s[0] for s in subs]
+    for r, u in enumerate(nodes.astype(np.int64)):
+        g = int(np.searchsorted(offs, u, side="right") - 1)
+        off, adj, _ = subs[g]
+        cand = [(oracle.distance(X[u], X[off + int(v)]), off + int(v)) for v in adj[u - off]
+                if v != NONE and valid[off + int(v)]]
+        for j, (offj, adjj, ej) in enumerate(subs):
+            if j == g:
+                continue
+            res, _, _, _ = oracle.knn_search(X[u], Xs[offj:offj + adjj.shape[0]], adjj, ej, L, "l2")
+            good = [offj + int(v) for v in res if valid[offj + int(v)]][:rr]
+            cand += [(oracle.distance(X[u], X[v]), v) for v in good]
+        cand.sort()
+        got = [(float(dd[r, t]), int(ids[r, t])) for t in range(k) if ids[r, t] != NONE]
+        assert got == cand[:k], u

@@ -27,10 +27,11 @@ def workload(name, sizes=None, device=None):
     return cfg, X, graphs, Q
 
 
-def to_gpu(X, graphs, metric, lowp=None, lowp_scale=None):
+def to_gpu(X, graphs, metric, lowp=None, lowp_scale=None, valid=None):
     import paper_2603_21710_amd as fg
     dev = torch.device("cuda")
     Xd = torch.from_numpy(np.ascontiguousarray(X)).to(dev)
     g = [(torch.from_numpy(np.ascontiguousarray(a).view(np.int32)).to(dev), int(e))
          for _, a, e in graphs]
-    return fg.Merge(Xd, g, metric, lowp, lowp_scale)
+    vd = None if valid is None else torch.from_numpy(np.ascontiguousarray(valid, np.uint8)).to(dev)
+    return fg.Merge(Xd, g, metric, lowp, lowp_scale, vd)
