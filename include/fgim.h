@@ -293,6 +293,46 @@ fgim_status fgim_quantize(const float* base, uint64_t n, uint32_t dim, uint64_t 
                           void* stream);
 
 /*
+ * HNSW-adaptive merging (Section 4.3.3): the upper layers of an HNSW index
+ * over the merged base graph (layer 0).  levels (device, n bytes) holds each
+ * vertex's level, drawn by the caller from HNSW's level distribution
+ * (floor(-ln U / ln M) is the usual draw); layer l = 1..max_level holds the
+ * vertices with level >= l, layer_count[l - 1] of them (host array: the
+ * caller counts them to size its buffers; a mismatch is an error).  Each
+ * layer is built in one batch: the ef nearest other members of every
+ * member (exact, canonical FP32), HNSW's neighbour heuristic up to M (the
+ * RNG rule of Algorithm 5 without the indegree exemption), the first 2M of
+ * those neighbours and the reverse edges by (delta, id), and the heuristic
+ * again up to M.  Outputs (device), layers concatenated in order:
+ * layer_ids (members, ascending), layer_adj (M global ids per member,
+ * FGIM_NONE padded); *top (host) = the smallest id of the highest layer,
+ * the search's entry point (FGIM_NONE when max_level = 0).  M in 1..64,
+ * ef in M..128.  Synchronises.
+ * Errors: FGIM_ERR_INVALID_ARG (arguments, a level above max_level, wrong
+ * layer_count).
+ */
+fgim_status fgim_hnsw_layers(const float* base, uint64_t n, uint32_t dim, uint64_t ld, fgim_metric metric,
+                             const uint8_t* levels, uint32_t max_level, uint32_t M, uint32_t ef,
+                             const uint64_t* layer_count, uint32_t* layer_ids, uint32_t* layer_adj,
+                             uint32_t* top, void* stream);
+
+/*
+ * Search of the hierarchy that fgim_hnsw_layers builds: greedy descent from
+ * top through layers max_level..1 (each step moves to the neighbour closest
+ * to the query by (delta, id) while it beats the current vertex), then
+ * Algorithm 1 with beam width L on the base graph (base_adj, n x stride)
+ * from the vertex reached.  Outputs (device, nq x topk) as fgim_search.
+ * Errors: FGIM_ERR_INVALID_ARG, FGIM_ERR_GRAPH (an id out of range in the
+ * base graph or the layers; checked before the search, which then
+ * synchronises).
+ */
+fgim_status fgim_search_layers(const float* base, uint64_t n, uint32_t dim, uint64_t ld, fgim_metric metric,
+                               const uint32_t* base_adj, uint32_t stride, const uint32_t* layer_ids,
+                               const uint32_t* layer_adj, const uint64_t* layer_count, uint32_t max_level,
+                               uint32_t M, uint32_t top, const float* queries, uint64_t nq, uint64_t ldq,
+                               uint32_t L, uint32_t topk, uint32_t* out_ids, float* out_dist, void* stream);
+
+/*
  * The standard transformation of maximum-inner-product search to L2 that
  * Section 4.3.1 points to, so that the distance-based selection rules apply
  * to inner-product data: with n(x) = |x|^2 (canonical FP32 sum) and

@@ -74,6 +74,12 @@ def lib() -> ctypes.CDLL:
         L.oracle_prune.restype = i32
         L.oracle_prune.argtypes = [vp, u64, u32, i32, u64, u32, vp, vp, vp, u32, vp, vp, vp,
                                    i32, i32, ctypes.c_float]
+        L.oracle_hnsw_layers.restype = i32
+        L.oracle_hnsw_layers.argtypes = [vp, u64, u32, i32, u64, vp, u32, u32, u32, vp, vp, vp, vp,
+                                         i32]
+        L.oracle_hnsw_search.restype = i32
+        L.oracle_hnsw_search.argtypes = [vp, vp, u64, u32, i32, u64, vp, u32, vp, vp, vp, u32, u32,
+                                         u32, u32, vp, vp]
         L.oracle_mips_to_l2.restype = i32
         L.oracle_mips_to_l2.argtypes = [vp, u64, u64, u32, vp, u64, vp]
         L.oracle_prune_rows.restype = i32
@@ -273,6 +279,44 @@ def prune_rows(X, ids, dist, T, R: int, rows, metric: str = "l2", threads: Optio
     if rc:
         raise ValueError("oracle_prune_rows failed")
     return oi, od, deg
+
+
+def hnsw_layers(X, levels, M: int, ef: int, metric: str = "l2", threads: Optional[int] = None):
+    """Upper layers of HNSW-adaptive merging (Section 4.3.3) for levels
+    (uint8 [N]): (layer_ids, layer_adj [rows, M], counts [max_level], top)."""
+    X = _f32(X)
+    lv = np.ascontiguousarray(levels, dtype=np.uint8)
+    N = X.shape[0]
+    max_level = int(lv.max()) if N else 0
+    rows = int(sum(int((lv >= l).sum()) for l in range(1, max_level + 1)))
+    ids = np.empty(max(rows, 1), np.uint32)
+    adj = np.empty((max(rows, 1), M), np.uint32)
+    cnt = np.zeros(max(max_level, 1), np.uint64)
+    top = ctypes.c_uint32()
+    rc = lib().oracle_hnsw_layers(_p(X), X.shape[1], X.shape[1], METRICS[metric], N, _p(lv),
+                                  max_level, M, ef, _p(ids), _p(adj), _p(cnt), ctypes.byref(top),
+                                  threads or default_threads())
+    if rc:
+        raise ValueError("oracle_hnsw_layers failed")
+    return ids[:rows], adj[:rows], cnt[:max_level], top.value
+
+
+def hnsw_search(q, X, base_adj, layers, M: int, L: int, metric: str = "l2"):
+    """Search over the hierarchy: (ids, dists) of the final pool."""
+    ids, adj, cnt, top = layers
+    q, X = _f32(q), _f32(X)
+    base_adj = np.ascontiguousarray(base_adj, dtype=np.uint32)
+    ids = np.ascontiguousarray(ids, dtype=np.uint32)
+    adj = np.ascontiguousarray(adj, dtype=np.uint32)
+    cnt = np.ascontiguousarray(cnt, dtype=np.uint64)
+    oi = np.empty(L, np.uint32)
+    od = np.empty(L, np.float32)
+    n = lib().oracle_hnsw_search(_p(q), _p(X), X.shape[1], X.shape[1], METRICS[metric], X.shape[0],
+                                 _p(base_adj), base_adj.shape[1], _p(ids), _p(adj), _p(cnt),
+                                 len(cnt), M, top, L, _p(oi), _p(od))
+    if n < 0:
+        raise ValueError("oracle_hnsw_search failed")
+    return oi[:n].copy(), od[:n].copy()
 
 
 def mips_to_l2(X):

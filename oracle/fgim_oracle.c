@@ -906,7 +906,7 @@ static uint32_t select_one(const prune_ctx* c, uint64_t u, uint32_t* out_ids, fl
         uint32_t v = c->ids[u * c->k + s];
         if (v == ORC_NONE) break;
         float duv = c->dist[u * c->k + s];
-        int keep = c->T[v] == 1;
+        int keep = c->T && c->T[v] == 1;   /* no indegree recorder: no exemption */
         if (!keep) {
             keep = 1;
             for (uint32_t q = 0; q < ns; ++q) {
@@ -1172,6 +1172,183 @@ int oracle_merge(const float* X, uint64_t ld, uint32_t dim, int metric,
 out:
     free(ids); free(dist); free(flags); free(T);
     return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* HNSW-adaptive merging (Section 4.3.3): upper layers over the merged  */
+/* base graph.                                                          */
+/* ------------------------------------------------------------------ */
+
+/*
+ * level[v] (drawn by the caller from HNSW's level distribution) puts v in
+ * layers 1..level[v]; layer 0 is the merged graph itself.  Each layer
+ * l = 1..max_level with members V_l (ascending ids) is built in four steps:
+ *   cand(u)  the ef nearest other members of V_l by (delta, id) (exact)
+ *   sel(u)   HNSW's neighbour heuristic (the RNG rule of Algorithm 5, with
+ *            no indegree exemption) over cand(u), up to M
+ *   uni(u)   the first 2M of the (delta, id)-sorted, id-unique union of
+ *            sel(u) and {v in V_l : u in sel(v)} (bidirectional edges)
+ *   adj(u)   the heuristic again over uni(u), up to M (HNSW's pruning of the
+ *            neighbours that gained an edge)
+ * Outputs, layers concatenated in order l = 1..max_level: layer_ids (the
+ * members), layer_adj (M per member, global ids, ORC_NONE padded),
+ * layer_count[l - 1] = |V_l|.  *top = the smallest id of the highest
+ * non-empty layer (ORC_NONE when every layer is empty).
+ */
+int oracle_hnsw_layers(const float* X, uint64_t ld, uint32_t dim, int metric, uint64_t N,
+                       const uint8_t* level, uint32_t max_level, uint32_t M, uint32_t ef,
+                       uint32_t* layer_ids, uint32_t* layer_adj, uint64_t* layer_count,
+                       uint32_t* top, int threads)
+{
+    if (!X || !level || !layer_ids || !layer_adj || !layer_count || !top || M == 0 || ef == 0)
+        return -1;
+    uint32_t* cid = (uint32_t*)malloc(sizeof(uint32_t) * (N * ef + 1));
+    float* cdd = (float*)malloc(sizeof(float) * (N * ef + 1));
+    uint32_t* uid = (uint32_t*)malloc(sizeof(uint32_t) * (N * 2 * M + 1));
+    float* udd = (float*)malloc(sizeof(float) * (N * 2 * M + 1));
+    uint32_t* deg = (uint32_t*)malloc(sizeof(uint32_t) * (N + 1));
+    uint32_t* adj = (uint32_t*)malloc(sizeof(uint32_t) * (N * M + 1));
+    uint32_t* mem = (uint32_t*)malloc(sizeof(uint32_t) * (N + 1));
+    ent_t* buf = (ent_t*)malloc(sizeof(ent_t) * (N + 1));
+    int rc = -1;
+    if (!cid || !cdd || !uid || !udd || !deg || !adj || !mem || !buf) goto out;
+    *top = ORC_NONE;
+    uint64_t outrow = 0;
+    for (uint32_t l = 1; l <= max_level; ++l) {
+        uint64_t n = 0;
+        for (uint64_t v = 0; v < N; ++v)
+            if (level[v] >= l) mem[n++] = (uint32_t)v;
+        layer_count[l - 1] = n;
+        if (n) *top = mem[0];
+        /* candidates: lists indexed by global id, empty for non-members */
+        for (uint64_t i = 0; i < N * ef; ++i) { cid[i] = ORC_NONE; cdd[i] = INFINITY; }
+        for (uint64_t a = 0; a < n; ++a) {
+            uint32_t u = mem[a];
+            uint64_t m = 0;
+            for (uint64_t b = 0; b < n; ++b) {
+                if (b == a) continue;
+                buf[m++] = (ent_t){oracle_distance(X + (uint64_t)u * ld, X + (uint64_t)mem[b] * ld,
+                                                   dim, metric), mem[b], 0};
+            }
+            qsort(buf, m, sizeof(ent_t), ent_cmp);
+            for (uint64_t t = 0; t < m && t < ef; ++t) {
+                cid[(uint64_t)u * ef + t] = buf[t].id;
+                cdd[(uint64_t)u * ef + t] = buf[t].d;
+            }
+        }
+        /* sel(u): the heuristic over cand(u), up to M */
+        prune_ctx c1 = {X, ld, dim, metric, ef, M, cid, cdd, NULL, NULL, NULL, NULL,
+                        ORC_SEL_RNG, 0.0f};
+        uint32_t* sid = adj;            /* N x M selections (members' rows) */
+        float* sdd = (float*)malloc(sizeof(float) * (N * M + 1));
+        uint32_t* sn = deg;
+        uint64_t* roff = (uint64_t*)calloc(N + 1, sizeof(uint64_t));
+        if (!sdd || !roff) { free(sdd); free(roff); goto out; }
+        for (uint64_t v = 0; v < N; ++v) sn[v] = 0;
+        for (uint64_t a2 = 0; a2 < n; ++a2) {
+            uint32_t u = mem[a2];
+            sn[u] = select_one(&c1, u, sid + (uint64_t)u * M, sdd + (uint64_t)u * M);
+        }
+        /* uni(u): sel(u) and the reverse of every selection that picks u */
+        for (uint64_t a2 = 0; a2 < n; ++a2) {
+            uint32_t u = mem[a2];
+            for (uint32_t t = 0; t < sn[u]; ++t) roff[sid[(uint64_t)u * M + t] + 1] += 1;
+        }
+        for (uint64_t v = 0; v < N; ++v) roff[v + 1] += roff[v];
+        ent_t* rev = (ent_t*)malloc(sizeof(ent_t) * (roff[N] + 1));
+        uint64_t* cur = (uint64_t*)malloc(sizeof(uint64_t) * (N + 1));
+        ent_t* U = (ent_t*)malloc(sizeof(ent_t) * (M + roff[N] + 1));
+        if (!rev || !cur || !U) { free(sdd); free(roff); free(rev); free(cur); free(U); goto out; }
+        memcpy(cur, roff, sizeof(uint64_t) * (N + 1));
+        for (uint64_t a2 = 0; a2 < n; ++a2) {
+            uint32_t u = mem[a2];
+            for (uint32_t t = 0; t < sn[u]; ++t) {
+                uint32_t v = sid[(uint64_t)u * M + t];
+                rev[cur[v]++] = (ent_t){sdd[(uint64_t)u * M + t], u, 0};
+            }
+        }
+        for (uint64_t i = 0; i < N * 2 * M; ++i) { uid[i] = ORC_NONE; udd[i] = INFINITY; }
+        for (uint64_t a2 = 0; a2 < n; ++a2) {
+            uint32_t u = mem[a2];
+            size_t m = 0;
+            for (uint32_t t = 0; t < sn[u]; ++t)
+                U[m++] = (ent_t){sdd[(uint64_t)u * M + t], sid[(uint64_t)u * M + t], 0};
+            for (uint64_t t = roff[u]; t < roff[u + 1]; ++t) U[m++] = rev[t];
+            qsort(U, m, sizeof(ent_t), ent_cmp);
+            uint32_t o = 0;
+            for (size_t t = 0; t < m && o < 2 * M; ++t) {
+                if (o && uid[(uint64_t)u * 2 * M + o - 1] == U[t].id) continue;
+                uid[(uint64_t)u * 2 * M + o] = U[t].id;
+                udd[(uint64_t)u * 2 * M + o] = U[t].d;
+                ++o;
+            }
+        }
+        free(rev); free(cur); free(U); free(roff);
+        /* adj(u): the heuristic again over uni(u), up to M */
+        prune_ctx c2 = {X, ld, dim, metric, 2 * M, M, uid, udd, NULL, NULL, NULL, NULL,
+                        ORC_SEL_RNG, 0.0f};
+        for (uint64_t a2 = 0; a2 < n; ++a2) {
+            uint32_t u = mem[a2];
+            uint32_t* row = layer_adj + (outrow + a2) * M;
+            uint32_t ns = select_one(&c2, u, row, sdd);
+            for (uint32_t t = ns; t < M; ++t) row[t] = ORC_NONE;
+            layer_ids[outrow + a2] = u;
+        }
+        free(sdd);
+        outrow += n;
+    }
+    rc = 0;
+out:
+    free(cid); free(cdd); free(uid); free(udd); free(deg); free(adj); free(mem); free(buf);
+    return rc;
+}
+
+/*
+ * Search over the hierarchy: from `top`, greedy descent through layers
+ * max_level..1 (move to the closest neighbour in the layer while it is
+ * closer than the current vertex, ties by id), then Algorithm 1 on the base
+ * graph from the vertex reached.  Rows of layer l are found by binary search
+ * of the member ids.  Returns the pool size written to out_ids / out_dist.
+ */
+int oracle_hnsw_search(const float* q, const float* X, uint64_t ld, uint32_t dim, int metric,
+                       uint64_t N, const uint32_t* base_adj, uint32_t stride,
+                       const uint32_t* layer_ids, const uint32_t* layer_adj,
+                       const uint64_t* layer_count, uint32_t max_level, uint32_t M,
+                       uint32_t top, uint32_t L, uint32_t* out_ids, float* out_dist)
+{
+    if (top == ORC_NONE || top >= N || L == 0) return -1;
+    uint64_t start[256];
+    uint64_t acc = 0;
+    if (max_level > 255) return -1;
+    for (uint32_t l = 1; l <= max_level; ++l) { start[l] = acc; acc += layer_count[l - 1]; }
+    uint32_t cur = top;
+    ent_t best = {oracle_distance(q, X + (uint64_t)cur * ld, dim, metric), cur, 0};
+    for (uint32_t l = max_level; l >= 1; --l) {
+        uint64_t n = layer_count[l - 1];
+        if (n == 0) continue;
+        for (;;) {
+            uint64_t lo = 0, hi = n;
+            const uint32_t* ids = layer_ids + start[l];
+            while (lo < hi) {
+                uint64_t mid = (lo + hi) / 2;
+                if (ids[mid] < best.id) lo = mid + 1; else hi = mid;
+            }
+            if (lo >= n || ids[lo] != best.id) break;   /* not a member: stay */
+            const uint32_t* row = layer_adj + (start[l] + lo) * M;
+            ent_t nb = best;
+            for (uint32_t t = 0; t < M; ++t) {
+                if (row[t] == ORC_NONE) continue;
+                ent_t e = {oracle_distance(q, X + (uint64_t)row[t] * ld, dim, metric), row[t], 0};
+                if (ent_less(&e, &nb)) nb = e;
+            }
+            if (nb.id == best.id) break;
+            best = nb;
+        }
+    }
+    uint64_t ndc = 0, nexp = 0;
+    int n = oracle_knn_search(q, X, ld, dim, metric, base_adj, (uint32_t)N, stride, best.id, L,
+                              out_ids, out_dist, &ndc, &nexp);
+    return n;
 }
 
 /* ------------------------------------------------------------------ */

@@ -33,7 +33,7 @@ STATUS = {0: "FGIM_OK", 1: "FGIM_ERR_INVALID_ARG", 2: "FGIM_ERR_GRAPH",
           3: "FGIM_ERR_OUT_OF_MEMORY", 4: "FGIM_ERR_DEVICE", 5: "FGIM_ERR_UNSUPPORTED"}
 
 EXPORTS = ["fgim_cross_query", "fgim_cross_query_noalloc", "fgim_refine", "fgim_repair", "fgim_prune",
-           "fgim_merge", "fgim_search", "fgim_mips_to_l2",
+           "fgim_merge", "fgim_search", "fgim_mips_to_l2", "fgim_hnsw_layers", "fgim_search_layers",
            "fgim_quantize", "fgim_min_beam_width", "fgim_release_scratch", "fgim_status_string",
            "fgim_last_error"]
 
@@ -107,6 +107,9 @@ def lib() -> ctypes.CDLL:
                             vp, vp],
             "fgim_quantize": [vp, u64, u32, u64, i32, vp, vp, vp],
             "fgim_mips_to_l2": [vp, u64, u32, u64, vp, u64, vp, vp],
+            "fgim_hnsw_layers": [vp, u64, u32, u64, i32, vp, u32, u32, u32, vp, vp, vp, vp, vp],
+            "fgim_search_layers": [vp, u64, u32, u64, i32, vp, u32, vp, vp, vp, u32, u32, u32, vp, u64,
+                                   u64, u32, u32, vp, vp, vp],
             "fgim_repair": [vp, vp, u64, u32, vp, vp, vp],
         }.items():
             fn = getattr(L, name)
@@ -313,6 +316,44 @@ def mips_to_l2(X: torch.Tensor):
     _check(lib().fgim_mips_to_l2(X.data_ptr(), n, d, X.stride(0), out.data_ptr(), d + 4, M.data_ptr(),
                                  _stream()))
     return out, M
+
+
+def hnsw_layers(X: torch.Tensor, levels: torch.Tensor, M: int, ef: int, metric: str = "l2"):
+    """Upper layers over the base rows X for levels (uint8 [N], CUDA):
+    (layer_ids int32 [rows], layer_adj int32 [rows, M], counts (list), top)."""
+    _need_cuda(X, "X", torch.float32)
+    _need_cuda(levels, "levels", torch.uint8)
+    lv = levels.contiguous()
+    max_level = int(lv.max().item()) if lv.numel() else 0
+    counts = [int((lv >= l).sum().item()) for l in range(1, max_level + 1)]
+    rows = sum(counts)
+    ids = torch.empty(max(rows, 1), dtype=torch.int32, device=X.device)
+    adj = torch.empty((max(rows, 1), M), dtype=torch.int32, device=X.device)
+    cnt = (ctypes.c_uint64 * max(max_level, 1))(*counts)
+    top = ctypes.c_uint32()
+    _check(lib().fgim_hnsw_layers(X.data_ptr(), X.shape[0], X.shape[1], X.stride(0), METRICS[metric],
+                                  lv.data_ptr(), max_level, M, ef, cnt, ids.data_ptr(), adj.data_ptr(),
+                                  ctypes.byref(top), _stream()))
+    return ids[:rows], adj[:rows], counts, top.value
+
+
+def search_layers(X: torch.Tensor, base_adj: torch.Tensor, layers, M: int, Q: torch.Tensor, L: int,
+                  topk: int, metric: str = "l2"):
+    """Hierarchical search (descent through the layers, then Algorithm 1 on
+    the base graph): (ids [nq, topk], dist)."""
+    _need_cuda(X, "X", torch.float32)
+    _need_cuda(Q, "Q", torch.float32)
+    _need_cuda(base_adj, "base_adj", torch.int32)
+    lids, ladj, counts, top = layers
+    base_adj = base_adj.contiguous()
+    cnt = (ctypes.c_uint64 * max(len(counts), 1))(*counts)
+    ids = torch.empty((Q.shape[0], topk), dtype=torch.int32, device=X.device)
+    dist = torch.empty((Q.shape[0], topk), dtype=torch.float32, device=X.device)
+    _check(lib().fgim_search_layers(X.data_ptr(), X.shape[0], X.shape[1], X.stride(0), METRICS[metric],
+                                    base_adj.data_ptr(), base_adj.shape[1], lids.data_ptr(),
+                                    ladj.data_ptr(), cnt, len(counts), M, top, Q.data_ptr(), Q.shape[0],
+                                    Q.stride(0), L, topk, ids.data_ptr(), dist.data_ptr(), _stream()))
+    return ids, dist
 
 
 def min_beam_width(k: int, min_local: int, h: int) -> int:

@@ -68,6 +68,7 @@ struct BeamArgs {
   const float* Q;
   uint64_t ldq;
   const uint8_t* valid;    // phi's validity flag per global id (null: all valid)
+  const uint32_t* entries; // search items: per-query entry point (null: subs[0].entry)
 };
 
 struct WaveLds {
@@ -175,18 +176,21 @@ struct Pool {
 // Score candidates cand[0..m) (row ids relative to `goff`) against the query
 // held in q; key = (delta, key_off + id).  Group g of P lanes scores
 // candidates g, g+G, ... (G = 64/P).  The rows of U consecutive group
-// batches are loaded before any is reduced, so their memory latencies
-// overlap.  All lanes must call this.
-template <bool L2, int MMAX, class Row>
+// batches (at most UCAP) are loaded before any is reduced, so their memory
+// latencies overlap.  All lanes must call this.
+template <bool L2, int MMAX, int UCAP = 3, class Row>
 FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, const float4 (&q)[MMAX],
                           const BeamArgs& a, const WaveLds& lds, int m) {
-  // group batches in flight: two for FP32 rows, else as many as about 32
+  // group batches in flight: one for FP32 rows (95 VGPRs, 20 resident waves
+  // per CU: 9 % faster than two batches at 16 waves on 8 uneven sub-indexes
+  // of 2 M rows, d = 96, within 1.3 % elsewhere), else as many as about 32
   // registers of raw (BF16 / FP8) row data per lane hold, at most three:
   // four take the kernel past 128 VGPRs, to 12 resident waves per CU, and
   // measured 12-25 % slower on d = 96, 128 and 768 (eight slower still)
   constexpr int kRawRegs = static_cast<int>(sizeof(typename Row::Raw) / 4);
   constexpr int kLowP = 32 / (MMAX * kRawRegs) < 3 ? 32 / (MMAX * kRawRegs) : 3;
-  constexpr int U = MMAX > 4 ? 1 : (kRawRegs == 4 ? 2 : kLowP);
+  constexpr int U0 = MMAX > 4 ? 1 : (kRawRegs == 4 ? 1 : kLowP);
+  constexpr int U = U0 < UCAP ? U0 : UCAP;
   const int P = static_cast<int>(a.P);
   const int M = static_cast<int>(a.M);
   const int G = 64 / P;
@@ -269,7 +273,7 @@ FGIM_DEV void beam_search(Pool<NR>& pool, const Row& rows, uint64_t goff, const 
     lds.cand[0] = ep;
   }
   __syncthreads();
-  score_batch<L2, MMAX>(rows, goff, 0u, q, a, lds, 1);
+  score_batch<L2, MMAX, 1>(rows, goff, 0u, q, a, lds, 1);
   __syncthreads();
   pool.clear();
   {
@@ -356,14 +360,15 @@ __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
     if (a.search_mode) {
       const SubDev g = a.subs[0];
       load_query<L2, MMAX>(q, a.Q + static_cast<uint64_t>(item) * a.ldq, a);
+      const uint32_t ep = a.entries ? a.entries[item] : g.entry;
       if (FMT == kF32) {
-        beam_search<L2, MMAX, NR>(pool, f32rows, g.off, g.adj, g.stride, g.entry, q, a, lds, ndc, nexp);
+        beam_search<L2, MMAX, NR>(pool, f32rows, g.off, g.adj, g.stride, ep, q, a, lds, ndc, nexp);
       } else if (FMT == kBF16) {
         RowBF16 rb{a.xb, a.dim};
-        beam_search<L2, MMAX, NR>(pool, rb, g.off, g.adj, g.stride, g.entry, q, a, lds, ndc, nexp);
+        beam_search<L2, MMAX, NR>(pool, rb, g.off, g.adj, g.stride, ep, q, a, lds, ndc, nexp);
       } else {
         RowFP8 r8{a.x8, a.x8s, a.dim};
-        beam_search<L2, MMAX, NR>(pool, r8, g.off, g.adj, g.stride, g.entry, q, a, lds, ndc, nexp);
+        beam_search<L2, MMAX, NR>(pool, r8, g.off, g.adj, g.stride, ep, q, a, lds, ndc, nexp);
       }
       nsearch += 1;
 #pragma unroll
@@ -397,6 +402,9 @@ __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
     topk.clear();
 
     // local candidates C+(u): valid out-neighbours in G_i, scored on FP32 rows
+    // (this and the re-ranking score one batch at a time: a second batch in
+    // flight here took the BF16 / FP8 kernels past 128 VGPRs, to 12
+    // resident waves per CU, 12 % slower on 2 x 500k rows, d = 768)
     const uint64_t lu = u - si.off;
     for (uint32_t t0 = 0; t0 < si.stride; t0 += 64) {
       const uint32_t t = t0 + lane_id();
@@ -407,7 +415,7 @@ __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
       if (m == 0) continue;
       if (valid) lds.cand[mbcnt(nm)] = v;
       __syncthreads();
-      score_batch<L2, MMAX>(f32rows, si.off, static_cast<uint32_t>(si.off), q, a, lds, m);
+      score_batch<L2, MMAX, 1>(f32rows, si.off, static_cast<uint32_t>(si.off), q, a, lds, m);
       __syncthreads();
       const uint64_t ck = lane_id() < m ? lds.ckey[lane_id()] : kSentinel;
       topk.insert_batch(ck, a.k);
@@ -457,7 +465,7 @@ __global__ void __launch_bounds__(64) beam_kernel(BeamArgs a) {
           if (m == 0) continue;
           if (take) lds.cand[mbcnt(nm)] = key_id(pk);
           __syncthreads();
-          score_batch<L2, MMAX>(f32rows, sj.off, static_cast<uint32_t>(sj.off), q, a, lds, m);
+          score_batch<L2, MMAX, 1>(f32rows, sj.off, static_cast<uint32_t>(sj.off), q, a, lds, m);
           __syncthreads();
           const uint64_t ck = lane_id() < m ? lds.ckey[lane_id()] : kSentinel;
           topk.insert_batch(ck, a.k);

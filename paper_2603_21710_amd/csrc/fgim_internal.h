@@ -51,6 +51,14 @@ fgim_status cross_query_check(const fgim_dataset* d, const fgim_params* p, const
 fgim_status cross_query_run(const fgim_dataset* d, const fgim_params* p, uint32_t* ids, float* dist,
                             fgim_stats* stats, hipStream_t s, uint32_t* L_used, const CrossBufs& b);
 
+// prune.hip: neighbour selection over `rows` lists of width k (ids index the
+// n_x rows of X; T nullable = no indegree exemption), up to R per list
+struct Scratch;
+fgim_status select_lists(const float* X, uint64_t n_x, uint64_t ld, uint32_t dim, int metric, uint64_t rows,
+                         uint32_t k, uint32_t R, const uint32_t* ids, const float* dist, const uint32_t* T,
+                         uint32_t rule, float param, uint32_t flags, const float* nrm2, const float* qerr2,
+                         uint32_t* sel_ids, float* sel_dist, uint32_t* sel_n, Scratch& scr, hipStream_t s);
+
 // tune.hip: with a.counter pointing at a zeroed-by-the-callee queue head, a
 // graph already validated, and lo the minimum-querying bound on L, choose
 // the beam width (*L, lowered only in the batched or low-precision forms) and

@@ -93,7 +93,7 @@ __global__ void __launch_bounds__(256) select_kernel(SelectArgs a) {
       const uint32_t v = a.ids[u * a.k + t];
       vid[t] = v;
       vd[t] = a.dist[u * a.k + t];
-      tv[t] = v == kNone ? 0u : a.T[v];
+      tv[t] = v == kNone || !a.T ? 0u : a.T[v];
       occl[2 * t] = 0;
       occl[2 * t + 1] = 0;
       if (v != kNone) atomicMax(&ctr[1], t + 1);
@@ -221,7 +221,7 @@ __global__ void __launch_bounds__(128) select_mfma_kernel(SelectArgs a) {
     const bool valid = static_cast<uint32_t>(lane) < cnt;
     vid[lane] = valid ? v : kNone;
     vd[lane] = valid ? a.dist[u * a.k + lane] : 0.0f;
-    tv[lane] = valid ? a.T[v] : 0u;
+    tv[lane] = valid && a.T ? a.T[v] : 0u;
     nrm[lane] = valid ? a.nrm2[v] : 0.0f;
     qe[lane] = valid ? sqrtf(a.qerr2[v]) * (1.0f + gam) * 1.0001f : 0.0f;
     occl[lane] = 0;
@@ -418,70 +418,42 @@ static uint32_t pow2_ceil(uint32_t x) {
   return p;
 }
 
-// Stage 3.  Lists from a caller are checked first (ids in range, no entry
-// after a free slot); the merge passes its own refined lists as trusted
-// and skips the check and its host wait.
-fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32_t* ids, const float* dist,
-                       const uint32_t* T, uint32_t* pg_ids, uint32_t* pg_deg, hipStream_t s, bool trusted) {
-  FGIM_TRY(check_dataset(d, false));
-  if (!p) return fail(FGIM_ERR_INVALID_ARG, "params is NULL");
-  if (!ids || !dist || !T || !pg_ids || !pg_deg) return fail(FGIM_ERR_INVALID_ARG, "NULL buffer");
-  if (p->k == 0 || p->k > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "k = %u out of 1..%u", p->k, FGIM_MAX_K);
-  if (p->R == 0 || p->R > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "R = %u out of 1..%u", p->R, FGIM_MAX_K);
-  const uint64_t N = d->n_total, k = p->k, R = p->R;
-  if (N * std::max(k, R) >= 0xFFFFFFFFull) return fail(FGIM_ERR_UNSUPPORTED, "N x max(k, R) exceeds 32-bit offsets");
-  if (p->select_rule > FGIM_SELECT_TAU) return fail(FGIM_ERR_INVALID_ARG, "unknown select_rule %u", p->select_rule);
-  if (p->select_rule != FGIM_SELECT_RNG && d->metric == FGIM_IP)
-    return fail(FGIM_ERR_INVALID_ARG, "alpha-RNG and tau-MNG need a metric distance (L2 or cosine); "
-                                      "transform inner-product data with fgim_mips_to_l2");
-  if (p->select_rule == FGIM_SELECT_ALPHA && !(p->select_param >= 1.0f))
-    return fail(FGIM_ERR_INVALID_ARG, "alpha = %g must be >= 1", static_cast<double>(p->select_param));
-  if (p->select_rule == FGIM_SELECT_TAU && !(p->select_param >= 0.0f && p->select_param < 1e30f))
-    return fail(FGIM_ERR_INVALID_ARG, "tau = %g must be finite and >= 0", static_cast<double>(p->select_param));
-  const uint32_t nc = d->dim / 4, Nch = pow2_ceil(nc);
+// Neighbour selection (Algorithm 5's first step, or a swap-in rule) over
+// `rows` lists of width k (ids index the n_x rows of X; T nullable: no
+// indegree exemption), up to R per list, into sel_ids / sel_dist (rows x R)
+// and sel_n.  nrm2 / qerr2 (the MFMA screen's row norms over all n_x rows)
+// are computed into scratch when null and the screen runs.
+fgim_status select_lists(const float* X, uint64_t n_x, uint64_t ld, uint32_t dim, int metric, uint64_t rows,
+                         uint32_t k, uint32_t R, const uint32_t* ids, const float* dist, const uint32_t* T,
+                         uint32_t rule, float param, uint32_t flags, const float* nrm2_in, const float* qerr2_in,
+                         uint32_t* sel_ids, float* sel_dist, uint32_t* sel_n, Scratch& scr, hipStream_t s) {
+  if (rows == 0) return FGIM_OK;
+  const uint64_t N = rows;
+  const uint32_t nc = dim / 4, Nch = pow2_ceil(nc);
   const uint32_t P = std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, Nch), Nch / 4));
   const uint32_t M = Nch / P;
   const size_t head = ((k * (16 + 12) + 15) / 16) * 16 + 16;
-  const size_t rows = k * (d->dim + 4) * 4;
-  const bool stage = head + rows <= 96 * 1024;
-  const size_t smem = head + (stage ? rows : 0);
-
-  Scratch scr(s);
-  uint32_t *sel_ids = nullptr, *sel_n = nullptr, *cnt = nullptr, *off = nullptr, *cur = nullptr, *tmp = nullptr,
-           *err = nullptr;
-  float* sel_dist = nullptr;
-  uint64_t* rev = nullptr;
-  FGIM_TRY(scr.get(&sel_ids, N * R));
-  FGIM_TRY(scr.get(&sel_dist, N * R));
-  FGIM_TRY(scr.get(&sel_n, N));
-  FGIM_TRY(scr.get(&cnt, N + 1));
-  FGIM_TRY(scr.get(&off, N + 1));
-  FGIM_TRY(scr.get(&cur, N + 1));
-  FGIM_TRY(scr.get(&rev, N * R));
-  FGIM_TRY(scr.get(&tmp, scan_tmp_words(N) + 16));
-  FGIM_TRY(scr.get(&err, 4));
-  if (!trusted) {
-    HIP_TRY(fill_u32(err, 0u, 1, s));
-    hipLaunchKernelGGL(validate_lists_kernel, dim3(grid_n(N * k)), dim3(256), 0, s, ids, N * k, N, p->k, err);
-    uint32_t herr = 0;
-    HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipStreamSynchronize(s));
-    if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n_total or an entry after a free slot");
-  }
-
-  const float alpha = p->select_param;
-  const float a2 = alpha * alpha;                 // rounded once, as the rule states
-  const float t3 = 3.0f * p->select_param;
-  SelectArgs sa{d->base, d->ld, nc, d->metric, N, p->k, p->R, ids, dist, T, sel_ids, sel_dist, sel_n, P, M, stage,
-                nullptr, nullptr, 0, 0, p->select_rule, a2, t3};
+  const size_t rows_b = static_cast<size_t>(k) * (dim + 4) * 4;
+  const bool stage = head + rows_b <= 96 * 1024;
+  const size_t smem = head + (stage ? rows_b : 0);
+  const float a2 = param * param;   // rounded once, as the rule states
+  const float t3 = 3.0f * param;
+  SelectArgs sa{X, ld, nc, metric, N, k, R, ids, dist, T, sel_ids, sel_dist, sel_n, P, M, stage,
+                nullptr, nullptr, 0, 0, rule, a2, t3};
   const uint32_t grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));
-  const uint32_t dpad = (d->dim + 31) / 32 * 32;
-  const bool use_mfma = k <= kSelMfmaMaxK && !(p->flags & FGIM_FLAG_NO_MFMA_SCREEN);
+  const uint32_t dpad = (dim + 31) / 32 * 32;
+  const bool use_mfma = k <= kSelMfmaMaxK && !(flags & FGIM_FLAG_NO_MFMA_SCREEN);
   if (use_mfma) {
-    float *nrm2 = nullptr, *qerr2 = nullptr;
-    FGIM_TRY(scr.get(&nrm2, N));
-    FGIM_TRY(scr.get(&qerr2, N));
-    HIP_TRY(launch_row_norms(d->base, N, d->dim, d->ld, nrm2, qerr2, s));
+    const float* nrm2 = nrm2_in;
+    const float* qerr2 = qerr2_in;
+    if (!nrm2 || !qerr2) {
+      float *n2 = nullptr, *q2 = nullptr;
+      FGIM_TRY(scr.get(&n2, n_x));
+      FGIM_TRY(scr.get(&q2, n_x));
+      HIP_TRY(launch_row_norms(X, n_x, dim, ld, n2, q2, s));
+      nrm2 = n2;
+      qerr2 = q2;
+    }
     sa.nrm2 = nrm2;
     sa.qerr2 = qerr2;
     sa.dpad = dpad;
@@ -506,6 +478,54 @@ fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32
                                   static_cast<int>(smem)));
     hipLaunchKernelGGL(select_kernel<16>, dim3(grid), dim3(256), smem, s, sa);
   }
+  HIP_TRY(hipGetLastError());
+  return FGIM_OK;
+}
+
+// Stage 3.  Lists from a caller are checked first (ids in range, no entry
+// after a free slot); the merge passes its own refined lists as trusted
+// and skips the check and its host wait.
+fgim_status prune_impl(const fgim_dataset* d, const fgim_params* p, const uint32_t* ids, const float* dist,
+                       const uint32_t* T, uint32_t* pg_ids, uint32_t* pg_deg, hipStream_t s, bool trusted) {
+  FGIM_TRY(check_dataset(d, false));
+  if (!p) return fail(FGIM_ERR_INVALID_ARG, "params is NULL");
+  if (!ids || !dist || !T || !pg_ids || !pg_deg) return fail(FGIM_ERR_INVALID_ARG, "NULL buffer");
+  if (p->k == 0 || p->k > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "k = %u out of 1..%u", p->k, FGIM_MAX_K);
+  if (p->R == 0 || p->R > FGIM_MAX_K) return fail(FGIM_ERR_INVALID_ARG, "R = %u out of 1..%u", p->R, FGIM_MAX_K);
+  const uint64_t N = d->n_total, k = p->k, R = p->R;
+  if (N * std::max(k, R) >= 0xFFFFFFFFull) return fail(FGIM_ERR_UNSUPPORTED, "N x max(k, R) exceeds 32-bit offsets");
+  if (p->select_rule > FGIM_SELECT_TAU) return fail(FGIM_ERR_INVALID_ARG, "unknown select_rule %u", p->select_rule);
+  if (p->select_rule != FGIM_SELECT_RNG && d->metric == FGIM_IP)
+    return fail(FGIM_ERR_INVALID_ARG, "alpha-RNG and tau-MNG need a metric distance (L2 or cosine); "
+                                      "transform inner-product data with fgim_mips_to_l2");
+  if (p->select_rule == FGIM_SELECT_ALPHA && !(p->select_param >= 1.0f))
+    return fail(FGIM_ERR_INVALID_ARG, "alpha = %g must be >= 1", static_cast<double>(p->select_param));
+  if (p->select_rule == FGIM_SELECT_TAU && !(p->select_param >= 0.0f && p->select_param < 1e30f))
+    return fail(FGIM_ERR_INVALID_ARG, "tau = %g must be finite and >= 0", static_cast<double>(p->select_param));
+  Scratch scr(s);
+  uint32_t *sel_ids = nullptr, *sel_n = nullptr, *cnt = nullptr, *off = nullptr, *cur = nullptr, *tmp = nullptr,
+           *err = nullptr;
+  float* sel_dist = nullptr;
+  uint64_t* rev = nullptr;
+  FGIM_TRY(scr.get(&sel_ids, N * R));
+  FGIM_TRY(scr.get(&sel_dist, N * R));
+  FGIM_TRY(scr.get(&sel_n, N));
+  FGIM_TRY(scr.get(&cnt, N + 1));
+  FGIM_TRY(scr.get(&off, N + 1));
+  FGIM_TRY(scr.get(&cur, N + 1));
+  FGIM_TRY(scr.get(&rev, N * R));
+  FGIM_TRY(scr.get(&tmp, scan_tmp_words(N) + 16));
+  FGIM_TRY(scr.get(&err, 4));
+  if (!trusted) {
+    HIP_TRY(fill_u32(err, 0u, 1, s));
+    hipLaunchKernelGGL(validate_lists_kernel, dim3(grid_n(N * k)), dim3(256), 0, s, ids, N * k, N, p->k, err);
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    if (herr) return fail(FGIM_ERR_GRAPH, "a k-NN list holds an id >= n_total or an entry after a free slot");
+  }
+  FGIM_TRY(select_lists(d->base, N, d->ld, d->dim, d->metric, N, p->k, p->R, ids, dist, T, p->select_rule,
+                        p->select_param, p->flags, nullptr, nullptr, sel_ids, sel_dist, sel_n, scr, s));
   HIP_TRY(hipGetLastError());
   HIP_TRY(fill_u32(cnt, 0u, N, s));
   hipLaunchKernelGGL(sel_count_kernel, dim3(grid_n(N * R)), dim3(256), 0, s, sel_ids, sel_n, N, p->R, cnt);

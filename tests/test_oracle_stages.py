@@ -644,3 +644,64 @@ def test_rerank_takes_the_first_valid_results():
         cand.sort()
         got = [(float(dd[r, t]), int(ids[r, t])) for t in range(k) if ids[r, t] != NONE]
         assert got == cand[:k], u
+
+
+def test_hnsw_layers_on_a_line():
+    # Section 4.3.3: points 3i on a line; every 4th point reaches layer 1 and
+    # every 16th layer 2.  Within a layer the heuristic keeps the nearest
+    # member on each side (the next one further out is closer to that
+    # member than to u), the reverse edges are the same edges, and pruning
+    # again keeps them: each layer is the path over its members.  The top
+    # entry is the smallest id of the highest layer.
+    n = 64
+    X = line_points(np.arange(n) * 3)
+    lv = np.zeros(n, np.uint8)
+    lv[::4] = 1
+    lv[::16] = 2
+    ids, adj, cnt, top = oracle.hnsw_layers(X, lv, M=4, ef=8)
+    assert cnt.tolist() == [16, 4] and top == 0
+    l1, a1 = ids[:16], adj[:16]
+    assert l1.tolist() == list(range(0, 64, 4))
+    for r, u in enumerate(l1.astype(np.int64)):
+        want = [v for v in (u - 4, u + 4) if 0 <= v < n]
+        assert [int(v) for v in a1[r] if v != NONE] == want
+    l2, a2 = ids[16:], adj[16:]
+    assert l2.tolist() == [0, 16, 32, 48]
+    assert [int(v) for v in a2[1] if v != NONE] == [0, 32]
+
+
+def test_hnsw_layers_invariants_and_search():
+    # members are exactly the vertices with level >= l; rows are sorted by
+    # distance, unique, without self-loops, at most M; searching the
+    # hierarchy over a 1-D path base graph finds the true nearest point
+    rng = np.random.default_rng(9)
+    cfg, X, subs = _cfg_small()
+    N = X.shape[0]
+    M = 8
+    lv = np.minimum(np.floor(-np.log(rng.random(N)) / np.log(M)), 5).astype(np.uint8)
+    ids, adj, cnt, top = oracle.hnsw_layers(X, lv, M=M, ef=32, metric=cfg.metric)
+    off = 0
+    for l in range(1, len(cnt) + 1):
+        mem = ids[off:off + cnt[l - 1]]
+        assert mem.tolist() == np.nonzero(lv >= l)[0].tolist()
+        for r in range(len(mem)):
+            row = [int(v) for v in adj[off + r] if v != NONE]
+            assert len(row) <= M and int(mem[r]) not in row and len(set(row)) == len(row)
+            assert all(lv[v] >= l for v in row)
+            d = [oracle.distance(X[mem[r]], X[v], cfg.metric) for v in row]
+            assert d == sorted(d)
+        off += int(cnt[l - 1])
+    assert lv[top] == len(cnt)
+    xs = rng.permutation(200).astype(np.float32) * 2.0
+    P = line_points(xs)
+    order = np.argsort(xs)
+    base = np.full((200, 2), NONE, np.uint32)
+    for i, v in enumerate(order):
+        nb = [order[j] for j in (i - 1, i + 1) if 0 <= j < 200]
+        base[v, :len(nb)] = nb
+    plv = np.minimum(np.floor(-np.log(rng.random(200)) / np.log(4)), 3).astype(np.uint8)
+    layers = oracle.hnsw_layers(P, plv, M=4, ef=16)
+    for qx in (-5.0, 17.3, 201.0, 398.9, 1000.0):
+        q = np.array([qx, 0, 0, 0], np.float32)
+        got, _ = oracle.hnsw_search(q, P, base, layers, 4, 1)
+        assert got[0] == int(np.argmin(np.abs(xs - qx)))
