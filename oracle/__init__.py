@@ -70,7 +70,7 @@ def lib() -> ctypes.CDLL:
         L.oracle_repair.argtypes = [u64, u32, vp, vp, vp, vp, vp]
         L.oracle_refine.restype = i32
         L.oracle_refine.argtypes = [vp, u64, u32, i32, vp, u32, u64, u32, u32, u32, vp, vp,
-                                    vp, vp, i32, i32, vp]
+                                    vp, vp, i32, i32, vp, u32]
         L.oracle_prune.restype = i32
         L.oracle_prune.argtypes = [vp, u64, u32, i32, u64, u32, vp, vp, vp, u32, vp, vp, vp,
                                    i32, i32, ctypes.c_float]
@@ -89,7 +89,7 @@ def lib() -> ctypes.CDLL:
         L.oracle_merged_entry.argtypes = [vp, u32, vp]
         L.oracle_merge.restype = i32
         L.oracle_merge.argtypes = [vp, u64, u32, i32, vp, u32, u32, u32, u32, u32, u32, vp,
-                                   vp, vp, i32, vp]
+                                   vp, vp, i32, vp, u32]
         L.oracle_bruteforce.restype = i32
         L.oracle_bruteforce.argtypes = [vp, u64, u64, u32, i32, vp, u64, u64, u32, vp, vp,
                                         vp, i32]
@@ -217,8 +217,11 @@ def repair(ids, dist, flags=None):
 
 
 def refine(X, subs, ids, dist, rounds: int, metric: str = "l2", k_rev: int = 0,
-           flags=None, do_repair: bool = True, threads: Optional[int] = None):
-    """Stage 2 on copies: (ids, dist, flags, T, stats)."""
+           flags=None, do_repair: bool = True, threads: Optional[int] = None,
+           batches: int = 1):
+    """Stage 2 on copies: (ids, dist, flags, T, stats).  batches > 1: the
+    streamlined form, each round visiting `batches` consecutive vertex
+    ranges in turn, each on the lists the ranges before it left."""
     X = _f32(X)
     arr, keep = _subs(subs)
     ids = np.array(ids, dtype=np.uint32, order="C", copy=True)
@@ -233,7 +236,7 @@ def refine(X, subs, ids, dist, rounds: int, metric: str = "l2", k_rev: int = 0,
     rc = lib().oracle_refine(_p(X), X.shape[1], X.shape[1], METRICS[metric],
                              ctypes.addressof(arr), len(subs), N, k, rounds, k_rev,
                              _p(ids), _p(dist), _p(flags), _p(T), int(do_repair),
-                             threads or default_threads(), _p(st))
+                             threads or default_threads(), _p(st), int(batches))
     if rc:
         raise ValueError("oracle_refine failed")
     return ids, dist, flags, T, {"proposals": int(st[0]), "repaired": int(st[1])}
@@ -339,8 +342,9 @@ def merged_entry(subs, valid=None) -> int:
 
 
 def merge(X, subs, k: int, L: int, rounds: int, R: int, metric: str = "l2",
-          k_rev: int = 0, threads: Optional[int] = None, valid=None):
-    """All three stages: (pg_ids [N, R], deg, entry).  valid: as cross_query."""
+          k_rev: int = 0, threads: Optional[int] = None, valid=None, batches: int = 1):
+    """All three stages: (pg_ids [N, R], deg, entry).  valid: as cross_query;
+    batches: as refine."""
     X = _f32(X)
     arr, keep = _subs(subs)
     N = X.shape[0]
@@ -351,7 +355,7 @@ def merge(X, subs, k: int, L: int, rounds: int, R: int, metric: str = "l2",
     rc = lib().oracle_merge(_p(X), X.shape[1], X.shape[1], METRICS[metric],
                             ctypes.addressof(arr), len(subs), k, L, rounds, k_rev, R,
                             _p(oi), _p(deg), ctypes.byref(ent), threads or default_threads(),
-                            None if vf is None else _p(vf))
+                            None if vf is None else _p(vf), int(batches))
     if rc:
         raise ValueError("oracle_merge failed")
     return oi, deg, ent.value

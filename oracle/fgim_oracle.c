@@ -408,8 +408,9 @@ uint32_t oracle_min_L(uint32_t k, uint32_t min_local, uint32_t h)
 }
 
 /* ------------------------------------------------------------------ */
-/* Stage 2: k-NNG refinement (Algorithm 3) in synchronous rounds, with   */
-/* indegree repair (Algorithm 4) after every round.                     */
+/* Stage 2: k-NNG refinement (Algorithm 3) in synchronous rounds or in   */
+/* streamlined micro-batches, with indegree repair (Algorithm 4) after   */
+/* every round.                                                         */
 /* ------------------------------------------------------------------ */
 
 /*
@@ -527,6 +528,7 @@ typedef struct {
     const uint32_t* co;
     prop_vec* pv;                  /* per thread */
     int* err;
+    uint64_t base;                 /* first vertex of the joined range */
 } join_ctx;
 
 /* worst key w[a] of the snapshot list of a (+inf when not full) */
@@ -557,7 +559,7 @@ static void join_range(void* p, uint64_t b, uint64_t e, int tid)
 {
     join_ctx* c = (join_ctx*)p;
     prop_vec* pv = &c->pv[tid];
-    for (uint64_t u = b; u < e; ++u) {
+    for (uint64_t u = c->base + b; u < c->base + e; ++u) {
         const uint32_t* Cn = c->cn + c->cn_off[u];
         uint64_t nn = c->cn_off[u + 1] - c->cn_off[u];
         const uint32_t* Co = c->co + c->co_off[u];
@@ -578,13 +580,15 @@ typedef struct {
     uint8_t* flags;
     const uint32_t* Sids;
     const float* Sdist;
+    const uint8_t* Sflags;
     const uint64_t* p_off;
     const prop_t* P;             /* proposals grouped by target a */
 } apply_ctx;
 
 /* list(a) <- first k of the (delta, id)-sorted union of the snapshot list
- * (entries stay old) and the proposals to a (entries are new); an id that
- * appears more than once keeps one entry, the snapshot's if present. */
+ * (entries keep their flag: old once a has been visited) and the proposals
+ * to a (entries are new); an id that appears more than once keeps one
+ * entry, the snapshot's if present. */
 static void apply_range(void* p, uint64_t b, uint64_t e, int tid)
 {
     (void)tid;
@@ -603,14 +607,15 @@ static void apply_range(void* p, uint64_t b, uint64_t e, int tid)
         for (uint32_t t = 0; t < c->k; ++t) {
             uint64_t i = a * c->k + t;
             if (c->Sids[i] == ORC_NONE) break;
-            U[n++] = (ent_t){c->Sdist[i], c->Sids[i], 0};
+            U[n++] = (ent_t){c->Sdist[i], c->Sids[i], (uint32_t)(c->Sflags[i] & FLAG_NEW)};
         }
         for (uint64_t t = 0; t < np; ++t) {
             const prop_t* q = &c->P[c->p_off[a] + t];
             U[n++] = (ent_t){q->d, q->b, FLAG_NEW};
         }
         /* equal ids carry equal distances (delta is symmetric), so after the
-         * sort duplicates are adjacent; flag order puts the old copy first */
+         * sort duplicates are adjacent; flag order puts an old copy first, and
+         * a new snapshot entry and a proposal agree on the flag */
         qsort(U, n, sizeof(ent_t), ent_cmp);
         uint32_t outn = 0;
         for (size_t t = 0; t < n && outn < c->k; ++t) {
@@ -687,22 +692,26 @@ static int cmp_prop_target(const void* a, const void* b)
 }
 
 /*
- * One synchronous round of Algorithm 3's Visit + Update over all vertices:
- *  Visit: fwd_new(u)/fwd_old(u) split u's list by flag; rev_new(v)/rev_old(v)
- *    hold the vertices whose new/old list entries point at v (first k_rev by
+ * Algorithm 3's Visit + Update for the vertices u in [lo, hi), on the lists
+ * as they stand (a synchronous round is the range [0, N)):
+ *  Visit: fwd_new(u)/fwd_old(u) split u's list by flag; rev_new(u)/rev_old(u)
+ *    hold the vertices whose new/old list entries point at u (first k_rev by
  *    (delta, id)); Cn(u) = fwd_new(u) U rev_new(u); Co(u) = (fwd_old(u) U
- *    rev_old(u)) \ Cn(u); then every new entry becomes old.
- *  Update: see join_range; the proposals are applied to every list at once.
+ *    rev_old(u)) \ Cn(u); then the new entries of u's list become old.
+ *  Update: see join_range; the proposals are applied to every list at once,
+ *    before the next range is visited.
  * Returns the number of proposals applied, or -1 on failure.
  */
-static int64_t refine_round(const float* X, uint64_t ld, uint32_t dim, int metric,
+static int64_t refine_range(const float* X, uint64_t ld, uint32_t dim, int metric,
                             const uint32_t* gsub, uint64_t N, uint32_t k, uint32_t k_rev,
-                            uint32_t* ids, float* dist, uint8_t* flags, int threads)
+                            uint32_t* ids, float* dist, uint8_t* flags, int threads,
+                            uint64_t lo, uint64_t hi)
 {
     int64_t ret = -1;
     uint64_t *rn_off = NULL, *ro_off = NULL, *cn_off = NULL, *co_off = NULL, *p_off = NULL;
     uint32_t *rn = NULL, *ro = NULL, *cn = NULL, *co = NULL, *Sids = NULL;
     float* Sdist = NULL;
+    uint8_t* Sflags = NULL;
     prop_vec pv[256];
     int err[256] = {0};
     memset(pv, 0, sizeof(pv));
@@ -720,14 +729,20 @@ static int64_t refine_round(const float* X, uint64_t ld, uint32_t dim, int metri
     tmp = (uint32_t*)malloc(sizeof(uint32_t) * (2 * ((size_t)k + k_rev) + 1));
     Sids = (uint32_t*)malloc(sizeof(uint32_t) * N * k);
     Sdist = (float*)malloc(sizeof(float) * N * k);
+    Sflags = (uint8_t*)malloc(N * k + 1);
     if (!rn_off || !ro_off || !rn || !ro || !cn_off || !co_off || !cn || !co || !tmp ||
-        !Sids || !Sdist)
+        !Sids || !Sdist || !Sflags)
         goto done;
     if (!build_reverse(N, k, ids, dist, flags, 1, k_rev, rn_off, rn)) goto done;
     if (!build_reverse(N, k, ids, dist, flags, 0, k_rev, ro_off, ro)) goto done;
 
     cn_off[0] = co_off[0] = 0;
     for (uint64_t u = 0; u < N; ++u) {
+        if (u < lo || u >= hi) {           /* not visited in this range */
+            cn_off[u + 1] = cn_off[u];
+            co_off[u + 1] = co_off[u];
+            continue;
+        }
         /* Cn(u): sorted unique ids of fwd_new(u) U rev_new(u) */
         size_t n = 0;
         for (uint32_t t = 0; t < k; ++t) {
@@ -758,14 +773,15 @@ static int64_t refine_round(const float* X, uint64_t ld, uint32_t dim, int metri
         }
         co_off[u + 1] = wo;
     }
-    for (uint64_t i = 0; i < N * k; ++i) flags[i] &= (uint8_t)~FLAG_NEW;
+    for (uint64_t i = lo * k; i < hi * k; ++i) flags[i] &= (uint8_t)~FLAG_NEW;
     memcpy(Sids, ids, sizeof(uint32_t) * N * k);
     memcpy(Sdist, dist, sizeof(float) * N * k);
+    memcpy(Sflags, flags, N * k);
 
     if (threads < 1) threads = 1;
     if (threads > 256) threads = 256;
-    join_ctx jc = {X, ld, dim, metric, gsub, k, Sids, Sdist, cn_off, cn, co_off, co, pv, err};
-    parallel_for(N, threads, join_range, &jc);
+    join_ctx jc = {X, ld, dim, metric, gsub, k, Sids, Sdist, cn_off, cn, co_off, co, pv, err, lo};
+    parallel_for(hi - lo, threads, join_range, &jc);
     size_t total = 0;
     for (int t = 0; t < 256; ++t) {
         if (err[t]) goto done;
@@ -782,13 +798,13 @@ static int64_t refine_round(const float* X, uint64_t ld, uint32_t dim, int metri
     qsort(P, total, sizeof(prop_t), cmp_prop_target);
     for (size_t t = 0; t < total; ++t) p_off[P[t].a + 1] += 1;
     for (uint64_t a = 0; a < N; ++a) p_off[a + 1] += p_off[a];
-    apply_ctx ac = {k, ids, dist, flags, Sids, Sdist, p_off, P};
+    apply_ctx ac = {k, ids, dist, flags, Sids, Sdist, Sflags, p_off, P};
     parallel_for(N, threads, apply_range, &ac);
     ret = (int64_t)total;
 done:
     for (int t = 0; t < 256; ++t) free(pv[t].v);
     free(rn_off); free(ro_off); free(rn); free(ro); free(cn_off); free(co_off);
-    free(cn); free(co); free(tmp); free(Sids); free(Sdist); free(P); free(p_off);
+    free(cn); free(co); free(tmp); free(Sids); free(Sdist); free(Sflags); free(P); free(p_off);
     return ret;
 }
 
@@ -798,12 +814,19 @@ done:
  * `rounds` rounds; after each, indegree repair when do_repair != 0.  T (N)
  * receives the indegrees after the last round.  stats (nullable) receives
  * {proposals, repaired}.
+ *
+ * batches <= 1: each round visits every vertex against one snapshot
+ * (synchronous).  batches = B > 1: the streamlined form of Section 4.2.1,
+ * in which a vertex's Visit and Update read the latest graph: each round
+ * visits the ranges [b N / B, (b + 1) N / B), b = 0 .. B-1, in turn, and a
+ * range's proposals are applied before the next range is visited.  B = N
+ * is the one-vertex-at-a-time pass, in ascending id.
  */
 int oracle_refine(const float* X, uint64_t ld, uint32_t dim, int metric,
                   const oracle_sub* subs, uint32_t h, uint64_t N, uint32_t k,
                   uint32_t rounds, uint32_t k_rev, uint32_t* ids, float* dist,
                   uint8_t* flags, uint32_t* T, int do_repair, int threads,
-                  uint64_t* stats)
+                  uint64_t* stats, uint32_t batches)
 {
     if (!X || !ids || !dist || !flags || !T || k == 0) return -1;
     if (k_rev == 0) k_rev = k;
@@ -814,11 +837,16 @@ int oracle_refine(const float* X, uint64_t ld, uint32_t dim, int metric,
         if (gsub[v] >= h) { free(gsub); return -1; }
     }
     uint64_t props = 0, rep = 0;
+    if (batches < 1) batches = 1;
     for (uint32_t r = 0; r < rounds; ++r) {
-        int64_t p = refine_round(X, ld, dim, metric, gsub, N, k, k_rev, ids, dist, flags,
-                                 threads);
-        if (p < 0) { free(gsub); return -1; }
-        props += (uint64_t)p;
+        for (uint32_t bt = 0; bt < batches; ++bt) {
+            uint64_t lo = N * bt / batches, hi = N * (bt + 1) / batches;
+            if (lo == hi) continue;
+            int64_t p = refine_range(X, ld, dim, metric, gsub, N, k, k_rev, ids, dist, flags,
+                                     threads, lo, hi);
+            if (p < 0) { free(gsub); return -1; }
+            props += (uint64_t)p;
+        }
         if (do_repair) {
             uint64_t nr = 0;
             if (oracle_repair(N, k, ids, dist, flags, T, &nr)) { free(gsub); return -1; }
@@ -1147,7 +1175,8 @@ uint64_t oracle_merged_entry(const oracle_sub* subs, uint32_t h, const uint8_t* 
 int oracle_merge(const float* X, uint64_t ld, uint32_t dim, int metric,
                  const oracle_sub* subs, uint32_t h, uint32_t k, uint32_t L,
                  uint32_t rounds, uint32_t k_rev, uint32_t R, uint32_t* out_ids,
-                 uint32_t* out_deg, uint64_t* entry, int threads, const uint8_t* valid)
+                 uint32_t* out_deg, uint64_t* entry, int threads, const uint8_t* valid,
+                 uint32_t batches)
 {
     uint64_t N = 0;
     for (uint32_t i = 0; i < h; ++i) N += subs[i].n;
@@ -1162,7 +1191,7 @@ int oracle_merge(const float* X, uint64_t ld, uint32_t dim, int metric,
         goto out;
     for (uint64_t i = 0; i < N * k; ++i) flags[i] = ids[i] == ORC_NONE ? 0 : FLAG_NEW;
     if (oracle_refine(X, ld, dim, metric, subs, h, N, k, rounds, k_rev, ids, dist, flags, T,
-                      1, threads, NULL))
+                      1, threads, NULL, batches))
         goto out;
     if (oracle_prune(X, ld, dim, metric, N, k, ids, dist, T, R, out_ids, NULL, out_deg,
                      threads, ORC_SEL_RNG, 0.0f))
