@@ -55,6 +55,7 @@ extern "C" {
 #define FGIM_MAX_K 128u       /* k, R */
 #define FGIM_MAX_L 256u       /* beam width */
 #define FGIM_MAX_STRIDE 128u  /* adjacency row stride */
+#define FGIM_MAX_STREAM_BATCHES 4096u /* vertex ranges of a streamlined round */
 
 typedef enum {
     FGIM_OK = 0,
@@ -128,6 +129,13 @@ typedef struct {
      * swap-ins, alpha-RNG and tau-MNG); FGIM_SELECT_RNG is Algorithm 5. */
     uint32_t select_rule;      /* FGIM_SELECT_* */
     float select_param;        /* alpha (>= 1) or tau (>= 0); unused by RNG */
+    /* Refinement schedule (Section 4.2.1).  0 or 1: synchronous rounds,
+     * every vertex visited against one snapshot.  B in 2..FGIM_MAX_STREAM_
+     * BATCHES: streamlined rounds, which visit the vertex ranges
+     * [t n / B, (t + 1) n / B), t = 0 .. B-1, in turn; each range's Visit and
+     * Update read the lists as the earlier ranges left them.  Deterministic
+     * for every B. */
+    uint32_t stream_batches;
 } fgim_params;
 
 /* Selection rules: whether a kept neighbour w, at delta(w, v) from the
@@ -213,12 +221,14 @@ fgim_status fgim_cross_query_noalloc(const fgim_dataset* data, const fgim_params
 
 /*
  * Stage 2, k-NNG refinement (Section 4.2, Algorithms 3 and 4), run as
- * `rounds` synchronous rounds.  Each round: Visit splits each list and its
- * reverse lists into new and old candidates, Update proposes every
- * cross-sub-index pair of C_n^2 U C_n x C_o to both ends, every list keeps
- * its k best of old entries and proposals, then indegree repair links each
- * zero-indegree vertex into a neighbour's list.  All input entries count as
- * new.  knn_ids / knn_dist (device, n_total x k) are read and rewritten;
+ * `rounds` rounds.  Each round: Visit splits each list and its reverse
+ * lists into new and old candidates, Update proposes every cross-sub-index
+ * pair of C_n^2 U C_n x C_o to both ends, every list keeps its k best of its
+ * entries and the proposals, then indegree repair links each zero-indegree
+ * vertex into a neighbour's list.  A synchronous round does this for all
+ * vertices at once; a streamlined one (params->stream_batches > 1) for one
+ * vertex range after another, each on the lists the earlier ranges left
+ * (Section 4.2.1).  All input entries count as new.  knn_ids / knn_dist (device, n_total x k) are read and rewritten;
  * indegree (device, n_total, nullable) receives T after the last round.
  * Errors: FGIM_ERR_INVALID_ARG (arguments), FGIM_ERR_GRAPH (a list id that
  * is neither FGIM_NONE nor below n_total; checked on the device before any

@@ -66,7 +66,7 @@ class Params(ctypes.Structure):
                 ("autotune", ctypes.c_int), ("lanes_per_dist", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("visited_slots", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("select_rule", ctypes.c_uint32),
-                ("select_param", ctypes.c_float)]
+                ("select_param", ctypes.c_float), ("stream_batches", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -191,10 +191,10 @@ class Merge:
 def params(k: int, L: int, R: int = 0, rounds: int = 0, precision: str = "fp32",
            rerank: int = 0, k_rev: int = 0, autotune: bool = False, lanes_per_dist: int = 0,
            waves_per_cu: int = 0, visited_slots: int = 0, flags: int = 0, select_rule: str = "rng",
-           select_param: float = 0.0) -> Params:
+           select_param: float = 0.0, stream_batches: int = 0) -> Params:
     return Params(k, L, R, rounds, PRECISIONS[precision], rerank, k_rev, int(autotune),
                   lanes_per_dist, waves_per_cu, visited_slots, flags, SELECT_RULES[select_rule],
-                  float(select_param))
+                  float(select_param), stream_batches)
 
 
 def cross_query(m: Merge, p: Params, stats: bool = False):

@@ -157,17 +157,20 @@ __global__ void copy_u32_kernel(const uint32_t* a, uint32_t* b, uint64_t n) {
 // ---------------------------------------------------------------------------
 // Visit: reverse lists
 
-// reverse entry of v in u's list: key (stored delta, u)
+// reverse entry of v in u's list: key (stored delta, u), for the targets v
+// in [lo, hi) that this Visit covers
 // old entries of an inactive vertex's reverse list are not placed: no
 // join reads them (see rev_sizes_kernel)
 __global__ void rev_scatter_kernel(const uint64_t* keys, const uint32_t* flags, uint64_t nk, uint32_t k,
-                                   const uint32_t* active, uint32_t* cur, uint64_t* rev) {
+                                   const uint32_t* active, uint32_t* cur, uint64_t* rev, uint64_t lo, uint64_t hi) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const uint64_t kk = keys[i];
     if (kk == kSentinel) continue;
+    const uint32_t t = key_id(kk);
+    if (t < lo || t >= hi) continue;
     const bool isnew = flags[i] & kFlagNew;
-    if (!isnew && !active[key_id(kk)]) continue;
+    if (!isnew && !active[t]) continue;
     const uint32_t seg = 2u * key_id(kk) + (isnew ? 0u : 1u);
     const uint32_t pos = atomicAdd(&cur[seg], 1u);
     rev[pos] = (kk & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(i / k);
@@ -214,6 +217,7 @@ struct JoinArgs {
   unsigned long long* npairs;      // pairs emitted this round (may exceed pair_cap; 64-bit: no wrap)
   unsigned long long* npairs_max;  // largest npairs over the rounds
   uint32_t pair_cap;
+  uint64_t u_lo, u_hi;       // the vertices this Visit + Update covers
 };
 
 // per-vertex data the MFMA screen reads for every candidate
@@ -222,6 +226,14 @@ struct CandAux {
   float nrm2;      // squared FP32 norm of the row
   float qerr;      // norm of the row's BF16 rounding residual, inflated by its own rounding bound
 };
+
+FGIM_DEV CandAux make_aux(uint64_t worst, float nrm2, float qerr2, float gam) {
+  CandAux x;
+  x.worst = worst;
+  x.nrm2 = nrm2;
+  x.qerr = sqrtf(qerr2) * (1.0f + gam) * 1.0001f;
+  return x;
+}
 
 // top-k_rev of a reverse segment by key, appended to list (ids) via counter
 template <int NR>
@@ -297,7 +309,7 @@ __global__ void __launch_bounds__(256) join_kernel(JoinArgs a) {
   const int M = static_cast<int>(a.M);
   const int l = threadIdx.x % P;
 
-  for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
+  for (uint64_t u = a.u_lo + blockIdx.x; u < a.u_hi; u += gridDim.x) {
     if (threadIdx.x < 8) counters[threadIdx.x] = 0;
     __syncthreads();
     // forward entries split by flag
@@ -524,7 +536,7 @@ __global__ void __launch_bounds__(256) cand_kernel(JoinArgs a) {
   uint32_t* arr_o = s_o[wave];
   uint32_t* cid = s_c[wave];
   const float gam = fp32_gamma(a.dim);
-  for (uint64_t u = blockIdx.x * 4ull + wave; u < a.N; u += gridDim.x * 4ull) {
+  for (uint64_t u = a.u_lo + blockIdx.x * 4ull + wave; u < a.u_hi; u += gridDim.x * 4ull) {
     // u's list, the bounds of its two reverse segments and its screen data
     // are independent loads, issued together
     const bool in = static_cast<uint32_t>(lane) < a.k;
@@ -547,13 +559,7 @@ __global__ void __launch_bounds__(256) cand_kernel(JoinArgs a) {
     if (valid && !isnew) arr_o[mbcnt(mo)] = key_id(kk);
     uint32_t cnt[2] = {static_cast<uint32_t>(popc64(mn)), static_cast<uint32_t>(popc64(mo))};
     const uint64_t wk = readlane64(kk, static_cast<int>(a.k - 1));
-    if (lane == 0) {
-      CandAux x;
-      x.worst = wk;
-      x.nrm2 = nrm;
-      x.qerr = sqrtf(qe2) * (1.0f + gam) * 1.0001f;
-      a.aux[u] = x;
-    }
+    if (lane == 0) a.aux[u] = make_aux(wk, nrm, qe2, gam);
     // the k_rev closest reverse entries of each kind, appended by ballot
 #pragma unroll
     for (int kind = 0; kind < 2; ++kind) {
@@ -638,7 +644,7 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
   uint32_t pf_n = 0, pf_o = 0, pf_v = kNone;
   CandAux pf_x{};
   auto fetch_ids = [&](uint64_t w) {
-    if (w < a.N) {
+    if (w < a.u_hi) {
       pf_n = a.ccnt[2 * w];
       pf_o = a.ccnt[2 * w + 1];
       pf_v = threadIdx.x < kMfmaMaxC ? a.cand[w * kMfmaMaxC + threadIdx.x] : kNone;
@@ -647,10 +653,10 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
   auto fetch_aux = [&]() {
     if (threadIdx.x < pf_n + pf_o) pf_x = a.aux[pf_v];
   };
-  fetch_ids(blockIdx.x);
+  fetch_ids(a.u_lo + blockIdx.x);
   fetch_aux();
 
-  for (uint64_t u = blockIdx.x; u < a.N; u += gridDim.x) {
+  for (uint64_t u = a.u_lo + blockIdx.x; u < a.u_hi; u += gridDim.x) {
     if (threadIdx.x < 8) counters[threadIdx.x] = 0;
     if (threadIdx.x < kMfmaMaxC) pmask[threadIdx.x] = 0;
     const uint32_t nn = uniform(pf_n), no = uniform(pf_o);
@@ -969,6 +975,102 @@ __global__ void __launch_bounds__(256) apply_kernel(uint64_t* keys, uint32_t* fl
   }
 }
 
+// Apply of one streamlined micro-batch, which visited the lists in
+// [lo, hi): a list keeps the first k of its entries and the proposals to it,
+// one entry per id.  Its surviving entries keep their flags, except that
+// the visited lists' entries are old now; accepted proposals are new.  T and
+// the counts of new in-edges follow every change.  Lists outside the range
+// without proposals do not change and are skipped.
+template <int NR>
+__global__ void __launch_bounds__(256) apply_stream_kernel(uint64_t* keys, uint32_t* flags, uint64_t N, uint32_t k,
+                                                           uint64_t lo, uint64_t hi, const uint32_t* poff,
+                                                           const uint64_t* sorted, uint32_t* ptotal_max,
+                                                           const uint32_t* ptotal, uint32_t* T, uint32_t* newc) {
+  // the list index and its proposal bounds are wave-uniform (readfirstlane),
+  // so the skip below is a uniform branch in a loop with cross-lane steps
+  const uint64_t wave = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
+  const uint64_t nw = gridDim.x * 4ull;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    atomicMax(ptotal_max, *ptotal);
+    atomicAdd(ptotal_max + 2, *ptotal);
+  }
+  for (uint64_t a = wave; a < N; a += nw) {
+    const bool visited = a >= lo && a < hi;
+    const uint32_t b0 = uniform(poff[a]), b1 = uniform(poff[a + 1]);
+    if (!visited && b1 == b0) continue;
+    Pool<NR> list;
+    uint32_t fl[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t e = r * 64 + lane_id();
+      list.key[r] = e < k ? keys[a * k + e] : kSentinel;
+      fl[r] = e < k ? (flags[a * k + e] & kFlagNew) : 0u;
+      // a visited list's new entries turn old
+      if (visited && fl[r] && list.key[r] != kSentinel) atomicSub(&newc[key_id(list.key[r])], 1u);
+      if (visited) fl[r] = 0u;
+    }
+    list.exp = 0;
+    uint64_t old[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) old[r] = list.key[r];
+    for (uint32_t b = b0; b < b1; b += 64) {
+      const uint64_t ck = b + lane_id() < b1 ? sorted[b + lane_id()] : kSentinel;
+      list.insert_batch(ck, k, 1u);
+    }
+    if (b1 > b0) {
+      // an old entry is kept iff it is not beyond the new last entry
+      const uint64_t last = list.theta(k);
+#pragma unroll
+      for (int r = 0; r < NR; ++r) {
+        if (old[r] != kSentinel && old[r] > last) {
+          atomicSub(&T[key_id(old[r])], 1u);
+          if (fl[r]) atomicSub(&newc[key_id(old[r])], 1u);
+        }
+        if ((list.exp >> r) & 1u) {
+          atomicAdd(&T[key_id(list.key[r])], 1u);
+          atomicAdd(&newc[key_id(list.key[r])], 1u);
+        }
+      }
+    }
+    // the kept entries of the list are its first entries, in order, so the
+    // j-th entry that is not a proposal is the list's j-th entry
+    uint32_t before = 0;
+    uint32_t out[NR];
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const bool kept = !((list.exp >> r) & 1u);
+      const uint64_t m = ballot(kept);
+      const uint32_t j = before + mbcnt(m);
+      before += static_cast<uint32_t>(popc64(m));
+      uint32_t f = 0u;
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const uint32_t fq = static_cast<uint32_t>(__shfl(static_cast<int>(fl[q]), static_cast<int>(j % 64), 64));
+        if (j / 64 == static_cast<uint32_t>(q)) f = fq;
+      }
+      out[r] = kept ? f : 1u;
+    }
+#pragma unroll
+    for (int r = 0; r < NR; ++r) {
+      const uint32_t e = r * 64 + lane_id();
+      if (e < k) {
+        keys[a * k + e] = list.key[r];
+        flags[a * k + e] = list.key[r] == kSentinel ? 0u : out[r];
+      }
+    }
+  }
+}
+
+// the screen data of every vertex from its current list (a streamlined
+// micro-batch screens against the lists the earlier ones left)
+__global__ void aux_refresh_kernel(const uint64_t* keys, uint64_t N, uint32_t k, const float* nrm2, const float* qerr2,
+                                   uint32_t dim, CandAux* aux) {
+  const float gam = fp32_gamma(dim);
+  for (uint64_t u = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; u < N;
+       u += static_cast<uint64_t>(gridDim.x) * blockDim.x)
+    aux[u] = make_aux(keys[u * k + k - 1], nrm2[u], qerr2[u], gam);
+}
+
 // reverse-list segment sizes of the next Visit from the maintained counts:
 // 2v holds v's new in-edges, 2v+1 its old ones
 // Reverse-list sizes from the maintained counts.  A vertex is active when
@@ -976,10 +1078,17 @@ __global__ void __launch_bounds__(256) apply_kernel(uint64_t* keys, uint32_t* fl
 // empty, its join forms no pair and reads no reverse entry, so its old
 // reverse segment is left empty (the reverse lists of new entries are
 // always complete).
+// Only the vertices in [lo, hi), which this Visit covers, get segments.
 __global__ void rev_sizes_kernel(const uint32_t* T, const uint32_t* newc, const uint32_t* flags, uint32_t k,
-                                 uint64_t N, uint32_t* cnt, uint32_t* active) {
+                                 uint64_t N, uint32_t* cnt, uint32_t* active, uint64_t lo, uint64_t hi) {
   for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < N;
        v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    if (v < lo || v >= hi) {
+      active[v] = 0u;
+      cnt[2 * v] = 0u;
+      cnt[2 * v + 1] = 0u;
+      continue;
+    }
     const uint32_t n = newc[v];
     bool act = n > 0;
     for (uint32_t e = 0; e < k && !act; ++e) act = (flags[v * k + e] & kFlagNew) != 0;
@@ -1650,6 +1759,7 @@ struct RoundPlan {
   uint32_t join_grid, cand_grid, recheck_grid;
   size_t join_smem;
   bool use_mfma;
+  uint32_t batches;  // > 1: streamlined rounds of this many vertex ranges
 };
 
 // indegrees T of the lists in b.keys
@@ -1682,19 +1792,22 @@ hipError_t launch_repair(const RefineBufs& b, uint64_t N, uint32_t k, hipStream_
 }
 
 // one refinement round; only kernel launches (graph-capturable)
+hipError_t run_stream_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s);
+
 hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
+  if (rp.batches > 1) return run_stream_round(rp, b, s);
   const uint64_t N = rp.N, nk = N * rp.k;
   hipError_t e;
   // Visit: reverse-list sizes from the maintained indegrees (T) and new
   // in-edge counts, then the reverse CSR
   // (b.zmask holds the active flags until the repair reuses it)
   hipLaunchKernelGGL(rev_sizes_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, b.newc, b.flags, rp.k, N, b.rev_cnt,
-                     b.zmask);
+                     b.zmask, 0ull, N);
   if ((e = exclusive_scan(b.rev_cnt, b.rev_off, 2 * N, b.scan_tmp, s)) != hipSuccess) return e;
   if ((e = fill_u32(b.newc, 0u, N, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(2 * N)), dim3(256), 0, s, b.rev_off, b.rev_cur, 2 * N);
   hipLaunchKernelGGL(rev_scatter_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, b.zmask, b.rev_cur,
-                     b.rev);
+                     b.rev, 0ull, N);
   // Update
   if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
   if (rp.use_mfma) {
@@ -1722,6 +1835,65 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
     hipLaunchKernelGGL(apply_kernel<2>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, b.poff,
                        b.psorted, b.hdr + 1, b.hdr, b.T, b.newc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
+  if (!rp.repair) return hipSuccess;
+  return launch_repair(b, N, rp.k, s);
+}
+
+// A streamlined round (Section 4.2.1): the vertex ranges [t N / B,
+// (t + 1) N / B) in turn, each a Visit + Update on the lists the ranges
+// before it left, its proposals applied before the next range; indegree
+// repair at the end, as in a synchronous round.
+hipError_t run_stream_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
+  const uint64_t N = rp.N, nk = N * rp.k;
+  const uint64_t cus = static_cast<uint64_t>(device_cus());
+  hipError_t e;
+  for (uint32_t t = 0; t < rp.batches; ++t) {
+    const uint64_t lo = N * t / rp.batches, hi = N * (t + 1) / rp.batches;
+    if (lo == hi) continue;
+    JoinArgs ja = rp.ja;
+    ja.u_lo = lo;
+    ja.u_hi = hi;
+    const uint64_t n = hi - lo;
+    // Visit: reverse segments of the range's vertices only
+    hipLaunchKernelGGL(rev_sizes_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, b.newc, b.flags, rp.k, N, b.rev_cnt,
+                       b.zmask, lo, hi);
+    if ((e = exclusive_scan(b.rev_cnt, b.rev_off, 2 * N, b.scan_tmp, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(2 * N)), dim3(256), 0, s, b.rev_off, b.rev_cur, 2 * N);
+    hipLaunchKernelGGL(rev_scatter_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, b.zmask,
+                       b.rev_cur, b.rev, lo, hi);
+    // Update of the range
+    if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
+    if (rp.use_mfma) {
+      hipLaunchKernelGGL(aux_refresh_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.keys, N, rp.k, ja.nrm2, ja.qerr2,
+                         ja.dim, ja.aux);
+      if ((e = fill_u32(reinterpret_cast<uint32_t*>(ja.npairs), 0u, 2, s)) != hipSuccess) return e;
+      hipLaunchKernelGGL(cand_kernel, dim3(static_cast<uint32_t>(std::min<uint64_t>((n + 3) / 4, cus * 16))), dim3(256),
+                         0, s, ja);
+      hipLaunchKernelGGL(join_mfma_kernel, dim3(static_cast<uint32_t>(std::min<uint64_t>(n, cus * 8))), dim3(256),
+                         rp.join_smem, s, ja);
+      if (rp.mmax == 4)
+        hipLaunchKernelGGL(recheck_kernel<4>, dim3(rp.recheck_grid), dim3(256), 0, s, ja);
+      else
+        hipLaunchKernelGGL(recheck_kernel<16>, dim3(rp.recheck_grid), dim3(256), 0, s, ja);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    } else if ((e = launch_join(ja, rp.nr, rp.mmax, static_cast<uint32_t>(std::min<uint64_t>(n, cus * 8)), rp.join_smem,
+                                s)) != hipSuccess) {
+      return e;
+    }
+    if ((e = fill_u32(b.pcnt, 0u, N, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(prop_count_kernel, dim3(4096), dim3(256), 0, s, b.ptgt, b.hdr, rp.cap, b.pcnt);
+    if ((e = exclusive_scan(b.pcnt, b.poff, N, b.scan_tmp, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.poff, b.pcur, N);
+    hipLaunchKernelGGL(prop_scatter_kernel, dim3(4096), dim3(256), 0, s, b.ptgt, b.pkey, b.hdr, rp.cap, b.pcur,
+                       b.psorted);
+    if (rp.nr == 1)
+      hipLaunchKernelGGL(apply_stream_kernel<1>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, lo, hi,
+                         b.poff, b.psorted, b.hdr + 1, b.hdr, b.T, b.newc);
+    else
+      hipLaunchKernelGGL(apply_stream_kernel<2>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, lo, hi,
+                         b.poff, b.psorted, b.hdr + 1, b.hdr, b.T, b.newc);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
   if (!rp.repair) return hipSuccess;
   return launch_repair(b, N, rp.k, s);
 }
@@ -1758,6 +1930,8 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   if (nk >= 0xFFFFFFFFull || 2 * N + 1 >= 0xFFFFFFFFull)
     return fail(FGIM_ERR_UNSUPPORTED, "N x k = %llu list entries exceed 32-bit offsets", (unsigned long long)nk);
   const bool repair = !(p->flags & FGIM_FLAG_NO_REPAIR);
+  if (p->stream_batches > FGIM_MAX_STREAM_BATCHES)
+    return fail(FGIM_ERR_INVALID_ARG, "stream_batches = %u > %u", p->stream_batches, FGIM_MAX_STREAM_BATCHES);
   if (!trusted) {
     Scratch chk(s);
     uint32_t* err = nullptr;
@@ -1871,6 +2045,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     rp.repair = repair;
     rp.nr = std::max(p->k, k_rev) <= 64 ? 1 : 2;
     rp.mmax = M <= 4 ? 4 : 16;
+    rp.batches = p->stream_batches;
     JoinArgs& ja = rp.ja;
     ja.X = d->base;
     ja.ld = d->ld;
@@ -1907,6 +2082,8 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     ja.npairs = reinterpret_cast<unsigned long long*>(b.hdr + 16);
     ja.npairs_max = reinterpret_cast<unsigned long long*>(b.hdr + 18);
     ja.pair_cap = static_cast<uint32_t>(pair_cap);
+    ja.u_lo = 0;
+    ja.u_hi = N;
     rp.use_mfma = use_mfma;
     rp.join_smem = use_mfma ? mfma_smem : base_smem + (stage_rows ? rows_smem : 0);
     rp.join_grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));

@@ -21,6 +21,19 @@ def test_header_and_binding_agree():
     assert sorted(fg.EXPORTS) == _declared()
 
 
+def _struct_fields(name):
+    src = open(os.path.join(ROOT, "include", "fgim.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    body = re.search(r"typedef struct \{([^{}]*)\} " + name + ";", src).group(1)
+    return [re.sub(r"\[.*\]", "", d.split()[-1]).lstrip("*") for d in body.split(";") if d.strip()]
+
+
+@pytest.mark.parametrize("name,cls", [("fgim_params", "Params"), ("fgim_dataset", "Dataset"),
+                                      ("fgim_stats", "Stats"), ("fgim_subindex", "Subindex")])
+def test_binding_structs_follow_the_header(name, cls):
+    assert [f for f, _ in getattr(fg, cls)._fields_] == _struct_fields(name)
+
+
 def test_library_exports_every_declared_symbol():
     L = fg.lib()
     for name in _declared():
@@ -120,3 +133,10 @@ def test_selection_rule_arguments_rejected_on_host(metric, rule, param):
 def test_mips_to_l2_bad_arguments_rejected_on_host(args):
     rc = fg.lib().fgim_mips_to_l2(*args, None)
     assert rc in (1, 5), fg.lib().fgim_last_error()
+
+
+def test_stream_batches_limit_rejected_on_host():
+    d, keep = _dataset()
+    p = fg.params(k=8, L=16, rounds=1, stream_batches=5000)
+    rc = fg.lib().fgim_refine(ctypes.byref(d), ctypes.byref(p), 0x40000, 0x50000, None, None, None)
+    assert rc == 1 and b"stream_batches" in fg.lib().fgim_last_error()
