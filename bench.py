@@ -9,7 +9,13 @@ low-precision copy, FP32 re-rank).  Prints one JSON line.
 
   python bench.py [--steps K] [--warmup W] [--config cfg4] [--also cfg3]
                   [--forms fp32,bf16,fp8] [--no-cpu-baseline] [--no-recall]
-                  [--no-parity] [--queries Q] [--cpu-nodes N] [--autotune]
+                  [--no-parity] [--queries Q] [--parity-nodes N] [--autotune]
+  python bench.py --refine-study cfg2,cfg3ov [--study-batches 1,4,16,64]
+                  [--study-rounds 6] [--study-nodes 5000] [--steps K]
+
+The second form compares refinement schedules instead: k-NNG recall and
+stage-2 time after each number of rounds, synchronous and streamlined
+(Section 4.2.1), from one stage-1 result.
 
 Defaults: the precision-form workload (2 x 500,000 vectors, d = 768,
 cosine), plus the batching-form workload (8 uneven sub-indexes, 2 M vectors,
@@ -19,8 +25,9 @@ Roofline of the dominant kernel (the stage-1 beam search): algorithmic bytes
 per launch (distance computations x row bytes + expansions x adjacency row
 bytes + per-vertex query, local candidates and output) over the kernel's
 duration, timed with hipEvents on the stream the kernel runs on.  The
-denominators are the published 8 TB/s and a copy kernel's bandwidth
-measured in the same run.
+denominators are the published 8 TB/s and a read stream's bandwidth
+measured in the same run (the beam kernel only reads; a copy kernel's
+read + write bandwidth is reported beside it).
 
 Parity at full size: every form's stage-1 rows of sampled vertices are
 compared bit for bit with the oracle's (the FP8 form excepted: the oracle's
@@ -114,6 +121,75 @@ def copy_peak_gbs(dev, gib: float = 2.0, reps: int = 20) -> float:
     return 2.0 * n * 4 / float(np.median(ts)) / 1e9
 
 
+def read_peak_gbs(dev, gib: float = 4.0, reps: int = 20) -> float:
+    """Bandwidth of a plain read stream (a sum over a device array: bytes
+    read over time, median of reps), the ceiling of a read-bound kernel such
+    as the beam search; a copy is slower since it also writes."""
+    n = int(gib * (1 << 30)) // 4
+    src = torch.empty(n, dtype=torch.float32, device=dev).fill_(1.0)
+    for _ in range(3):
+        src.sum()
+    ts = []
+    for _ in range(reps):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        src.sum()
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b) / 1e3)
+    del src
+    torch.cuda.empty_cache()
+    return n * 4 / float(np.median(ts)) / 1e9
+
+
+def refine_study(fg, cfg, batch_list, max_rounds, n_nodes, reps, dev):
+    """Refinement schedules compared on one workload: k-NNG recall and
+    stage-2 time after r = 1..max_rounds rounds, synchronous (B = 1) and
+    streamlined (B vertex ranges per round), all from one stage-1 result."""
+    from workloads.evaluate import exact_knn_screened, tie_recall
+    X, graphs, reach, build_s = build_inputs(cfg, "cuda")
+    N = X.shape[0]
+    Xd = torch.from_numpy(X).to(dev)
+    gl = [(torch.from_numpy(a.view(np.int32)).to(dev), int(e)) for _, a, e in graphs]
+    m = fg.Merge(Xd, gl, cfg.metric)
+    knodes = sample_nodes(N, n_nodes, 7)
+    _, kd, _ = exact_knn_screened(X, X[knodes], cfg.k, cfg.metric, exclude=knodes, Xdev=Xd)
+    ids0, dist0, st1 = fg.cross_query(m, fg.params(k=cfg.k, L=cfg.L), stats=True)
+
+    def recall(ids):
+        return tie_recall(X, X[knodes], fg.as_uint32(ids)[knodes], kd[:, -1], cfg.k, cfg.metric)
+
+    out = {"workload": cfg.name, "N": N, "k": cfg.k, "rounds_configured": cfg.rounds,
+           "stage1_ms": round(st1["ms_stage"][0], 3), "knng_recall_after_stage1": round(recall(ids0), 5),
+           "recall_nodes": len(knodes), "schedules": {}}
+    for B in batch_list:
+        rows = []
+        for r in range(1, max_rounds + 1):
+            p = fg.params(k=cfg.k, L=cfg.L, rounds=r, stream_batches=B)
+            ms = []
+            for _ in range(reps + 1):
+                ids, dist = ids0.clone(), dist0.clone()
+                _, st = fg.refine(m, p, ids, dist, stats=True)
+                ms.append(st["ms_stage"][1])
+            rows.append({"rounds": r, "stage2_ms": round(float(np.median(ms[1:])), 3),
+                         "knng_recall": round(recall(ids), 5), "proposals": st["proposals"]})
+            log(f"{cfg.name} B={B} rounds={r}: {rows[-1]}")
+        out["schedules"][str(B)] = rows
+    # rounds and time each schedule needs to reach what the synchronous
+    # rounds reach after the configured number of rounds
+    target = out["schedules"]["1"][cfg.rounds - 1]["knng_recall"] if 1 in batch_list else None
+    if target is not None:
+        out["target_recall"] = target
+        for B in batch_list:
+            hit = [row for row in out["schedules"][str(B)] if row["knng_recall"] >= target]
+            if hit:
+                t = out["stage1_ms"] + hit[0]["stage2_ms"]
+                out.setdefault("to_target", {})[str(B)] = {
+                    "rounds": hit[0]["rounds"], "stage2_ms": hit[0]["stage2_ms"],
+                    "stage1_plus_2_vectors_per_s": round(N / (t / 1e3), 1)}
+    return out
+
+
 def build_inputs(cfg, device):
     from workloads import build_input_pg, make_vectors, reach_fraction, split_sizes
     t0 = time.time()
@@ -162,7 +238,7 @@ def beam_roofline(fg, m, cfg, X, graphs, precision, st, beam_ms, peak_meas, coun
     traffic = measured_traffic(cfg.name, precision)
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-            "measured_peak": round(peak_meas, 1),
+            "measured_peak": round(peak_meas, 1), "measured_peak_kind": "read stream (sum over 4 GiB)",
             "frac_of_measured_peak": round(achieved / peak_meas, 4),
             "traffic_frac_of_measured_peak": None if traffic is None else round(traffic / kern_s / 1e9 / peak_meas, 4),
             "kernel": "beam_kernel (stage-1 cross-query)", "kernel_ms": round(kern_s * 1e3, 3),
@@ -176,8 +252,8 @@ def beam_roofline(fg, m, cfg, X, graphs, precision, st, beam_ms, peak_meas, coun
     # by concurrent searches (the entry region of each graph above all) hit
     # L2 and the memory-side cache, so `frac` can pass what HBM alone could
     # serve.  `traffic` is the counted fabric traffic (an upper bound of HBM
-    # bytes), and its fraction of the measured copy peak is the physically
-    # bounded figure.
+    # bytes), and its fraction of the measured read-stream peak is the
+    # physically bounded figure.
     roof["cache_assisted"] = bool(traffic is not None and alg_bytes > traffic)
     return roof
 
@@ -414,6 +490,12 @@ def main():
     ap.add_argument("--no-ndc-count", action="store_true",
                     help="take the distance count from the timed launch (re-scored ids included) "
                          "instead of an extra counting launch; for the largest workloads")
+    ap.add_argument("--refine-study", default="",
+                    help="comma-separated workloads: compare synchronous and streamlined refinement "
+                         "(k-NNG recall and stage-2 time per round) instead of the merge benchmark")
+    ap.add_argument("--study-batches", default="1,4,16,64")
+    ap.add_argument("--study-rounds", type=int, default=6)
+    ap.add_argument("--study-nodes", type=int, default=5000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -429,11 +511,21 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.refine_study:
+        batches = [int(b) for b in args.study_batches.split(",") if b]
+        res = {"study": "refinement schedule", "unit": "vectors/s", "steps": args.steps, "results": []}
+        for name in args.refine_study.split(","):
+            res["results"].append(refine_study(fg, get_config(name), batches, args.study_rounds, args.study_nodes,
+                                               args.steps, dev))
+        print(json.dumps(res), flush=True)
+        return
     peak = copy_peak_gbs(dev)
     log(f"copy kernel: {peak:.1f} GB/s (read + write)")
+    rpeak = read_peak_gbs(dev)
+    log(f"read stream: {rpeak:.1f} GB/s")
 
     cfg = get_config(args.config)
-    head, X, graphs = measure(fg, cfg, forms, args, dev, peak, not args.no_parity, not args.no_recall)
+    head, X, graphs = measure(fg, cfg, forms, args, dev, rpeak, not args.no_parity, not args.no_recall)
     lead = forms[0]
     hf = head["forms"][lead]
     out = {"metric": METRIC, "value": hf["value"], "unit": "vectors/s", "n_gpus": 1,
@@ -445,6 +537,7 @@ def main():
                       "rounds": cfg.rounds, "R": cfg.R, "precision": lead, "forms": forms,
                       "parallelism": "1 GPU"},
            "stages_ms": hf["stages_ms"], "roofline": hf["roofline"], "copy_peak_gbs": round(peak, 1),
+           "read_peak_gbs": round(rpeak, 1),
            "forms": head["forms"]}
     for key in ("input_build_s", "input_reach", "quality_setup"):
         if key in head:
@@ -452,7 +545,7 @@ def main():
     also = [] if args.also in ("", "none") else [a for a in args.also.split(",") if a]
     out["also"] = {}
     for name in also:
-        o, _, _ = measure(fg, get_config(name), forms, args, dev, peak, not args.no_parity,
+        o, _, _ = measure(fg, get_config(name), forms, args, dev, rpeak, not args.no_parity,
                           not args.no_recall)
         out["also"][name] = o
     if not args.no_cpu_baseline:

@@ -35,6 +35,11 @@
 
 #define FLAG_NEW 1u
 #define FLAG_REPLACED 2u
+/* A list entry (t -> v) recorded, at t's Visit while it was new, as a new
+ * reverse link of v, and not yet consumed by a Visit of v (Section 4.2.1:
+ * Visit records reverse links; the target's Visit moves them into Cn). */
+#define FLAG_RNEW 4u
+#define ENT_SNAPSHOT 0x100u   /* apply: the entry comes from the list itself */
 
 /* neighbour-selection rules of stage 3 (Section 4.3.1) */
 #define ORC_SEL_RNG 0     /* Algorithm 5: delta(u,v) < delta(w,v) */
@@ -586,9 +591,9 @@ typedef struct {
 } apply_ctx;
 
 /* list(a) <- first k of the (delta, id)-sorted union of the snapshot list
- * (entries keep their flag: old once a has been visited) and the proposals
- * to a (entries are new); an id that appears more than once keeps one
- * entry, the snapshot's if present. */
+ * (entries keep their flags) and the proposals to a (entries are new); an
+ * id that appears more than once keeps one entry, with the snapshot's flags
+ * if it is in the snapshot. */
 static void apply_range(void* p, uint64_t b, uint64_t e, int tid)
 {
     (void)tid;
@@ -607,25 +612,27 @@ static void apply_range(void* p, uint64_t b, uint64_t e, int tid)
         for (uint32_t t = 0; t < c->k; ++t) {
             uint64_t i = a * c->k + t;
             if (c->Sids[i] == ORC_NONE) break;
-            U[n++] = (ent_t){c->Sdist[i], c->Sids[i], (uint32_t)(c->Sflags[i] & FLAG_NEW)};
+            U[n++] = (ent_t){c->Sdist[i], c->Sids[i],
+                             ENT_SNAPSHOT | (uint32_t)(c->Sflags[i] & (FLAG_NEW | FLAG_RNEW))};
         }
         for (uint64_t t = 0; t < np; ++t) {
             const prop_t* q = &c->P[c->p_off[a] + t];
             U[n++] = (ent_t){q->d, q->b, FLAG_NEW};
         }
         /* equal ids carry equal distances (delta is symmetric), so after the
-         * sort duplicates are adjacent; flag order puts an old copy first, and
-         * a new snapshot entry and a proposal agree on the flag */
+         * sort the copies of an id are adjacent, in no particular order */
         qsort(U, n, sizeof(ent_t), ent_cmp);
         uint32_t outn = 0;
-        for (size_t t = 0; t < n && outn < c->k; ++t) {
+        for (size_t t = 0; t < n; ++t) {
             if (outn && c->ids[a * c->k + outn - 1] == U[t].id) {
-                if (!(U[t].flag & FLAG_NEW)) c->flags[a * c->k + outn - 1] = 0;
+                if (U[t].flag & ENT_SNAPSHOT)
+                    c->flags[a * c->k + outn - 1] = (uint8_t)(U[t].flag & ~ENT_SNAPSHOT);
                 continue;
             }
+            if (outn == c->k) break;
             c->ids[a * c->k + outn] = U[t].id;
             c->dist[a * c->k + outn] = U[t].d;
-            c->flags[a * c->k + outn] = (uint8_t)U[t].flag;
+            c->flags[a * c->k + outn] = (uint8_t)(U[t].flag & ~ENT_SNAPSHOT);
             ++outn;
         }
         for (; outn < c->k; ++outn) {
@@ -644,16 +651,16 @@ static int cmp_u32(const void* a, const void* b)
 }
 
 /* reverse lists: rev[v] = first k_rev by (stored delta, u) of {u : v in sel(u)},
- * where sel picks the list entries whose flag matches want_new */
+ * where sel picks the list entries whose revnew mark matches want_new */
 static int build_reverse(uint64_t N, uint32_t k, const uint32_t* ids, const float* dist,
-                         const uint8_t* flags, int want_new, uint32_t k_rev,
+                         const uint8_t* revnew, int want_new, uint32_t k_rev,
                          uint64_t* off /* N+1 */, uint32_t* out /* N*k_rev */)
 {
     uint64_t* cnt = (uint64_t*)calloc(N + 1, sizeof(uint64_t));
     if (!cnt) return 0;
     for (uint64_t i = 0; i < N * k; ++i) {
         if (ids[i] == ORC_NONE) continue;
-        if (((flags[i] & FLAG_NEW) != 0) != (want_new != 0)) continue;
+        if ((revnew[i] != 0) != (want_new != 0)) continue;
         cnt[ids[i] + 1] += 1;
     }
     for (uint64_t v = 0; v < N; ++v) cnt[v + 1] += cnt[v];
@@ -665,7 +672,7 @@ static int build_reverse(uint64_t N, uint32_t k, const uint32_t* ids, const floa
         for (uint32_t t = 0; t < k; ++t) {
             uint64_t i = u * k + t;
             if (ids[i] == ORC_NONE) continue;
-            if (((flags[i] & FLAG_NEW) != 0) != (want_new != 0)) continue;
+            if ((revnew[i] != 0) != (want_new != 0)) continue;
             buf[cur[ids[i]]++] = (ent_t){dist[i], (uint32_t)u, 0};
         }
     off[0] = 0;
@@ -694,10 +701,15 @@ static int cmp_prop_target(const void* a, const void* b)
 /*
  * Algorithm 3's Visit + Update for the vertices u in [lo, hi), on the lists
  * as they stand (a synchronous round is the range [0, N)):
- *  Visit: fwd_new(u)/fwd_old(u) split u's list by flag; rev_new(u)/rev_old(u)
- *    hold the vertices whose new/old list entries point at u (first k_rev by
- *    (delta, id)); Cn(u) = fwd_new(u) U rev_new(u); Co(u) = (fwd_old(u) U
- *    rev_old(u)) \ Cn(u); then the new entries of u's list become old.
+ *  Visit: fwd_new(u)/fwd_old(u) split u's list by flag.  Each new entry of a
+ *    visited list is recorded as a new reverse link of its target, and a
+ *    visited vertex consumes the new reverse links recorded for it:
+ *    rev_new(u) holds the w whose entry (w -> u) is such a link (recorded
+ *    earlier, or by this range's Visit), rev_old(u) the w of u's other
+ *    in-edges, each the first k_rev by (stored delta, w).  Cn(u) =
+ *    fwd_new(u) U rev_new(u); Co(u) = (fwd_old(u) U rev_old(u)) \ Cn(u); then
+ *    the new entries of u's list become old.  In a synchronous round every
+ *    link is recorded and consumed in the same Visit.
  *  Update: see join_range; the proposals are applied to every list at once,
  *    before the next range is visited.
  * Returns the number of proposals applied, or -1 on failure.
@@ -712,6 +724,7 @@ static int64_t refine_range(const float* X, uint64_t ld, uint32_t dim, int metri
     uint32_t *rn = NULL, *ro = NULL, *cn = NULL, *co = NULL, *Sids = NULL;
     float* Sdist = NULL;
     uint8_t* Sflags = NULL;
+    uint8_t* revnew = NULL;
     prop_vec pv[256];
     int err[256] = {0};
     memset(pv, 0, sizeof(pv));
@@ -733,8 +746,14 @@ static int64_t refine_range(const float* X, uint64_t ld, uint32_t dim, int metri
     if (!rn_off || !ro_off || !rn || !ro || !cn_off || !co_off || !cn || !co || !tmp ||
         !Sids || !Sdist || !Sflags)
         goto done;
-    if (!build_reverse(N, k, ids, dist, flags, 1, k_rev, rn_off, rn)) goto done;
-    if (!build_reverse(N, k, ids, dist, flags, 0, k_rev, ro_off, ro)) goto done;
+    revnew = (uint8_t*)malloc(N * k + 1);
+    if (!revnew) goto done;
+    for (uint64_t i = 0; i < N * k; ++i) {
+        uint64_t o = i / k;
+        revnew[i] = (flags[i] & FLAG_RNEW) || (o >= lo && o < hi && (flags[i] & FLAG_NEW));
+    }
+    if (!build_reverse(N, k, ids, dist, revnew, 1, k_rev, rn_off, rn)) goto done;
+    if (!build_reverse(N, k, ids, dist, revnew, 0, k_rev, ro_off, ro)) goto done;
 
     cn_off[0] = co_off[0] = 0;
     for (uint64_t u = 0; u < N; ++u) {
@@ -773,6 +792,13 @@ static int64_t refine_range(const float* X, uint64_t ld, uint32_t dim, int metri
         }
         co_off[u + 1] = wo;
     }
+    /* reverse links: consumed by a visited target, recorded for a later one */
+    for (uint64_t i = 0; i < N * k; ++i) {
+        if (ids[i] == ORC_NONE) continue;
+        uint64_t o = i / k;
+        if (ids[i] >= lo && ids[i] < hi) flags[i] &= (uint8_t)~FLAG_RNEW;
+        else if (o >= lo && o < hi && (flags[i] & FLAG_NEW)) flags[i] |= (uint8_t)FLAG_RNEW;
+    }
     for (uint64_t i = lo * k; i < hi * k; ++i) flags[i] &= (uint8_t)~FLAG_NEW;
     memcpy(Sids, ids, sizeof(uint32_t) * N * k);
     memcpy(Sdist, dist, sizeof(float) * N * k);
@@ -804,13 +830,16 @@ static int64_t refine_range(const float* X, uint64_t ld, uint32_t dim, int metri
 done:
     for (int t = 0; t < 256; ++t) free(pv[t].v);
     free(rn_off); free(ro_off); free(rn); free(ro); free(cn_off); free(co_off);
-    free(cn); free(co); free(tmp); free(Sids); free(Sdist); free(Sflags); free(P); free(p_off);
+    free(cn); free(co); free(tmp); free(Sids); free(Sdist); free(Sflags); free(revnew); free(P);
+    free(p_off);
     return ret;
 }
 
 /*
  * Stage 2 on an N x k list set sorted by (delta, id).  `flags` (N x k, bit 0 =
- * new) is in/out; pass all-new flags for a stage-1 output.  Runs exactly
+ * new, bit 2 = an unconsumed new reverse link, FLAG_RNEW) is in/out; pass
+ * all-new flags for a stage-1 output.  Synchronous rounds never leave
+ * FLAG_RNEW set.  Runs exactly
  * `rounds` rounds; after each, indegree repair when do_repair != 0.  T (N)
  * receives the indegrees after the last round.  stats (nullable) receives
  * {proposals, repaired}.

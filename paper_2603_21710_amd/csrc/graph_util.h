@@ -9,6 +9,9 @@ namespace fgim {
 
 constexpr uint8_t kFlagNew = 1;
 constexpr uint8_t kFlagReplaced = 2;
+// a list entry (t -> v) that t's Visit recorded, while it was new, as a new
+// reverse link of v, not yet consumed by a Visit of v (streamlined rounds)
+constexpr uint8_t kFlagRevNew = 4;
 
 // per row of X: squared FP32 norm and squared norm of its BF16 rounding
 // residual (round to nearest even)

@@ -157,23 +157,87 @@ __global__ void copy_u32_kernel(const uint32_t* a, uint32_t* b, uint64_t n) {
 // ---------------------------------------------------------------------------
 // Visit: reverse lists
 
-// reverse entry of v in u's list: key (stored delta, u), for the targets v
-// in [lo, hi) that this Visit covers
+// reverse entry of v in u's list: key (stored delta, u)
 // old entries of an inactive vertex's reverse list are not placed: no
 // join reads them (see rev_sizes_kernel)
 __global__ void rev_scatter_kernel(const uint64_t* keys, const uint32_t* flags, uint64_t nk, uint32_t k,
-                                   const uint32_t* active, uint32_t* cur, uint64_t* rev, uint64_t lo, uint64_t hi) {
+                                   const uint32_t* active, uint32_t* cur, uint64_t* rev) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t kk = keys[i];
+    if (kk == kSentinel) continue;
+    const uint32_t t = key_id(kk);
+    const bool isnew = flags[i] & kFlagNew;
+    if (!isnew && !active[t]) continue;
+    const uint32_t seg = 2u * t + (isnew ? 0u : 1u);
+    const uint32_t pos = atomicAdd(&cur[seg], 1u);
+    rev[pos] = (kk & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(i / k);
+  }
+}
+
+// Visit of a streamlined range [lo, hi).  An entry (o -> t) is a new
+// reverse link of t when an earlier Visit of o recorded it and t has not
+// been visited since (kFlagRevNew), or when o is in the range and the entry
+// is new (recorded by this Visit).
+
+FGIM_DEV bool link_is_new(uint32_t fl, uint64_t o, uint64_t lo, uint64_t hi) {
+  return (fl & kFlagRevNew) || (o >= lo && o < hi && (fl & kFlagNew));
+}
+
+// reverse-segment sizes of the range's vertices: 2t new links, 2t+1 other
+// in-edges (cnt zero on entry)
+__global__ void rev_count_range_kernel(const uint64_t* keys, const uint32_t* flags, uint64_t nk, uint32_t k,
+                                       uint64_t lo, uint64_t hi, uint32_t* cnt) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
     const uint64_t kk = keys[i];
     if (kk == kSentinel) continue;
     const uint32_t t = key_id(kk);
     if (t < lo || t >= hi) continue;
-    const bool isnew = flags[i] & kFlagNew;
-    if (!isnew && !active[t]) continue;
-    const uint32_t seg = 2u * key_id(kk) + (isnew ? 0u : 1u);
-    const uint32_t pos = atomicAdd(&cur[seg], 1u);
-    rev[pos] = (kk & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(i / k);
+    atomicAdd(&cnt[2u * t + (link_is_new(flags[i], i / k, lo, hi) ? 0u : 1u)], 1u);
+  }
+}
+
+// A range vertex is active when its Cn is not empty (a new list entry or a
+// new reverse link); an inactive one forms no pair, so its other in-edges
+// are not placed.  Vertices outside the range are inactive.
+__global__ void rev_active_range_kernel(const uint32_t* flags, uint64_t N, uint32_t k, uint64_t lo, uint64_t hi,
+                                        uint32_t* cnt, uint32_t* active) {
+  for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < N;
+       v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    bool act = false;
+    if (v >= lo && v < hi) {
+      act = cnt[2 * v] > 0;
+      for (uint32_t e = 0; e < k && !act; ++e) act = (flags[v * k + e] & kFlagNew) != 0;
+      if (!act) cnt[2 * v + 1] = 0u;
+    }
+    active[v] = act ? 1u : 0u;
+  }
+}
+
+// reverse entries of the range's vertices; then the range's vertices
+// consume their new links, and the range's new entries pointing outside it
+// are recorded as new links of their targets
+__global__ void rev_scatter_range_kernel(const uint64_t* keys, uint32_t* flags, uint64_t nk, uint32_t k,
+                                         uint64_t lo, uint64_t hi, const uint32_t* active, uint32_t* cur,
+                                         uint64_t* rev) {
+  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
+       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    const uint64_t kk = keys[i];
+    if (kk == kSentinel) continue;
+    const uint32_t t = key_id(kk);
+    const uint64_t o = i / k;
+    const uint32_t fl = flags[i];
+    if (t >= lo && t < hi) {
+      const bool isnew = link_is_new(fl, o, lo, hi);
+      if (isnew || active[t]) {
+        const uint32_t pos = atomicAdd(&cur[2u * t + (isnew ? 0u : 1u)], 1u);
+        rev[pos] = (kk & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(o);
+      }
+      if (fl & kFlagRevNew) flags[i] = fl & ~static_cast<uint32_t>(kFlagRevNew);
+    } else if (o >= lo && o < hi && (fl & kFlagNew)) {
+      flags[i] = fl | kFlagRevNew;
+    }
   }
 }
 
@@ -977,15 +1041,16 @@ __global__ void __launch_bounds__(256) apply_kernel(uint64_t* keys, uint32_t* fl
 
 // Apply of one streamlined micro-batch, which visited the lists in
 // [lo, hi): a list keeps the first k of its entries and the proposals to it,
-// one entry per id.  Its surviving entries keep their flags, except that
-// the visited lists' entries are old now; accepted proposals are new.  T and
-// the counts of new in-edges follow every change.  Lists outside the range
-// without proposals do not change and are skipped.
+// one entry per id.  Its surviving entries keep their flags (new, recorded
+// link), except that the visited lists' entries are no longer new; accepted
+// proposals are new.  T follows every change (the counts of new in-edges
+// are not kept: streamlined Visits count links directly).  Lists outside
+// the range without proposals do not change and are skipped.
 template <int NR>
 __global__ void __launch_bounds__(256) apply_stream_kernel(uint64_t* keys, uint32_t* flags, uint64_t N, uint32_t k,
                                                            uint64_t lo, uint64_t hi, const uint32_t* poff,
                                                            const uint64_t* sorted, uint32_t* ptotal_max,
-                                                           const uint32_t* ptotal, uint32_t* T, uint32_t* newc) {
+                                                           const uint32_t* ptotal, uint32_t* T) {
   // the list index and its proposal bounds are wave-uniform (readfirstlane),
   // so the skip below is a uniform branch in a loop with cross-lane steps
   const uint64_t wave = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
@@ -1004,10 +1069,9 @@ __global__ void __launch_bounds__(256) apply_stream_kernel(uint64_t* keys, uint3
     for (int r = 0; r < NR; ++r) {
       const uint32_t e = r * 64 + lane_id();
       list.key[r] = e < k ? keys[a * k + e] : kSentinel;
-      fl[r] = e < k ? (flags[a * k + e] & kFlagNew) : 0u;
+      fl[r] = e < k ? (flags[a * k + e] & (kFlagNew | kFlagRevNew)) : 0u;
       // a visited list's new entries turn old
-      if (visited && fl[r] && list.key[r] != kSentinel) atomicSub(&newc[key_id(list.key[r])], 1u);
-      if (visited) fl[r] = 0u;
+      if (visited) fl[r] &= ~static_cast<uint32_t>(kFlagNew);
     }
     list.exp = 0;
     uint64_t old[NR];
@@ -1022,14 +1086,8 @@ __global__ void __launch_bounds__(256) apply_stream_kernel(uint64_t* keys, uint3
       const uint64_t last = list.theta(k);
 #pragma unroll
       for (int r = 0; r < NR; ++r) {
-        if (old[r] != kSentinel && old[r] > last) {
-          atomicSub(&T[key_id(old[r])], 1u);
-          if (fl[r]) atomicSub(&newc[key_id(old[r])], 1u);
-        }
-        if ((list.exp >> r) & 1u) {
-          atomicAdd(&T[key_id(list.key[r])], 1u);
-          atomicAdd(&newc[key_id(list.key[r])], 1u);
-        }
+        if (old[r] != kSentinel && old[r] > last) atomicSub(&T[key_id(old[r])], 1u);
+        if ((list.exp >> r) & 1u) atomicAdd(&T[key_id(list.key[r])], 1u);
       }
     }
     // the kept entries of the list are its first entries, in order, so the
@@ -1048,7 +1106,7 @@ __global__ void __launch_bounds__(256) apply_stream_kernel(uint64_t* keys, uint3
         const uint32_t fq = static_cast<uint32_t>(__shfl(static_cast<int>(fl[q]), static_cast<int>(j % 64), 64));
         if (j / 64 == static_cast<uint32_t>(q)) f = fq;
       }
-      out[r] = kept ? f : 1u;
+      out[r] = kept ? f : static_cast<uint32_t>(kFlagNew);
     }
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
@@ -1078,17 +1136,10 @@ __global__ void aux_refresh_kernel(const uint64_t* keys, uint64_t N, uint32_t k,
 // empty, its join forms no pair and reads no reverse entry, so its old
 // reverse segment is left empty (the reverse lists of new entries are
 // always complete).
-// Only the vertices in [lo, hi), which this Visit covers, get segments.
 __global__ void rev_sizes_kernel(const uint32_t* T, const uint32_t* newc, const uint32_t* flags, uint32_t k,
-                                 uint64_t N, uint32_t* cnt, uint32_t* active, uint64_t lo, uint64_t hi) {
+                                 uint64_t N, uint32_t* cnt, uint32_t* active) {
   for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < N;
        v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    if (v < lo || v >= hi) {
-      active[v] = 0u;
-      cnt[2 * v] = 0u;
-      cnt[2 * v + 1] = 0u;
-      continue;
-    }
     const uint32_t n = newc[v];
     bool act = n > 0;
     for (uint32_t e = 0; e < k && !act; ++e) act = (flags[v * k + e] & kFlagNew) != 0;
@@ -1802,12 +1853,12 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   // in-edge counts, then the reverse CSR
   // (b.zmask holds the active flags until the repair reuses it)
   hipLaunchKernelGGL(rev_sizes_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, b.newc, b.flags, rp.k, N, b.rev_cnt,
-                     b.zmask, 0ull, N);
+                     b.zmask);
   if ((e = exclusive_scan(b.rev_cnt, b.rev_off, 2 * N, b.scan_tmp, s)) != hipSuccess) return e;
   if ((e = fill_u32(b.newc, 0u, N, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(2 * N)), dim3(256), 0, s, b.rev_off, b.rev_cur, 2 * N);
   hipLaunchKernelGGL(rev_scatter_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, b.zmask, b.rev_cur,
-                     b.rev, 0ull, N);
+                     b.rev);
   // Update
   if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
   if (rp.use_mfma) {
@@ -1854,13 +1905,17 @@ hipError_t run_stream_round(const RoundPlan& rp, const RefineBufs& b, hipStream_
     ja.u_lo = lo;
     ja.u_hi = hi;
     const uint64_t n = hi - lo;
-    // Visit: reverse segments of the range's vertices only
-    hipLaunchKernelGGL(rev_sizes_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, b.newc, b.flags, rp.k, N, b.rev_cnt,
-                       b.zmask, lo, hi);
+    // Visit: reverse segments of the range's vertices only, from the
+    // recorded links; then links are consumed and recorded
+    if ((e = fill_u32(b.rev_cnt, 0u, 2 * N, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(rev_count_range_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, lo, hi,
+                       b.rev_cnt);
+    hipLaunchKernelGGL(rev_active_range_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.flags, N, rp.k, lo, hi, b.rev_cnt,
+                       b.zmask);
     if ((e = exclusive_scan(b.rev_cnt, b.rev_off, 2 * N, b.scan_tmp, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(2 * N)), dim3(256), 0, s, b.rev_off, b.rev_cur, 2 * N);
-    hipLaunchKernelGGL(rev_scatter_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, b.zmask,
-                       b.rev_cur, b.rev, lo, hi);
+    hipLaunchKernelGGL(rev_scatter_range_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, lo, hi,
+                       b.zmask, b.rev_cur, b.rev);
     // Update of the range
     if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
     if (rp.use_mfma) {
@@ -1888,10 +1943,10 @@ hipError_t run_stream_round(const RoundPlan& rp, const RefineBufs& b, hipStream_
                        b.psorted);
     if (rp.nr == 1)
       hipLaunchKernelGGL(apply_stream_kernel<1>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, lo, hi,
-                         b.poff, b.psorted, b.hdr + 1, b.hdr, b.T, b.newc);
+                         b.poff, b.psorted, b.hdr + 1, b.hdr, b.T);
     else
       hipLaunchKernelGGL(apply_stream_kernel<2>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, lo, hi,
-                         b.poff, b.psorted, b.hdr + 1, b.hdr, b.T, b.newc);
+                         b.poff, b.psorted, b.hdr + 1, b.hdr, b.T);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (!rp.repair) return hipSuccess;

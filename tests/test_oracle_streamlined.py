@@ -41,10 +41,15 @@ def _inputs(seed, N, k, dim, sizes, metric, partial=0.2):
 
 def _sequential(X, gsub, ids, dd, rounds, k_rev, metric):
     """Algorithm 3 one vertex at a time in ascending id, with its updates
-    applied in place; reverse lists are read from the current lists (first
-    k_rev by (stored delta, id)).  Returns (ids, dist, flags)."""
+    applied in place.  An entry carries two marks: new (not yet seen by a
+    Visit of its owner) and a recorded reverse link (set when its owner's
+    Visit sees it new, moved into Cn by the next Visit of its target).
+    Reverse lists are read from the current lists, the first k_rev by
+    (stored delta, id).  Returns (ids, dist, flags) with flags bit 0 = new
+    and bit 2 = recorded reverse link."""
     N, k = ids.shape
-    lists = [[(int(d), int(v), True) for d, v in zip(dd[u], ids[u]) if v != NONE] for u in range(N)]
+    # entries [delta, id, new, rlink]
+    lists = [[[int(d), int(v), True, False] for d, v in zip(dd[u], ids[u]) if v != NONE] for u in range(N)]
 
     def insert(t, v, d):
         L = lists[t]
@@ -52,19 +57,26 @@ def _sequential(X, gsub, ids, dd, rounds, k_rev, metric):
             return
         if len(L) == k and (d, v) >= (L[-1][0], L[-1][1]):
             return
-        L.append((d, v, True))
+        L.append([d, v, True, False])
         L.sort(key=lambda e: (e[0], e[1]))
         del L[k:]
 
     for _ in range(rounds):
         for u in range(N):
-            fwd_new = [v for _, v, f in lists[u] if f]
-            fwd_old = [v for _, v, f in lists[u] if not f]
-            rn = sorted((d, w) for w in range(N) for d, v, f in lists[w] if v == u and f)[:k_rev]
-            ro = sorted((d, w) for w in range(N) for d, v, f in lists[w] if v == u and not f)[:k_rev]
+            inn = [(e[0], w, e[3]) for w in range(N) for e in lists[w] if e[1] == u]
+            rn = sorted((d, w) for d, w, rl in inn if rl)[:k_rev]
+            ro = sorted((d, w) for d, w, rl in inn if not rl)[:k_rev]
+            fwd_new = [e[1] for e in lists[u] if e[2]]
+            fwd_old = [e[1] for e in lists[u] if not e[2]]
             Cn = sorted(set(fwd_new) | {w for _, w in rn})
             Co = sorted((set(fwd_old) | {w for _, w in ro}) - set(Cn))
-            lists[u] = [(d, v, False) for d, v, _ in lists[u]]
+            for w in range(N):             # u consumes its reverse links
+                for e in lists[w]:
+                    if e[1] == u:
+                        e[3] = False
+            for e in lists[u]:             # and records its new entries as links
+                if e[2]:
+                    e[2], e[3] = False, True
             pairs = [(Cn[i], Cn[j]) for i in range(len(Cn)) for j in range(i + 1, len(Cn))]
             pairs += [(a, b) for a in Cn for b in Co]
             for a, b in pairs:
@@ -77,8 +89,8 @@ def _sequential(X, gsub, ids, dd, rounds, k_rev, metric):
     od = np.full((N, k), np.inf, np.float32)
     of = np.zeros((N, k), np.uint8)
     for u in range(N):
-        for j, (d, v, f) in enumerate(lists[u]):
-            oi[u, j], od[u, j], of[u, j] = v, d, int(f)
+        for j, (d, v, f, rl) in enumerate(lists[u]):
+            oi[u, j], od[u, j], of[u, j] = v, d, int(f) | (4 if rl else 0)
     return oi, od, of
 
 
@@ -86,6 +98,10 @@ def _sequential(X, gsub, ids, dd, rounds, k_rev, metric):
     (1, "l2", (14, 12, 10), 5, 5, 2),
     (2, "l2", (20, 16), 6, 3, 2),
     (3, "ip", (9, 11, 8, 10), 4, 4, 3),
+    # small k: a proposal that duplicates a list's last entry is common
+    (7, "l2", (12, 12), 2, 2, 3),
+    (8, "l2", (10, 9, 11), 3, 2, 3),
+    (9, "ip", (15, 15), 3, 3, 2),
 ])
 def test_one_vertex_batches_equal_the_sequential_pass(seed, metric, sizes, k, k_rev, rounds):
     N = sum(sizes)
@@ -105,6 +121,8 @@ def test_one_batch_is_the_synchronous_round():
     b = oracle.refine(X, subs, ids, dd, 3, "l2", batches=1)
     for x, y in zip(a[:4], b[:4]):
         assert (x == y).all()
+    # a synchronous round records and consumes every reverse link at once
+    assert not (a[2] & 4).any()
 
 
 def test_streamlined_differs_from_synchronous():
