@@ -136,6 +136,12 @@ typedef struct {
      * Update read the lists as the earlier ranges left them.  Deterministic
      * for every B. */
     uint32_t stream_batches;
+    /* Synchronous rounds with the MFMA join: the Update runs in this many
+     * vertex chunks (at most FGIM_MAX_STREAM_BATCHES) that share one buffer
+     * of screened pairs; every chunk joins against the same snapshot, so the
+     * count changes no result, only the buffer size.  0: as many as keep
+     * the buffer within 2^28 pairs (2 GiB). */
+    uint32_t update_chunks;
 } fgim_params;
 
 /* Selection rules: whether a kept neighbour w, at delta(w, v) from the
@@ -292,6 +298,18 @@ fgim_status fgim_search(const float* base, uint64_t n, uint32_t dim, uint64_t ld
                         uint32_t entry, const float* queries, uint64_t nq, uint64_t ldq,
                         uint32_t L, uint32_t topk, uint32_t* out_ids, float* out_dist,
                         void* stream);
+
+/*
+ * Measurement aid, not a step of the method: reads `bytes` bytes of `data`
+ * (device, 16-byte aligned, bytes a multiple of 16; may be NULL when bytes
+ * is 0) once with wide
+ * coalesced loads spread over every compute unit, and writes the XOR of all
+ * its 32-bit words to *checksum (device; zeroed first).  Its duration is the
+ * read-stream bandwidth that bounds a kernel which only reads, such as the
+ * stage-1 beam search.  Asynchronous on `stream`.
+ * Errors: FGIM_ERR_INVALID_ARG.
+ */
+fgim_status fgim_read_stream(const void* data, uint64_t bytes, uint32_t* checksum, void* stream);
 
 /*
  * Low-precision copy for the BF16 / FP8 forms.  BF16: codes = uint16

@@ -33,7 +33,7 @@ STATUS = {0: "FGIM_OK", 1: "FGIM_ERR_INVALID_ARG", 2: "FGIM_ERR_GRAPH",
           3: "FGIM_ERR_OUT_OF_MEMORY", 4: "FGIM_ERR_DEVICE", 5: "FGIM_ERR_UNSUPPORTED"}
 
 EXPORTS = ["fgim_cross_query", "fgim_cross_query_noalloc", "fgim_refine", "fgim_repair", "fgim_prune",
-           "fgim_merge", "fgim_search", "fgim_mips_to_l2", "fgim_hnsw_layers", "fgim_search_layers",
+           "fgim_merge", "fgim_search", "fgim_mips_to_l2", "fgim_hnsw_layers", "fgim_search_layers", "fgim_read_stream",
            "fgim_quantize", "fgim_min_beam_width", "fgim_release_scratch", "fgim_status_string",
            "fgim_last_error"]
 
@@ -66,7 +66,8 @@ class Params(ctypes.Structure):
                 ("autotune", ctypes.c_int), ("lanes_per_dist", ctypes.c_uint32),
                 ("waves_per_cu", ctypes.c_uint32), ("visited_slots", ctypes.c_uint32),
                 ("flags", ctypes.c_uint32), ("select_rule", ctypes.c_uint32),
-                ("select_param", ctypes.c_float), ("stream_batches", ctypes.c_uint32)]
+                ("select_param", ctypes.c_float), ("stream_batches", ctypes.c_uint32),
+                ("update_chunks", ctypes.c_uint32)]
 
 
 class Stats(ctypes.Structure):
@@ -107,6 +108,7 @@ def lib() -> ctypes.CDLL:
                             vp, vp],
             "fgim_quantize": [vp, u64, u32, u64, i32, vp, vp, vp],
             "fgim_mips_to_l2": [vp, u64, u32, u64, vp, u64, vp, vp],
+            "fgim_read_stream": [vp, u64, vp, vp],
             "fgim_hnsw_layers": [vp, u64, u32, u64, i32, vp, u32, u32, u32, vp, vp, vp, vp, vp],
             "fgim_search_layers": [vp, u64, u32, u64, i32, vp, u32, vp, vp, vp, u32, u32, u32, vp, u64,
                                    u64, u32, u32, vp, vp, vp],
@@ -191,10 +193,10 @@ class Merge:
 def params(k: int, L: int, R: int = 0, rounds: int = 0, precision: str = "fp32",
            rerank: int = 0, k_rev: int = 0, autotune: bool = False, lanes_per_dist: int = 0,
            waves_per_cu: int = 0, visited_slots: int = 0, flags: int = 0, select_rule: str = "rng",
-           select_param: float = 0.0, stream_batches: int = 0) -> Params:
+           select_param: float = 0.0, stream_batches: int = 0, update_chunks: int = 0) -> Params:
     return Params(k, L, R, rounds, PRECISIONS[precision], rerank, k_rev, int(autotune),
                   lanes_per_dist, waves_per_cu, visited_slots, flags, SELECT_RULES[select_rule],
-                  float(select_param), stream_batches)
+                  float(select_param), stream_batches, update_chunks)
 
 
 def cross_query(m: Merge, p: Params, stats: bool = False):
@@ -305,6 +307,17 @@ def quantize(X: torch.Tensor, precision: str):
     _check(lib().fgim_quantize(X.data_ptr(), n, d, X.stride(0), PRECISIONS[precision],
                                codes.data_ptr(), _ptr(scales), _stream()))
     return codes, scales
+
+
+def read_stream(buf: torch.Tensor) -> torch.Tensor:
+    """Reads every byte of a contiguous device tensor once (a measurement
+    aid: its duration gives the read-stream bandwidth); returns the XOR of
+    its 32-bit words as an int32 tensor [1]."""
+    if not buf.is_cuda or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous device tensor")
+    out = torch.empty(1, dtype=torch.int32, device=buf.device)
+    _check(lib().fgim_read_stream(buf.data_ptr(), buf.numel() * buf.element_size(), out.data_ptr(), _stream()))
+    return out
 
 
 def mips_to_l2(X: torch.Tensor):

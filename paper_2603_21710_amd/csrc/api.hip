@@ -351,6 +351,30 @@ __global__ void __launch_bounds__(256) mips_write_kernel(const float* X, uint64_
   }
 }
 
+// Read stream: every 16-byte word of the buffer once, kReadUnroll loads in
+// flight per thread, XOR-folded into one word so no load can be dropped.
+constexpr int kReadUnroll = 4;
+typedef uint32_t u32x4_t __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) read_stream_kernel(const u32x4_t* data, uint64_t n16, uint32_t* checksum) {
+  uint32_t x = 0;
+  const uint64_t stride = static_cast<uint64_t>(gridDim.x) * blockDim.x;
+  uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x;
+  for (; i + (kReadUnroll - 1) * stride < n16; i += kReadUnroll * stride) {
+    u32x4_t v[kReadUnroll];
+#pragma unroll
+    for (int u = 0; u < kReadUnroll; ++u) v[u] = data[i + u * stride];
+#pragma unroll
+    for (int u = 0; u < kReadUnroll; ++u) x ^= v[u].x ^ v[u].y ^ v[u].z ^ v[u].w;
+  }
+  for (; i < n16; i += stride) {
+    const u32x4_t v = data[i];
+    x ^= v.x ^ v.y ^ v.z ^ v.w;
+  }
+  for (int o = 32; o >= 1; o >>= 1) x ^= static_cast<uint32_t>(__shfl_xor(static_cast<int>(x), o, 64));
+  if (lane_id() == 0) atomicXor(checksum, x);
+}
+
 // ---------------------------------------------------------------------------
 // host helpers
 
@@ -751,6 +775,22 @@ fgim_status fgim_mips_to_l2(const float* base, uint64_t n, uint32_t dim, uint64_
   const uint64_t items = n * (dim / 4 + 1);
   hipLaunchKernelGGL(mips_write_kernel, dim3(static_cast<uint32_t>(std::min<uint64_t>((items + 255) / 256, 65536))),
                      dim3(256), 0, s, base, n, dim, ld, out, ld_out, max_norm2);
+  HIP_TRY(hipGetLastError());
+  return FGIM_OK;
+}
+
+fgim_status fgim_read_stream(const void* data, uint64_t bytes, uint32_t* checksum, void* stream) {
+  g_last_error.clear();
+  if (!checksum || (bytes && !data)) return fail(FGIM_ERR_INVALID_ARG, "data or checksum is NULL");
+  if (bytes % 16 || reinterpret_cast<uintptr_t>(data) % 16)
+    return fail(FGIM_ERR_INVALID_ARG, "data must be 16-byte aligned and a multiple of 16 bytes long");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIP_TRY(fill_u32(checksum, 0u, 1, s));
+  if (bytes == 0) return FGIM_OK;
+  const uint64_t n16 = bytes / 16;
+  const uint64_t blocks = std::min<uint64_t>((n16 + 255) / 256, static_cast<uint64_t>(device_cus()) * 16);
+  hipLaunchKernelGGL(read_stream_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(256), 0, s,
+                     static_cast<const u32x4_t*>(data), n16, checksum);
   HIP_TRY(hipGetLastError());
   return FGIM_OK;
 }

@@ -274,8 +274,8 @@ struct JoinArgs {
   uint32_t slice;            // dimensions staged in LDS at a time (multiple of 32)
   uint32_t* rechecked;       // pairs re-scored in FP32 after the screen
   // candidate sets of the MFMA join, built by cand_kernel
-  uint32_t* cand;            // N x kMfmaMaxC: Cn then Co, each ascending
-  uint32_t* ccnt;            // 2N: |Cn|, |Co|
+  uint32_t* cand;            // (u_hi - u_lo) x kMfmaMaxC: Cn then Co, each ascending
+  uint32_t* ccnt;            // 2 (u_hi - u_lo): |Cn|, |Co|
   struct CandAux* aux;       // N: per-vertex screen data
   uint64_t* pairs;           // pairs passing the screen: (Cn id) | (partner id) << 32
   unsigned long long* npairs;      // pairs emitted this round (may exceed pair_cap; 64-bit: no wrap)
@@ -534,6 +534,7 @@ constexpr uint32_t kMfmaMaxC = 128;       // candidates per vertex on the MFMA p
 constexpr uint32_t kMfmaMaxCn = 64;       // |Cn| bound on the MFMA path (k + k_rev <= 64)
 constexpr uint32_t kMfmaTilesPerWave = 7; // ceil(26 tile pairs / 4 waves) for |Cn| <= 64, c <= 128
 constexpr uint32_t kPairChunk = 1024;     // pair-buffer slots a join workgroup claims at a time
+constexpr uint64_t kPairBudget = 1ull << 28;  // pair-buffer entries (2 GiB) an Update chunk may use
 constexpr uint64_t kNoPair = ~0ull;       // an unused pair-buffer slot
 constexpr uint32_t kJoinStage = 4;  // row chunks a thread gathers before storing them
 
@@ -647,8 +648,8 @@ __global__ void __launch_bounds__(256) cand_kernel(JoinArgs a) {
     // no new candidate: no pair, so no set (the join skips the vertex)
     if (cnt[0] == 0) {
       if (lane == 0) {
-        a.ccnt[2 * u] = 0;
-        a.ccnt[2 * u + 1] = 0;
+        a.ccnt[2 * (u - a.u_lo)] = 0;
+        a.ccnt[2 * (u - a.u_lo) + 1] = 0;
       }
       continue;
     }
@@ -675,10 +676,10 @@ __global__ void __launch_bounds__(256) cand_kernel(JoinArgs a) {
     if (keep) cid[nn + mbcnt(mk)] = vo;
     const uint32_t no = static_cast<uint32_t>(popc64(mk));
     wave_lds_sync();
-    for (uint32_t i = lane; i < nn + no; i += 64) a.cand[u * kMfmaMaxC + i] = cid[i];
+    for (uint32_t i = lane; i < nn + no; i += 64) a.cand[(u - a.u_lo) * kMfmaMaxC + i] = cid[i];
     if (lane == 0) {
-      a.ccnt[2 * u] = nn;
-      a.ccnt[2 * u + 1] = no;
+      a.ccnt[2 * (u - a.u_lo)] = nn;
+      a.ccnt[2 * (u - a.u_lo) + 1] = no;
     }
     wave_lds_sync();
   }
@@ -709,9 +710,9 @@ __global__ void __launch_bounds__(256) join_mfma_kernel(JoinArgs a) {
   CandAux pf_x{};
   auto fetch_ids = [&](uint64_t w) {
     if (w < a.u_hi) {
-      pf_n = a.ccnt[2 * w];
-      pf_o = a.ccnt[2 * w + 1];
-      pf_v = threadIdx.x < kMfmaMaxC ? a.cand[w * kMfmaMaxC + threadIdx.x] : kNone;
+      pf_n = a.ccnt[2 * (w - a.u_lo)];
+      pf_o = a.ccnt[2 * (w - a.u_lo) + 1];
+      pf_v = threadIdx.x < kMfmaMaxC ? a.cand[(w - a.u_lo) * kMfmaMaxC + threadIdx.x] : kNone;
     }
   };
   auto fetch_aux = [&]() {
@@ -1811,6 +1812,7 @@ struct RoundPlan {
   size_t join_smem;
   bool use_mfma;
   uint32_t batches;  // > 1: streamlined rounds of this many vertex ranges
+  uint32_t chunks;   // Update of a synchronous round in this many vertex chunks (MFMA join)
 };
 
 // indegrees T of the lists in b.keys
@@ -1859,17 +1861,33 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(2 * N)), dim3(256), 0, s, b.rev_off, b.rev_cur, 2 * N);
   hipLaunchKernelGGL(rev_scatter_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, b.zmask, b.rev_cur,
                      b.rev);
-  // Update
+  // Update, in vertex chunks that share one pair buffer: every chunk joins
+  // against the same snapshot, and the proposals of all of them are applied
+  // together, so the chunking changes no result
   if ((e = fill_u32(b.hdr, 0u, 1, s)) != hipSuccess) return e;
   if (rp.use_mfma) {
-    if ((e = fill_u32(reinterpret_cast<uint32_t*>(rp.ja.npairs), 0u, 2, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(cand_kernel, dim3(rp.cand_grid), dim3(256), 0, s, rp.ja);
-    hipLaunchKernelGGL(join_mfma_kernel, dim3(rp.join_grid), dim3(256), rp.join_smem, s, rp.ja);
-    if (rp.mmax == 4)
-      hipLaunchKernelGGL(recheck_kernel<4>, dim3(rp.recheck_grid), dim3(256), 0, s, rp.ja);
-    else
-      hipLaunchKernelGGL(recheck_kernel<16>, dim3(rp.recheck_grid), dim3(256), 0, s, rp.ja);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
+    const uint64_t cus = static_cast<uint64_t>(device_cus());
+    // the screen reads every candidate's data, later chunks' vertices too
+    if (rp.chunks > 1)
+      hipLaunchKernelGGL(aux_refresh_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.keys, N, rp.k, rp.ja.nrm2,
+                         rp.ja.qerr2, rp.ja.dim, rp.ja.aux);
+    for (uint32_t c = 0; c < rp.chunks; ++c) {
+      JoinArgs ja = rp.ja;
+      ja.u_lo = N * c / rp.chunks;
+      ja.u_hi = N * (c + 1) / rp.chunks;
+      const uint64_t n = ja.u_hi - ja.u_lo;
+      if (n == 0) continue;
+      if ((e = fill_u32(reinterpret_cast<uint32_t*>(ja.npairs), 0u, 2, s)) != hipSuccess) return e;
+      hipLaunchKernelGGL(cand_kernel, dim3(static_cast<uint32_t>(std::min<uint64_t>((n + 3) / 4, cus * 16))), dim3(256),
+                         0, s, ja);
+      hipLaunchKernelGGL(join_mfma_kernel, dim3(static_cast<uint32_t>(std::min<uint64_t>(n, cus * 8))), dim3(256),
+                         rp.join_smem, s, ja);
+      if (rp.mmax == 4)
+        hipLaunchKernelGGL(recheck_kernel<4>, dim3(rp.recheck_grid), dim3(256), 0, s, ja);
+      else
+        hipLaunchKernelGGL(recheck_kernel<16>, dim3(rp.recheck_grid), dim3(256), 0, s, ja);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
   } else if ((e = launch_join(rp.ja, rp.nr, rp.mmax, rp.join_grid, rp.join_smem, s)) != hipSuccess) {
     return e;
   }
@@ -1987,6 +2005,8 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   const bool repair = !(p->flags & FGIM_FLAG_NO_REPAIR);
   if (p->stream_batches > FGIM_MAX_STREAM_BATCHES)
     return fail(FGIM_ERR_INVALID_ARG, "stream_batches = %u > %u", p->stream_batches, FGIM_MAX_STREAM_BATCHES);
+  if (p->update_chunks > FGIM_MAX_STREAM_BATCHES)
+    return fail(FGIM_ERR_INVALID_ARG, "update_chunks = %u > %u", p->update_chunks, FGIM_MAX_STREAM_BATCHES);
   if (!trusted) {
     Scratch chk(s);
     uint32_t* err = nullptr;
@@ -2019,24 +2039,44 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
   const size_t mfma_smem = mfma_head + static_cast<size_t>(kMfmaMaxC) * (slice + 8) * 2;
 
   uint64_t cap = std::max<uint64_t>(N * std::max<uint32_t>(4 * p->k, 64), 1 << 16);
-  // pairs passing the screen: about k per vertex in the first round at
-  // k = 32 on clustered data, several times that on others; an overflow
-  // re-runs the rounds with larger buffers, and the per-vertex demand seen
-  // so far sizes the buffers of later calls
-  uint64_t pair_cap = std::max<uint64_t>(N * 3 * p->k, 1 << 16) + static_cast<uint64_t>(device_cus()) * 8 * kPairChunk;
+  // Pairs passing the screen: about k per vertex in the first round at
+  // k = 32 on clustered data, several times that on others.  The pair
+  // buffer holds one chunk of the Update's vertices at a time and is kept
+  // within kPairBudget; the chunk count follows from the expected demand
+  // (the per-vertex demand seen so far in this process, else 3k).  A chunk
+  // that overflows re-runs the rounds with a larger buffer, or, at the
+  // budget, with more chunks.
+  const uint64_t reserve = static_cast<uint64_t>(device_cus()) * 8 * kPairChunk;
+  double ppv = 3.0 * p->k;
+  {
+    std::lock_guard<std::mutex> lock(g_demand_mu);
+    cap = std::max<uint64_t>(cap, static_cast<uint64_t>(g_props_per_vertex * 1.25 * static_cast<double>(N)) + 1024);
+    if (g_pairs_per_vertex > 0.0) ppv = g_pairs_per_vertex;
+  }
+  // The unit of one Update pass: a streamlined micro-batch, or a chunk of a
+  // synchronous round (whose count may grow on overflow).
+  const bool streamed = p->stream_batches > 1;
+  const uint64_t pair_limit = streamed ? 0xF0000000ull : kPairBudget;
+  uint32_t chunks = streamed ? 1u : p->update_chunks;
+  if (chunks == 0) {
+    const double demand = ppv * 1.25 * static_cast<double>(N);
+    chunks = static_cast<uint32_t>(std::min<double>(std::ceil(demand / static_cast<double>(kPairBudget - reserve)), N));
+    chunks = std::max<uint32_t>(chunks, 1);
+  }
+  auto unit_len = [&]() -> uint64_t {
+    const uint64_t parts = streamed ? p->stream_batches : chunks;
+    return std::min<uint64_t>(N, (N + parts - 1) / parts + 1);
+  };
+  uint64_t pair_cap = std::min<uint64_t>(static_cast<uint64_t>(ppv * 1.25 * static_cast<double>(unit_len())) + reserve,
+                                         pair_limit);
+  pair_cap = std::max<uint64_t>(pair_cap, 1 << 16);
   if (p->flags & FGIM_FLAG_MIN_BUFFERS) {
     cap = 1 << 16;
     pair_cap = 1 << 16;
-  } else {
-    std::lock_guard<std::mutex> lock(g_demand_mu);
-    cap = std::max<uint64_t>(cap, static_cast<uint64_t>(g_props_per_vertex * 1.25 * static_cast<double>(N)) + 1024);
-    pair_cap = std::max<uint64_t>(pair_cap, static_cast<uint64_t>(g_pairs_per_vertex * 1.25 * static_cast<double>(N)) +
-                                                static_cast<uint64_t>(device_cus()) * 8 * kPairChunk);
   }
   cap = std::min<uint64_t>(cap, 0xF0000000ull);
-  pair_cap = std::min<uint64_t>(pair_cap, 0xF0000000ull);
 
-  for (int attempt = 0; attempt < 3; ++attempt) {
+  for (int attempt = 0; attempt < 4; ++attempt) {
     Scratch scr(s);
     RefineBufs b{};
     FGIM_TRY(scr.get(&b.keys, nk));
@@ -2066,8 +2106,8 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     if (use_mfma) {
       FGIM_TRY(scr.get(&nrm2, N));
       FGIM_TRY(scr.get(&qerr2, N));
-      FGIM_TRY(scr.get(&cand, N * kMfmaMaxC));
-      FGIM_TRY(scr.get(&ccnt, 2 * N));
+      FGIM_TRY(scr.get(&cand, unit_len() * kMfmaMaxC));
+      FGIM_TRY(scr.get(&ccnt, 2 * unit_len()));
       FGIM_TRY(scr.get(&aux, N));
       FGIM_TRY(scr.get(&pairs, pair_cap));
       // the screen's error bound is derived for round-to-nearest-even BF16
@@ -2101,6 +2141,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     rp.nr = std::max(p->k, k_rev) <= 64 ? 1 : 2;
     rp.mmax = M <= 4 ? 4 : 16;
     rp.batches = p->stream_batches;
+    rp.chunks = chunks;
     JoinArgs& ja = rp.ja;
     ja.X = d->base;
     ja.ld = d->ld;
@@ -2210,7 +2251,19 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
       // later rounds of a truncated run may have needed less than a full
       // run does: at least double the buffer that overflowed
       if (hh[1] > cap) cap = std::min<uint64_t>(std::max<uint64_t>(static_cast<uint64_t>(hh[1]) * 5 / 4, 2 * cap) + 1024, 0xF0000000ull);
-      if (pairs_max > pair_cap) pair_cap = std::min<uint64_t>(std::max<uint64_t>(pairs_max * 5 / 4, 2 * pair_cap) + 1024, 0xF0000000ull);
+      if (pairs_max > pair_cap) {
+        const uint64_t want = std::max<uint64_t>(pairs_max * 5 / 4, 2 * pair_cap) + 1024;
+        if (want <= pair_limit) {
+          pair_cap = want;
+        } else if (streamed) {
+          pair_cap = pair_limit;
+        } else {
+          // at the budget: split the Update into proportionally more chunks
+          pair_cap = kPairBudget;
+          const double grow = std::ceil(static_cast<double>(pairs_max) * 1.25 / static_cast<double>(kPairBudget - reserve));
+          chunks = static_cast<uint32_t>(std::min<double>(static_cast<double>(chunks) * std::max(2.0, grow), N));
+        }
+      }
       continue;
     }
     hipLaunchKernelGGL(from_keys_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, nk, ids, dist);

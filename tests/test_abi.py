@@ -140,3 +140,17 @@ def test_stream_batches_limit_rejected_on_host():
     p = fg.params(k=8, L=16, rounds=1, stream_batches=5000)
     rc = fg.lib().fgim_refine(ctypes.byref(d), ctypes.byref(p), 0x40000, 0x50000, None, None, None)
     assert rc == 1 and b"stream_batches" in fg.lib().fgim_last_error()
+
+
+@pytest.mark.parametrize("data,nbytes,out", [(0, 64, 0x50000), (0x40000, 64, 0), (0x40004, 64, 0x50000),
+                                             (0x40000, 60, 0x50000), (0, 0, 0)])
+def test_read_stream_bad_arguments_rejected_on_host(data, nbytes, out):
+    assert fg.lib().fgim_read_stream(data, nbytes, out, None) == 1
+    assert fg.lib().fgim_last_error()
+
+
+def test_update_chunks_limit_rejected_on_host():
+    d, keep = _dataset()
+    p = fg.params(k=8, L=16, rounds=1, update_chunks=5000)
+    rc = fg.lib().fgim_refine(ctypes.byref(d), ctypes.byref(p), 0x40000, 0x50000, None, None, None)
+    assert rc == 1 and b"update_chunks" in fg.lib().fgim_last_error()

@@ -149,6 +149,24 @@ def test_buffer_overflow_reruns_to_the_same_result():
     assert st["proposals"] == st0["proposals"] and st["rechecked"] == st0["rechecked"]
 
 
+@pytest.mark.parametrize("name,sizes", [("cfg1", None), ("cfg3", (300, 500, 700, 150, 900, 400, 1200, 650))])
+def test_update_chunks_change_no_result(name, sizes):
+    """The Update of a synchronous round split into vertex chunks that share
+    one pair buffer (every chunk against the same snapshot) gives the
+    unsplit result, chunk boundaries included."""
+    cfg, X, graphs, m, ids, dist = _stage1(name, sizes)
+    oi, od, of, oT, ost = oracle.refine(X, graphs, _u32(ids), dist.cpu().numpy(), cfg.rounds, cfg.metric)
+    for chunks in (1, 7, 64):
+        print(f"case {name} update_chunks={chunks}", flush=True)
+        a_ids, a_d = ids.clone(), dist.clone()
+        T, st = fg.refine(m, fg.params(k=cfg.k, L=cfg.L, rounds=cfg.rounds, update_chunks=chunks), a_ids, a_d,
+                          stats=True)
+        assert (_u32(a_ids) == oi).all()
+        assert (a_d.cpu().numpy().view(np.uint32) == od.view(np.uint32)).all()
+        assert (_u32(T) == oT).all()
+        assert st["proposals"] == ost["proposals"]
+
+
 def test_refine_rejects_out_of_range_ids():
     cfg, X, graphs, m, ids, dist = _stage1("cfg1", None)
     bad = ids.clone()

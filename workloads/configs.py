@@ -124,6 +124,16 @@ CONFIGS: Dict[str, WorkloadConfig] = {
         dist_params=(("clusters", 1024), ("centre_std", 1.0), ("sigma", 1.0)),
         r_in=48, k=32, L=96, rounds=4, R=48, n_queries=10_000,
         precision="bf16", seed=1005),
+    # Same sizes with centres ~ N(0, 0.25 I): overlapping clusters, so that
+    # the input graphs are navigable from their medoid (quality supplement;
+    # the literal recipe's graphs are islands of one cluster each).
+    "cfg5ov": WorkloadConfig(
+        name="cfg5ov",
+        sizes=(2_500_000,) * 4 + _fresh_sizes(16, 10_000, 200_000, 3005),
+        dim=128, metric="l2", dist="gmm",
+        dist_params=(("clusters", 1024), ("centre_std", 0.5), ("sigma", 1.0)),
+        r_in=48, k=32, L=96, rounds=4, R=48, n_queries=10_000,
+        precision="bf16", seed=1015),
 }
 
 
