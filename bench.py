@@ -329,8 +329,12 @@ def measure(fg, cfg, forms, args, dev, peak_meas, with_parity, with_recall):
         t0 = time.time()
         Q = make_queries(cfg, args.queries)
         knodes = sample_nodes(X.shape[0], args.queries, 7)
-        _, kd, fb1 = exact_knn_screened(X, X[knodes], cfg.k, cfg.metric, exclude=knodes, Xdev=Xd)
-        _, qd, fb2 = exact_knn_screened(X, Q, 10, cfg.metric, Xdev=Xd)
+        def prog(what):
+            return lambda done, total: log(f"ground truth {cfg.name} {what}: {done}/{total}")
+        log(f"ground truth {cfg.name}: {len(knodes)} vertices and {Q.shape[0]} queries")
+        _, kd, fb1 = exact_knn_screened(X, X[knodes], cfg.k, cfg.metric, exclude=knodes, Xdev=Xd,
+                                        progress=prog("vertices"))
+        _, qd, fb2 = exact_knn_screened(X, Q, 10, cfg.metric, Xdev=Xd, progress=prog("queries"))
         gt = (Q, knodes, kd, qd)
         log(f"ground truth {cfg.name}: {time.time() - t0:.1f}s (fallbacks {fb1}, {fb2})")
     for form in forms:

@@ -2244,7 +2244,10 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     {
       std::lock_guard<std::mutex> lock(g_demand_mu);
       g_props_per_vertex = std::max(g_props_per_vertex, static_cast<double>(hh[1]) / static_cast<double>(N));
-      g_pairs_per_vertex = std::max(g_pairs_per_vertex, static_cast<double>(pairs_max) / static_cast<double>(N));
+      // the pair demand is the largest Update unit's, per vertex of a unit
+      const uint64_t parts = streamed ? p->stream_batches : chunks;
+      const double unit_n = static_cast<double>((N + parts - 1) / parts);
+      g_pairs_per_vertex = std::max(g_pairs_per_vertex, static_cast<double>(pairs_max) / unit_n);
     }
     if (hh[1] > cap || pairs_max > pair_cap) {
       // a buffer overflowed: run again with larger ones (same result)

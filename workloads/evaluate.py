@@ -14,6 +14,8 @@ evaluation arithmetic, not part of the merge.
 
 from __future__ import annotations
 
+import time
+
 import numpy as np
 import torch
 
@@ -74,7 +76,7 @@ def exact_knn_fp64(X: np.ndarray, Q: np.ndarray, k: int, metric: str = "l2",
 
 def exact_knn_screened(X: np.ndarray, Q: np.ndarray, k: int, metric: str = "l2",
                        exclude: np.ndarray | None = None, Xdev: torch.Tensor | None = None,
-                       block: int = 1024, margin: int = 48, widen: int = 16):
+                       block: int | None = None, margin: int = 48, widen: int = 16, progress=None):
     """exact_knn_fp64 with the shortlist screened in FP32 on the GPU (torch
     matmul: evaluation arithmetic, not the merge).  Every shortlist is
     re-ranked by the direct FP64 form on the CPU, and its completeness is
@@ -86,19 +88,27 @@ def exact_knn_screened(X: np.ndarray, Q: np.ndarray, k: int, metric: str = "l2",
     fail the test get a 16x longer shortlist, then the direct FP64 pass over
     every row.  Returns what exact_knn_fp64 returns, and the count of
     queries that needed each fallback.  margin and widen set the two shortlist
-    lengths, k + margin and widen (k + margin)."""
+    lengths, k + margin and widen (k + margin).  block (queries per GPU
+    pass) defaults to what keeps one distance block near 2^30 entries;
+    progress(done, total), if given, is called every ten seconds or so."""
     dev = Xdev.device if Xdev is not None else torch.device("cuda")
     Xg = Xdev if Xdev is not None else torch.from_numpy(np.ascontiguousarray(X)).to(dev)
     n, d = Xg.shape
     sqx = (Xg * Xg).sum(1)
-    sqmax = float((torch.from_numpy(np.ascontiguousarray(X)).to(torch.float64) ** 2).sum(1).max())
+    sqmax = max(float((Xg[c:c + (1 << 20)].to(torch.float64) ** 2).sum(1).max()) for c in range(0, n, 1 << 20))
     u = 2.0 ** -24
     gamma = d * u / (1.0 - d * u)
     nq = Q.shape[0]
+    if block is None:
+        block = max(32, min(1024, (1 << 30) // max(1, n)))
     ids = np.empty((nq, k), np.int64)
     dd = np.empty((nq, k), np.float64)
     fallback = [0, 0]
+    t_last = time.time()
     for s in range(0, nq, block):
+        if progress is not None and time.time() - t_last > 10.0:
+            progress(s, nq)
+            t_last = time.time()
         e = min(nq, s + block)
         Qg = torch.from_numpy(np.ascontiguousarray(Q[s:e])).to(dev)
         G = Qg @ Xg.T
