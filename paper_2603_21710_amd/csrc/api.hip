@@ -306,24 +306,11 @@ __global__ void __launch_bounds__(256) mips_norm_kernel(const float* X, uint64_t
       const uint32_t c = lane + i * P;
       if (i < M && lane < P && c < nc) {
         const float4 x = *reinterpret_cast<const float4*>(X + row * ld + 4ull * c);
-        s[i] = __builtin_fmaf(x.x, x.x, s[i]);
-        s[i] = __builtin_fmaf(x.y, x.y, s[i]);
-        s[i] = __builtin_fmaf(x.z, x.z, s[i]);
-        s[i] = __builtin_fmaf(x.w, x.w, s[i]);
+        s[i] = chunk_sum<kIP>(x, x);
       }
     }
-#pragma unroll
-    for (uint32_t st = 8; st >= 1; st /= 2) {
-      if (st < M) {
-#pragma unroll
-        for (uint32_t i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
-      }
-    }
-    float r = s[0];
-#pragma unroll
-    for (uint32_t st = 32; st >= 1; st /= 2)
-      if (st < P) r = r + __shfl_xor(r, static_cast<int>(st), 64);
-    r = r + 0.0f;
+    // the squared length is the L2 form's sum: no sign, -0 made +0
+    const float r = finish<kL2>(reduce_chunk_sums<16>(s, static_cast<int>(P), static_cast<int>(M)));
     if (lane == 0) out[row * ld_out + dim] = r;
     const uint32_t b = __float_as_uint(r);
     mx = b > mx ? b : mx;

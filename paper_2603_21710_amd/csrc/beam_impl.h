@@ -228,21 +228,7 @@ FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, cons
         const uint32_t ch = static_cast<uint32_t>(l + mi * P);
         if (mi < M && act && ch < a.nc) s[mi] = chunk_sum<L2 ? kL2 : kIP>(q[mi], Row::decode(rv[u][mi], sc[u]));
       }
-#pragma unroll
-      for (int st = MMAX / 2; st >= 1; st /= 2) {
-        if (2 * st <= M) {
-#pragma unroll
-          for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
-        }
-      }
-      float r = s[0];
-#pragma unroll
-      for (int st = 32; st >= 1; st /= 2)
-        if (st < P) r = r + shfl_xor_f(r, st);
-      float d;
-      if (a.metric == kL2) d = finish<kL2>(r);
-      else if (a.metric == kIP) d = finish<kIP>(r);
-      else d = finish<kCos>(r);
+      const float d = finish_metric(reduce_chunk_sums<MMAX>(s, P, M), a.metric);
       if (act && l == 0) lds.ckey[c] = make_key(d, key_off + rid[u]);
     }
   }

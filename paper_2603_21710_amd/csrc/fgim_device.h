@@ -132,6 +132,35 @@ FGIM_DEV float finish(float r) {
   return d + 0.0f;
 }
 
+FGIM_DEV float finish_metric(float r, int metric) {
+  if (metric == kL2) return finish<kL2>(r);
+  if (metric == kIP) return finish<kIP>(r);
+  return finish<kCos>(r);
+}
+
+// The canonical order's reduction inside a group of P lanes (P a power of
+// two): s[mi] holds the sum of the lane's chunk l + mi * P, or zero where the
+// lane holds none, for the first M (a power of two) of MMAX entries.  The
+// stride tree s[c] += s[c + st] over the zero-padded chunks runs in
+// registers for strides >= P (the lane's own entries) and as xor
+// butterflies for strides < P, so every lane of the group ends with the
+// same bits for any P.  Every distance of the library goes through here.
+template <int MMAX>
+FGIM_DEV float reduce_chunk_sums(float (&s)[MMAX], int P, int M) {
+#pragma unroll
+  for (int st = MMAX / 2; st >= 1; st /= 2) {
+    if (2 * st <= M) {
+#pragma unroll
+      for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
+    }
+  }
+  float r = s[0];
+#pragma unroll
+  for (int st = 32; st >= 1; st /= 2)
+    if (st < P) r = r + shfl_xor_f(r, st);
+  return r;
+}
+
 // ---------------------------------------------------------------------------
 // row formats
 

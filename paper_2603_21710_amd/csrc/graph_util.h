@@ -46,20 +46,7 @@ FGIM_DEV float chunks_distance(const float4 (&x)[MMAX], const float4 (&y)[MMAX],
     const uint32_t ch = static_cast<uint32_t>(l + mi * P);
     if (mi < M && act && ch < nc) s[mi] = metric == kL2 ? chunk_sum<kL2>(x[mi], y[mi]) : chunk_sum<kIP>(x[mi], y[mi]);
   }
-#pragma unroll
-  for (int st = MMAX / 2; st >= 1; st /= 2) {
-    if (2 * st <= M) {
-#pragma unroll
-      for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
-    }
-  }
-  float r = s[0];
-#pragma unroll
-  for (int st = 32; st >= 1; st /= 2)
-    if (st < P) r = r + shfl_xor_f(r, st);
-  if (metric == kL2) return finish<kL2>(r);
-  if (metric == kIP) return finish<kIP>(r);
-  return finish<kCos>(r);
+  return finish_metric(reduce_chunk_sums<MMAX>(s, P, M), metric);
 }
 
 // canonical distance between rows a and b (pointers to row starts), computed
@@ -73,36 +60,8 @@ FGIM_DEV float pair_distance(const float* a, const float* b, int metric, uint32_
   return chunks_distance<MMAX>(x, y, metric, nc, P, M, l, act);
 }
 
-// canonical distance of the P-lane group's row (chunks held in x) to row b
-template <int MMAX>
-FGIM_DEV float row_distance(const float4 (&x)[MMAX], const float* b, int metric, uint32_t nc, int P, int M, int l) {
-  float s[MMAX];
-#pragma unroll
-  for (int mi = 0; mi < MMAX; ++mi) {
-    s[mi] = 0.0f;
-    const uint32_t ch = static_cast<uint32_t>(l + mi * P);
-    if (mi < M && ch < nc) {
-      const float4 y = *reinterpret_cast<const float4*>(b + 4 * ch);
-      s[mi] = metric == kL2 ? chunk_sum<kL2>(x[mi], y) : chunk_sum<kIP>(x[mi], y);
-    }
-  }
-#pragma unroll
-  for (int st = MMAX / 2; st >= 1; st /= 2) {
-    if (2 * st <= M) {
-#pragma unroll
-      for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
-    }
-  }
-  float r = s[0];
-#pragma unroll
-  for (int st = 32; st >= 1; st /= 2)
-    if (st < P) r = r + shfl_xor_f(r, st);
-  if (metric == kL2) return finish<kL2>(r);
-  if (metric == kIP) return finish<kIP>(r);
-  return finish<kCos>(r);
-}
-
-// row_distance with loads predicated on `act`; call from wave-uniform code
+// canonical distance of the P-lane group's row (chunks held in x) to row
+// b, with the loads predicated on `act`; call from wave-uniform code
 template <int MMAX>
 FGIM_DEV float pair_distance_x(const float4 (&x)[MMAX], const float* b, int metric, uint32_t nc, int P, int M, int l,
                                bool act) {
@@ -116,20 +75,7 @@ FGIM_DEV float pair_distance_x(const float4 (&x)[MMAX], const float* b, int metr
       s[mi] = metric == kL2 ? chunk_sum<kL2>(x[mi], y) : chunk_sum<kIP>(x[mi], y);
     }
   }
-#pragma unroll
-  for (int st = MMAX / 2; st >= 1; st /= 2) {
-    if (2 * st <= M) {
-#pragma unroll
-      for (int i = 0; i < st; ++i) s[i] = s[i] + s[i + st];
-    }
-  }
-  float r = s[0];
-#pragma unroll
-  for (int st = 32; st >= 1; st /= 2)
-    if (st < P) r = r + shfl_xor_f(r, st);
-  if (metric == kL2) return finish<kL2>(r);
-  if (metric == kIP) return finish<kIP>(r);
-  return finish<kCos>(r);
+  return finish_metric(reduce_chunk_sums<MMAX>(s, P, M), metric);
 }
 
 template <int MMAX>
