@@ -184,11 +184,14 @@ FGIM_DEV void score_batch(const Row& rows, uint64_t goff, uint32_t key_off, cons
   // group batches in flight: one for FP32 rows (95 VGPRs, 20 resident waves
   // per CU: 9 % faster than two batches at 16 waves on 8 uneven sub-indexes
   // of 2 M rows, d = 96, within 1.3 % elsewhere), else as many as about 32
-  // registers of raw (BF16 / FP8) row data per lane hold, at most three:
-  // four take the kernel past 128 VGPRs, to 12 resident waves per CU, and
-  // measured 12-25 % slower on d = 96, 128 and 768 (eight slower still)
+  // registers of raw (BF16 / FP8) row data per lane hold, at most three for
+  // BF16 (four take the kernel past 128 VGPRs, to 12 resident waves per CU,
+  // and measured 12-25 % slower on d = 96, 128 and 768) and four for FP8
+  // (122 VGPRs: 3.7 % faster at d = 768, level at d = 96 and 128; five
+  // reach 130 VGPRs and are 20-28 % slower)
   constexpr int kRawRegs = static_cast<int>(sizeof(typename Row::Raw) / 4);
-  constexpr int kLowP = 32 / (MMAX * kRawRegs) < 3 ? 32 / (MMAX * kRawRegs) : 3;
+  constexpr int kRawCap = kRawRegs == 1 ? 4 : 3;
+  constexpr int kLowP = 32 / (MMAX * kRawRegs) < kRawCap ? 32 / (MMAX * kRawRegs) : kRawCap;
   constexpr int U0 = MMAX > 4 ? 1 : (kRawRegs == 4 ? 1 : kLowP);
   constexpr int U = U0 < UCAP ? U0 : UCAP;
   const int P = static_cast<int>(a.P);
@@ -291,7 +294,7 @@ FGIM_DEV void beam_search(Pool<NR>& pool, const Row& rows, uint64_t goff, const 
       // two raw batches, not three, beside a two-register pool: that keeps
       // the BF16 / FP8 instances at 124 VGPRs (16 resident waves per CU
       // instead of 12) and measured 18-19 % faster at L = 96 (d = 96, 128)
-      score_batch<L2, MMAX, (NR >= 2 ? 2 : 3)>(rows, goff, 0u, q, a, lds, m);
+      score_batch<L2, MMAX, (NR >= 2 ? 2 : 4)>(rows, goff, 0u, q, a, lds, m);
       __syncthreads();
       ndc += static_cast<unsigned long long>(m);
       const uint64_t ck = lane_id() < m ? lds.ckey[lane_id()] : kSentinel;

@@ -87,3 +87,23 @@ def test_merge_with_validity_matches_oracle(scenario):
     assert (_u32(pg) == oi).all() and (_u32(deg) == odeg).all()
     assert entry == oent and valid[entry] == 1
     assert (odeg[valid == 0] == 0).all() and valid[oi[oi != NONE]].all()
+
+
+@pytest.mark.parametrize("name,sizes,batches", [("cfg1ov", None, 5),
+                                                ("cfg3", (300, 500, 700, 150, 900, 400, 1200, 650), 3)])
+def test_streamlined_merge_with_deletions_matches_oracle(name, sizes, batches):
+    # validity, streamlined refinement and the prune together: the dropped
+    # vertices stay out of every list through the ranges as well
+    cfg, X, graphs, _ = workload(name, sizes)
+    valid = _mask(X.shape[0], 0.25, 11)
+    print(f"case {name} N={X.shape[0]} dropped={int((valid == 0).sum())} batches={batches}", flush=True)
+    m = to_gpu(X, graphs, cfg.metric, valid=valid)
+    p = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds, stream_batches=batches)
+    pg, deg, entry, _ = fg.merge(m, p, stats=True)
+    oi, odeg, oent = oracle.merge(X, graphs, cfg.k, cfg.L, cfg.rounds, cfg.R, cfg.metric, valid=valid,
+                                  batches=batches)
+    assert (_u32(pg) == oi).all()
+    assert (_u32(deg) == odeg).all()
+    assert entry == oent
+    gone = np.nonzero(valid == 0)[0]
+    assert (odeg[gone] == 0).all() and not np.isin(oi[oi != NONE], gone).any()
