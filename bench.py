@@ -250,11 +250,16 @@ def beam_roofline(fg, m, cfg, X, graphs, precision, st, beam_ms, peak_meas, coun
             "beam_sources_sha256": beam_source_hash()}
     # Algorithmic bytes count every row gather as an HBM read; rows re-read
     # by concurrent searches (the entry region of each graph above all) hit
-    # L2 and the memory-side cache, so `frac` can pass what HBM alone could
-    # serve.  `traffic` is the counted fabric traffic (an upper bound of HBM
-    # bytes), and its fraction of the measured read-stream peak is the
-    # physically bounded figure.
-    roof["cache_assisted"] = bool(traffic is not None and alg_bytes > traffic)
+    # L2, so `frac` can pass what HBM alone could serve: `cache_assisted`
+    # says the algorithmic bytes exceed the counted fabric traffic by more
+    # than 5 %.  `traffic` (FETCH_SIZE + WRITE_SIZE) still counts reads the
+    # memory-side cache serves, so it bounds HBM bytes from above;
+    # `traffic_exceeds_read_stream` says its rate passed the read stream
+    # measured in this run, which only the memory-side cache can explain.
+    roof["cache_assisted"] = bool(traffic is not None and alg_bytes > 1.05 * traffic)
+    roof["algorithmic_over_traffic"] = None if traffic is None else round(alg_bytes / traffic, 4)
+    roof["traffic_frac"] = None if traffic is None else round(traffic / kern_s / 1e9 / HBM_PEAK_GBS, 4)
+    roof["traffic_exceeds_read_stream"] = bool(traffic is not None and traffic / kern_s / 1e9 > peak_meas)
     return roof
 
 
