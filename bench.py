@@ -190,6 +190,110 @@ def refine_study(fg, cfg, batch_list, max_rounds, n_nodes, reps, dev):
     return out
 
 
+def _timed(fn, reps=3):
+    """(result of the last call, median seconds over reps after one untimed call)."""
+    out = fn()
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = fn()
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t0)
+    return out, float(np.median(ts))
+
+
+def rows_study(fg, cfg, n_queries, dev):
+    """The follow-on rows on one full-size workload: the selection rules
+    (alpha-RNG, tau-MNG; on inner-product data through the MIPS transform),
+    validity (a quarter of the vertices dropped), and HNSW-adaptive merging
+    (the upper layers and the layered search against the flat one), each
+    with its time and search recall@10 against FP64 truth."""
+    from workloads import make_queries
+    from workloads.evaluate import exact_knn_screened, tie_recall
+    X, graphs, _, _ = build_inputs(cfg, "cuda")
+    N = X.shape[0]
+    Xd = torch.from_numpy(X).to(dev)
+    gl = [(torch.from_numpy(a.view(np.int32)).to(dev), int(e)) for _, a, e in graphs]
+    Q = make_queries(cfg, n_queries)
+    Qd = torch.from_numpy(Q).to(dev)
+    _, qd, _ = exact_knn_screened(X, Q, 10, cfg.metric, Xdev=Xd)
+    out = {"workload": cfg.name, "N": N, "queries": n_queries}
+
+    def recall_of(pg, entry, Xs=Xd, Qs=Qd, metric=cfg.metric, kth=qd[:, -1], L=64):
+        found, _ = fg.search(Xs, pg, entry, Qs, L, 10, metric)
+        return round(tie_recall(X, Q, fg.as_uint32(found), kth, 10, cfg.metric), 5)
+
+    base = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds)
+    m = fg.Merge(Xd, gl, cfg.metric)
+    (pg, deg, entry, st), t = _timed(lambda: fg.merge(m, base, stats=True), 2)
+    out["rng"] = {"merge_ms": round(t * 1e3, 2), "stage3_ms": round(st["ms_stage"][2], 3),
+                  "mean_degree": round(float(deg.float().mean()), 3), "recall@10_L64": recall_of(pg, entry)}
+    log(f"{cfg.name} rng: {out['rng']}")
+
+    # selection rules: metric ones, so inner-product data goes through MIPS
+    if cfg.metric == "ip":
+        (Xt, Mx), t = _timed(lambda: fg.mips_to_l2(Xd), 5)
+        d = X.shape[1]
+        # read every row once, write every transformed row once, and the
+        # squared length parked and read back (8 B a row)
+        moved = N * d * 4 + N * (d + 4) * 4 + N * 8
+        out["mips_to_l2"] = {"ms": round(t * 1e3, 3), "bytes": moved, "GB/s": round(moved / t / 1e9, 1),
+                             "frac_of_8TB/s": round(moved / t / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"{cfg.name} mips: {out['mips_to_l2']}")
+        Xs = Xt.contiguous()
+        Qs = torch.nn.functional.pad(Qd, (0, 4))
+        rmetric = "l2"
+    else:
+        Xs, Qs, rmetric = Xd, Qd, cfg.metric
+    mr = fg.Merge(Xs, gl, rmetric)
+    first = fg.merge(mr, base)[0]
+    tau = 0.1 * float(np.median(np.sqrt(np.maximum(
+        ((Xs[:2000] - Xs[first[:2000, 0].long().clamp_min(0)]) ** 2).sum(1).cpu().numpy(), 0.0))))
+    for rule, param in (("rng", 0.0), ("alpha", 1.2), ("tau", tau)):
+        p = fg.params(k=cfg.k, L=cfg.L, R=cfg.R, rounds=cfg.rounds, select_rule=rule, select_param=param)
+        (pg, deg, entry, st), t = _timed(lambda: fg.merge(mr, p, stats=True), 2)
+        out.setdefault("rules", {})[rule] = {
+            "param": round(param, 6), "metric": rmetric, "merge_ms": round(t * 1e3, 2),
+            "stage3_ms": round(st["ms_stage"][2], 3), "mean_degree": round(float(deg.float().mean()), 3),
+            "recall@10_L64": recall_of(pg, entry, Xs, Qs, rmetric)}
+        log(f"{cfg.name} {rule}: {out['rules'][rule]}")
+
+    # validity: a quarter of the vertices dropped (seeded)
+    rng = np.random.default_rng(4242)
+    valid = (rng.random(N) >= 0.25).astype(np.uint8)
+    keep = np.nonzero(valid)[0]
+    _, vqd, _ = exact_knn_screened(X[keep], Q, 10, cfg.metric)
+    mv = fg.Merge(Xd, gl, cfg.metric, valid=torch.from_numpy(valid).to(dev))
+    (pg, deg, entry, st), t = _timed(lambda: fg.merge(mv, base, stats=True), 2)
+    found, _ = fg.search(Xd, pg, entry, Qd, 64, 10, cfg.metric)
+    fnd = fg.as_uint32(found)
+    out["validity"] = {"dropped": int(N - keep.size), "merge_ms": round(t * 1e3, 2),
+                       "stages_ms": [round(x, 3) for x in st["ms_stage"]],
+                       "recall@10_L64": round(tie_recall(X, Q, fnd, vqd[:, -1], 10, cfg.metric), 5),
+                       "dropped_in_results": int(np.isin(fnd[fnd != 0xFFFFFFFF], np.nonzero(valid == 0)[0]).sum())}
+    log(f"{cfg.name} validity: {out['validity']}")
+
+    # HNSW-adaptive: levels drawn as HNSW draws them (mL = 1 / ln M), M = R
+    M = cfg.R
+    lv = np.minimum(np.floor(-np.log(np.random.default_rng(77).random(N)) / np.log(M)), 8).astype(np.uint8)
+    lvd = torch.from_numpy(lv).to(dev)
+    layers, t = _timed(lambda: fg.hnsw_layers(Xd, lvd, M, 64, cfg.metric), 2)
+    out["hnsw"] = {"M": M, "ef": 64, "layers": len(layers[2]), "members": layers[2], "build_ms": round(t * 1e3, 2),
+                   "search": {}}
+    pg, deg, entry, _ = fg.merge(m, base)
+    for L in (16, 32, 64):
+        (fl, _), tl = _timed(lambda: fg.search_layers(Xd, pg, layers, M, Qd, L, 10, cfg.metric), 3)
+        (ff, _), tf = _timed(lambda: fg.search(Xd, pg, entry, Qd, L, 10, cfg.metric), 3)
+        out["hnsw"]["search"][str(L)] = {
+            "layered": {"queries/s": round(n_queries / tl, 1),
+                        "recall@10": round(tie_recall(X, Q, fg.as_uint32(fl), qd[:, -1], 10, cfg.metric), 5)},
+            "flat": {"queries/s": round(n_queries / tf, 1),
+                     "recall@10": round(tie_recall(X, Q, fg.as_uint32(ff), qd[:, -1], 10, cfg.metric), 5)}}
+        log(f"{cfg.name} hnsw L={L}: {out['hnsw']['search'][str(L)]}")
+    return out
+
+
 def build_inputs(cfg, device):
     from workloads import build_input_pg, make_vectors, reach_fraction, split_sizes
     t0 = time.time()
@@ -505,6 +609,10 @@ def main():
     ap.add_argument("--study-batches", default="1,4,16,64")
     ap.add_argument("--study-rounds", type=int, default=6)
     ap.add_argument("--study-nodes", type=int, default=5000)
+    ap.add_argument("--rows-study", default="",
+                    help="comma-separated workloads: time the selection rules, MIPS transform, validity "
+                         "and HNSW layers instead of the merge benchmark")
+    ap.add_argument("--study-queries", type=int, default=10000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); "
@@ -520,6 +628,12 @@ def main():
         sys.exit(2)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.rows_study:
+        res = {"study": "follow-on rows", "results": []}
+        for name in args.rows_study.split(","):
+            res["results"].append(rows_study(fg, get_config(name), args.study_queries, dev))
+        print(json.dumps(res), flush=True)
+        return
     if args.refine_study:
         batches = [int(b) for b in args.study_batches.split(",") if b]
         res = {"study": "refinement schedule", "unit": "vectors/s", "steps": args.steps, "results": []}

@@ -285,56 +285,75 @@ __global__ void __launch_bounds__(256) quantize_fp8_kernel(const float* X, uint6
   }
 }
 
-// MIPS -> L2, first pass, one wavefront per row: n(x) = the canonical FP32
-// squared length (chunks of 4 summed with fused multiply-adds from +0,
-// padded to Np chunks and added by the stride tree; lane l owns chunks
-// l, l + P, ...), parked in the row's extra output slot and folded into the
-// maximum (non-negative floats order like their bit patterns).
+// MIPS -> L2, first pass: n(x) = the canonical FP32 squared length (chunks of
+// 4 summed with fused multiply-adds from +0, padded to Np chunks and added by
+// the stride tree), parked in the row's extra output slot and folded into the
+// maximum (non-negative floats order like their bit patterns); the row's
+// own chunks are copied to the output on the way.  A group of P = min(Np,
+// 64) lanes takes a row (lane l owns chunks l, l + P, ...), a wavefront
+// 64 / P rows at a time, and U such steps are loaded before any is reduced,
+// so their latencies overlap.
+template <int MMAX, int U>
 __global__ void __launch_bounds__(256) mips_norm_kernel(const float* X, uint64_t n, uint32_t nc, uint32_t Np,
                                                         uint64_t ld, float* out, uint64_t ld_out, uint32_t dim,
                                                         uint32_t* max_bits) {
-  const uint32_t wave = threadIdx.x / 64;
   const uint32_t lane = static_cast<uint32_t>(lane_id());
   const uint32_t P = Np < 64 ? Np : 64;
-  const uint32_t M = Np / P;  // <= 16 for dim <= 4096
+  const uint32_t M = Np / P;  // <= MMAX
+  const uint32_t G = 64 / P;
+  const uint32_t g = lane / P, l = lane % P;
+  const uint64_t waves = gridDim.x * 4ull;
+  const uint64_t w = uniform(blockIdx.x * 4u + threadIdx.x / 64u);
   uint32_t mx = 0;
-  for (uint64_t row = blockIdx.x * 4ull + wave; row < n; row += gridDim.x * 4ull) {
-    float s[16];
+  for (uint64_t base = w * G * U; base < n; base += waves * G * U) {
+    float4 x[U][MMAX];
 #pragma unroll
-    for (uint32_t i = 0; i < 16; ++i) {
-      s[i] = 0.0f;
-      const uint32_t c = lane + i * P;
-      if (i < M && lane < P && c < nc) {
-        const float4 x = *reinterpret_cast<const float4*>(X + row * ld + 4ull * c);
-        s[i] = chunk_sum<kIP>(x, x);
+    for (int u = 0; u < U; ++u) {
+      const uint64_t row = base + static_cast<uint64_t>(u) * G + g;
+#pragma unroll
+      for (int mi = 0; mi < MMAX; ++mi) {
+        const uint32_t c = l + mi * P;
+        x[u][mi] = row < n && static_cast<uint32_t>(mi) < M && c < nc
+                       ? *reinterpret_cast<const float4*>(X + row * ld + 4ull * c)
+                       : make_float4(0.f, 0.f, 0.f, 0.f);
       }
     }
-    // the squared length is the L2 form's sum: no sign, -0 made +0
-    const float r = finish<kL2>(reduce_chunk_sums<16>(s, static_cast<int>(P), static_cast<int>(M)));
-    if (lane == 0) out[row * ld_out + dim] = r;
-    const uint32_t b = __float_as_uint(r);
-    mx = b > mx ? b : mx;
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint64_t row = base + static_cast<uint64_t>(u) * G + g;
+#pragma unroll
+      for (int mi = 0; mi < MMAX; ++mi) {
+        const uint32_t c = l + mi * P;
+        if (row < n && static_cast<uint32_t>(mi) < M && c < nc)
+          *reinterpret_cast<float4*>(out + row * ld_out + 4ull * c) = x[u][mi];
+      }
+      float s[MMAX];
+#pragma unroll
+      for (int mi = 0; mi < MMAX; ++mi) s[mi] = chunk_sum<kIP>(x[u][mi], x[u][mi]);
+      // the squared length is the L2 form's sum: no sign, -0 made +0
+      const float r = finish<kL2>(reduce_chunk_sums<MMAX>(s, static_cast<int>(P), static_cast<int>(M)));
+      if (row < n && l == 0) {
+        out[row * ld_out + dim] = r;
+        const uint32_t b = __float_as_uint(r);
+        mx = b > mx ? b : mx;
+      }
+    }
+  }
+  for (int o = 32; o >= 1; o >>= 1) {
+    const uint32_t t = static_cast<uint32_t>(__shfl_xor(static_cast<int>(mx), o, 64));
+    mx = t > mx ? t : mx;
   }
   if (lane == 0) atomicMax(max_bits, mx);
 }
 
-// second pass: x' = (x, sqrt(M - n(x)), 0, 0, 0), one float4 per thread step
-__global__ void __launch_bounds__(256) mips_write_kernel(const float* X, uint64_t n, uint32_t dim, uint64_t ld,
-                                                         float* out, uint64_t ld_out, const float* max_norm2) {
-  const uint32_t per_row = dim / 4 + 1;
+// second pass: the last chunk of each row, (sqrt(M - n(x)), 0, 0, 0)
+__global__ void __launch_bounds__(256) mips_write_kernel(uint64_t n, uint32_t dim, float* out, uint64_t ld_out,
+                                                         const float* max_norm2) {
   const float Mx = *max_norm2;
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < n * per_row;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t row = i / per_row;
-    const uint32_t c = static_cast<uint32_t>(i - row * per_row);
-    float4 v;
-    if (c < dim / 4) {
-      v = *reinterpret_cast<const float4*>(X + row * ld + 4ull * c);
-    } else {
-      const float n2 = out[row * ld_out + dim];
-      v = make_float4(__builtin_sqrtf(Mx - n2), 0.0f, 0.0f, 0.0f);
-    }
-    *reinterpret_cast<float4*>(out + row * ld_out + 4ull * c) = v;
+  for (uint64_t row = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; row < n;
+       row += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
+    float* t = out + row * ld_out + dim;
+    *reinterpret_cast<float4*>(t) = make_float4(__builtin_sqrtf(Mx - t[0]), 0.0f, 0.0f, 0.0f);
   }
 }
 
@@ -763,13 +782,21 @@ fgim_status fgim_mips_to_l2(const float* base, uint64_t n, uint32_t dim, uint64_
   hipStream_t s = static_cast<hipStream_t>(stream);
   const uint32_t nc = dim / 4;
   HIP_TRY(fill_u32(reinterpret_cast<uint32_t*>(max_norm2), 0u, 1, s));
-  const uint32_t blocks = static_cast<uint32_t>(std::min<uint64_t>((n + 3) / 4, 65536));
-  hipLaunchKernelGGL(mips_norm_kernel, dim3(blocks), dim3(256), 0, s, base, n, nc, ceil_pow2(nc), ld, out, ld_out,
-                     dim, reinterpret_cast<uint32_t*>(max_norm2));
+  const uint32_t Np = ceil_pow2(nc);
+  const uint32_t M = Np <= 64 ? 1u : Np / 64;
+  const dim3 grid(static_cast<uint32_t>(std::min<uint64_t>((n + 3) / 4, static_cast<uint64_t>(device_cus()) * 8)));
+  uint32_t* mb = reinterpret_cast<uint32_t*>(max_norm2);
+  if (M == 1)
+    hipLaunchKernelGGL((mips_norm_kernel<1, 4>), grid, dim3(256), 0, s, base, n, nc, Np, ld, out, ld_out, dim, mb);
+  else if (M == 2)
+    hipLaunchKernelGGL((mips_norm_kernel<2, 2>), grid, dim3(256), 0, s, base, n, nc, Np, ld, out, ld_out, dim, mb);
+  else if (M == 4)
+    hipLaunchKernelGGL((mips_norm_kernel<4, 1>), grid, dim3(256), 0, s, base, n, nc, Np, ld, out, ld_out, dim, mb);
+  else
+    hipLaunchKernelGGL((mips_norm_kernel<16, 1>), grid, dim3(256), 0, s, base, n, nc, Np, ld, out, ld_out, dim, mb);
   HIP_TRY(hipGetLastError());
-  const uint64_t items = n * (dim / 4 + 1);
-  hipLaunchKernelGGL(mips_write_kernel, dim3(static_cast<uint32_t>(std::min<uint64_t>((items + 255) / 256, 65536))),
-                     dim3(256), 0, s, base, n, dim, ld, out, ld_out, max_norm2);
+  hipLaunchKernelGGL(mips_write_kernel, dim3(static_cast<uint32_t>(std::min<uint64_t>((n + 255) / 256, 65536))),
+                     dim3(256), 0, s, n, dim, out, ld_out, max_norm2);
   HIP_TRY(hipGetLastError());
   return FGIM_OK;
 }

@@ -1161,10 +1161,13 @@ __global__ void indegree_kernel(const uint64_t* keys, uint64_t nk, uint32_t* T) 
   }
 }
 
-__global__ void zero_mask_kernel(const uint32_t* T, uint64_t N, uint32_t* mask) {
+// zero-indegree vertices with a neighbour to try: a vertex whose own list is
+// empty (a dropped one, or one no search reached) has no candidate, so its
+// step could change nothing and is left out of the batches
+__global__ void zero_mask_kernel(const uint32_t* T, const uint64_t* keys, uint32_t k, uint64_t N, uint32_t* mask) {
   for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < N;
        i += static_cast<uint64_t>(gridDim.x) * blockDim.x)
-    mask[i] = T[i] == 0u ? 1u : 0u;
+    mask[i] = T[i] == 0u && keys[i * k] != kSentinel ? 1u : 0u;
 }
 
 // list of the zero-indegree vertices in ascending id, with the first key of
@@ -1828,7 +1831,7 @@ hipError_t launch_indegree(const RefineBufs& b, uint64_t N, uint32_t k, hipStrea
 // current, with b.newc when set); repaired count added to b.hdr[2]
 hipError_t launch_repair(const RefineBufs& b, uint64_t N, uint32_t k, hipStream_t s) {
   hipError_t e;
-  hipLaunchKernelGGL(zero_mask_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, N, b.zmask);
+  hipLaunchKernelGGL(zero_mask_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, b.keys, k, N, b.zmask);
   if ((e = exclusive_scan(b.zmask, b.zoff, N, b.scan_tmp, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(zero_compact_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.zmask, b.zoff, N, b.keys, k, b.zero,
                      b.zkey);

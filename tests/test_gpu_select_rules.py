@@ -98,3 +98,16 @@ def test_mips_to_l2_matches_oracle_and_merges_under_l2():
     ri, rd, _, rT, _ = oracle.refine(Xl, graphs, oi, od, cfg.rounds, "l2")
     pi, _, pdeg = oracle.prune(Xl, ri, rd, rT, cfg.R, "l2", rule="alpha", param=1.2)
     assert (_u32(pg) == pi).all() and (_u32(deg) == pdeg).all()
+
+
+@pytest.mark.parametrize("n,d", [(100_003, 96), (20_001, 300), (9_999, 768), (1_003, 4096), (7, 8)])
+def test_mips_to_l2_every_row_shape(n, d):
+    # one chunk per lane (d <= 256) and 2, 4 and 16 per lane (d = 300, 768,
+    # 4096), with row counts that leave the last step of row groups partial
+    rng = np.random.default_rng(d)
+    X = (rng.normal(size=(n, d)) * np.exp(rng.uniform(-3, 3, (n, 1)))).astype(np.float32)
+    print(f"case n={n} d={d}", flush=True)
+    Xt, M = fg.mips_to_l2(torch.from_numpy(X).cuda())
+    ot, oM = oracle.mips_to_l2(X)
+    assert float(M.item()) == oM
+    assert (Xt.cpu().numpy().view(np.uint32) == ot.view(np.uint32)).all()
