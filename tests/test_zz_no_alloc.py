@@ -13,13 +13,16 @@ pytestmark = pytest.mark.gpu
 fg = pytest.importorskip("paper_2603_21710_amd")
 
 
-def _both(name, sizes, precision="fp32"):
+def _both(name, sizes, precision="fp32", drop=0.0):
     cfg, X, graphs, _ = workload(name, sizes)
     lowp = lows = None
     if precision != "fp32":
         Xd = torch.from_numpy(X).cuda()
         lowp, lows = fg.quantize(Xd, precision)
-    m = to_gpu(X, graphs, cfg.metric, lowp, lows)
+    valid = None
+    if drop:
+        valid = (np.random.default_rng(3).random(X.shape[0]) >= drop).astype(np.uint8)
+    m = to_gpu(X, graphs, cfg.metric, lowp, lows, valid=valid)
     p = fg.params(k=cfg.k, L=cfg.L, precision=precision)
     ref_ids, ref_d, _ = fg.cross_query(m, p)
     ids = torch.full_like(ref_ids, 7)
@@ -39,6 +42,15 @@ def _both(name, sizes, precision="fp32"):
 def test_noalloc_matches_cross_query_twice(first, second, precision):
     for name, sizes in (first, second):
         ref_ids, ref_d, ids, dist = _both(name, sizes, precision)
+        assert torch.equal(ids, ref_ids), f"{name} {sizes}: ids differ"
+        assert torch.equal(dist.view(torch.int32), ref_d.view(torch.int32)), f"{name} {sizes}: distances differ"
+
+
+def test_noalloc_with_validity_matches_cross_query_twice():
+    # dropped vertices (the ID mapping's validity flags) on the first call,
+    # none on the second, smaller one
+    for (name, sizes), drop in ((("cfg2", (2500, 2000)), 0.3), (("cfg1", (600, 400)), 0.0)):
+        ref_ids, ref_d, ids, dist = _both(name, sizes, drop=drop)
         assert torch.equal(ids, ref_ids), f"{name} {sizes}: ids differ"
         assert torch.equal(dist.view(torch.int32), ref_d.view(torch.int32)), f"{name} {sizes}: distances differ"
 
