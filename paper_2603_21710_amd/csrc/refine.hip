@@ -10,9 +10,10 @@
 // the demand seen in earlier calls; a round that needs more is detected at
 // the end (64-bit demand counters) and the rounds run again with larger
 // buffers.
-//   Visit   reverse-list sizes from the maintained counts, scan, rev_scatter:
-//           reverse lists of new and old entries as a CSR (segment 2v: u
-//           with v new in u's list, 2v+1: old)
+//   Visit   active vertices from the maintained counts; reverse lists of
+//           new and old entries as a CSR (segment 2v: u with v new in u's
+//           list, 2v+1: old), grouped without global atomics
+//           (group_records)
 //   Update  Cn(u) = fwd_new U rev_new and Co(u) = (fwd_old U rev_old) \ Cn,
 //           reverse lists cut to their k_rev best by (delta, u); every
 //           cross-sub-index pair of Cn^2 U Cn x Co proposes each end to the
@@ -23,7 +24,7 @@
 //           without a new candidate has no pair and stages no row); otherwise
 //           join_kernel scores every pair in FP32 from rows staged in LDS.
 //           Proposals are appended to a global buffer and grouped by target
-//           with a CSR pass.
+//           (group_records).
 //   apply   per target: first k of the snapshot list (entries turn old) and
 //           its proposals (entries new), one entry per id.
 //   repair  ordered list of zero-indegree vertices, then Algorithm 4 in one
@@ -127,6 +128,212 @@ hipError_t exclusive_scan(const uint32_t* in, uint32_t* out, uint64_t n, uint32_
 }
 
 // ---------------------------------------------------------------------------
+// Records (segment, value) grouped by segment into a CSR, with atomics in
+// LDS only.  Segments fall into coarse buckets of 2^shift consecutive
+// segments.  (1) Each of G workgroups takes one contiguous share of the
+// records and counts its records per bucket; the counts form a bucket-major
+// matrix.  (2) An exclusive scan of the matrix gives every (bucket,
+// workgroup) pair its run of the output, and the runs of one bucket are
+// contiguous.  (3) Each workgroup moves its records into its runs.  (4) One
+// workgroup per bucket counts its records per segment, scans the counts,
+// writes the segments' offsets and places every record in its segment.
+// The order of the records within a segment is not fixed; every reader of
+// these segments selects from them under the total order of keys.
+
+constexpr uint32_t kBucketMax = 2048;     // coarse buckets
+constexpr uint32_t kBucketWindow = 8192;  // segments a placing workgroup counts at a time
+constexpr uint32_t kBucketThreads = 512;
+constexpr int kBucketUnroll = 4;          // records per thread in flight
+
+struct BucketPlan {
+  uint64_t nseg;
+  uint32_t shift;  // bucket of segment s: s >> shift
+  uint32_t C;      // buckets
+  uint32_t G;      // workgroups of the count and move passes
+  uint64_t words() const { return static_cast<uint64_t>(C) * G; }
+};
+
+BucketPlan bucket_plan(uint64_t nseg, uint64_t max_records) {
+  BucketPlan p{};
+  p.nseg = nseg;
+  while (((nseg + (1ull << p.shift) - 1) >> p.shift) > kBucketMax) ++p.shift;
+  p.C = static_cast<uint32_t>(std::max<uint64_t>((nseg + (1ull << p.shift) - 1) >> p.shift, 1));
+  const uint64_t g = (max_records + 16383) / 16384;
+  p.G = static_cast<uint32_t>(std::min<uint64_t>(std::max<uint64_t>(g, 1), 4ull * device_cus()));
+  return p;
+}
+
+// proposals: record i = (target ptgt[i], key pkey[i]) for i < min(*total, cap)
+struct PropRecords {
+  const uint32_t* tgt;
+  const uint64_t* key;
+  const uint32_t* total;
+  uint32_t cap;
+  FGIM_DEV uint64_t count() const { return min(*total, cap); }
+  FGIM_DEV bool seg_of(uint64_t i, uint32_t& seg) const {
+    seg = tgt[i];
+    return true;
+  }
+  FGIM_DEV uint64_t value(uint64_t i) const { return key[i]; }
+};
+
+// reverse entries of a synchronous Visit: list entry i, u -> t with u = i / k,
+// gives the record (2t if the entry is new, else 2t + 1; key (stored delta,
+// u)).  Old entries of an inactive target give none: no join reads them.
+struct RevRecords {
+  const uint64_t* keys;
+  const uint32_t* flags;
+  const uint32_t* active;
+  uint64_t nk;
+  uint32_t k;
+  FGIM_DEV uint64_t count() const { return nk; }
+  FGIM_DEV bool seg_of(uint64_t i, uint32_t& seg) const {
+    const uint64_t kk = keys[i];
+    if (kk == kSentinel) return false;
+    const uint32_t t = key_id(kk);
+    const bool isnew = flags[i] & kFlagNew;
+    if (!isnew && !active[t]) return false;
+    seg = 2u * t + (isnew ? 0u : 1u);
+    return true;
+  }
+  FGIM_DEV uint64_t value(uint64_t i) const {
+    return (keys[i] & 0xFFFFFFFF00000000ull) | (static_cast<uint32_t>(i) / k);  // nk < 2^32
+  }
+};
+
+// pass (1): mat[b G + g] = records of workgroup g's share in bucket b
+template <class Src>
+__global__ void __launch_bounds__(kBucketThreads) bucket_count_kernel(Src src, uint32_t shift, uint32_t C,
+                                                                      uint32_t* mat) {
+  __shared__ uint32_t hist[kBucketMax];
+  for (uint32_t b = threadIdx.x; b < C; b += kBucketThreads) hist[b] = 0u;
+  __syncthreads();
+  const uint64_t n = src.count(), G = gridDim.x;
+  const uint64_t lo = n * blockIdx.x / G, hi = n * (blockIdx.x + 1) / G;
+  for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kBucketUnroll * kBucketThreads) {
+    uint32_t seg[kBucketUnroll];
+    bool ok[kBucketUnroll];
+#pragma unroll
+    for (int u = 0; u < kBucketUnroll; ++u) {
+      const uint64_t i = i0 + static_cast<uint64_t>(u) * kBucketThreads;
+      ok[u] = i < hi && src.seg_of(i, seg[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kBucketUnroll; ++u)
+      if (ok[u]) atomicAdd(&hist[seg[u] >> shift], 1u);
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < C; b += kBucketThreads) mat[static_cast<uint64_t>(b) * G + blockIdx.x] = hist[b];
+}
+
+// pass (3): the share's records into their runs (moff: the scanned matrix)
+template <class Src>
+__global__ void __launch_bounds__(kBucketThreads) bucket_move_kernel(Src src, uint32_t shift, uint32_t C,
+                                                                     const uint32_t* moff, uint32_t* cseg,
+                                                                     uint64_t* cval) {
+  __shared__ uint32_t cur[kBucketMax];
+  const uint64_t n = src.count(), G = gridDim.x;
+  for (uint32_t b = threadIdx.x; b < C; b += kBucketThreads) cur[b] = moff[static_cast<uint64_t>(b) * G + blockIdx.x];
+  __syncthreads();
+  const uint64_t lo = n * blockIdx.x / G, hi = n * (blockIdx.x + 1) / G;
+  for (uint64_t i0 = lo + threadIdx.x; i0 < hi; i0 += kBucketUnroll * kBucketThreads) {
+    uint32_t seg[kBucketUnroll];
+    bool ok[kBucketUnroll];
+    uint64_t val[kBucketUnroll];
+#pragma unroll
+    for (int u = 0; u < kBucketUnroll; ++u) {
+      const uint64_t i = i0 + static_cast<uint64_t>(u) * kBucketThreads;
+      ok[u] = i < hi && src.seg_of(i, seg[u]);
+      val[u] = ok[u] ? src.value(i) : 0ull;
+    }
+#pragma unroll
+    for (int u = 0; u < kBucketUnroll; ++u) {
+      if (!ok[u]) continue;
+      const uint32_t pos = atomicAdd(&cur[seg[u] >> shift], 1u);
+      cseg[pos] = seg[u];
+      cval[pos] = val[u];
+    }
+  }
+}
+
+// pass (4): bucket b's records lie in [moff[b G], moff[(b + 1) G]) (the
+// scan's total closes the last bucket); they are counted per segment a
+// window of segments at a time, and placed.  off[nseg] = the total.
+__global__ void __launch_bounds__(kBucketThreads) bucket_place_kernel(const uint32_t* moff, uint32_t G, uint32_t shift,
+                                                                      uint32_t C, uint64_t nseg, const uint32_t* cseg,
+                                                                      const uint64_t* cval, uint32_t* off,
+                                                                      uint64_t* out) {
+  __shared__ uint32_t cnt[kBucketWindow];
+  __shared__ uint32_t wsum[kBucketThreads / 64];
+  const uint32_t b = blockIdx.x;
+  const uint32_t r0 = uniform(moff[static_cast<uint64_t>(b) * G]);
+  const uint32_t r1 = uniform(moff[static_cast<uint64_t>(b + 1) * G]);
+  const uint64_t s0 = static_cast<uint64_t>(b) << shift;
+  const uint64_t s_end = static_cast<uint64_t>(b + 1) << shift;
+  const uint64_t s1 = s_end < nseg ? s_end : nseg;
+  const uint32_t wid = threadIdx.x / 64, lane = lane_id();
+  uint32_t base = r0;
+  for (uint64_t w0 = s0; w0 < s1; w0 += kBucketWindow) {
+    const uint32_t wn = static_cast<uint32_t>(s1 - w0 < kBucketWindow ? s1 - w0 : kBucketWindow);
+    for (uint32_t i = threadIdx.x; i < wn; i += kBucketThreads) cnt[i] = 0u;
+    __syncthreads();
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kBucketThreads) {
+      const uint64_t sg = cseg[r];
+      if (sg >= w0 && sg < w0 + wn) atomicAdd(&cnt[sg - w0], 1u);
+    }
+    __syncthreads();
+    // exclusive scan of the window's counts, kBucketThreads at a time
+    uint32_t carry = base;
+    for (uint32_t c0 = 0; c0 < wn; c0 += kBucketThreads) {
+      const uint32_t i = c0 + threadIdx.x;
+      const uint32_t v = i < wn ? cnt[i] : 0u;
+      uint32_t x = v;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const uint32_t y = __shfl_up(x, d, 64);
+        if (lane >= static_cast<uint32_t>(d)) x += y;
+      }
+      if (lane == 63) wsum[wid] = x;
+      __syncthreads();
+      uint32_t before = carry, total = 0;
+#pragma unroll
+      for (uint32_t w = 0; w < kBucketThreads / 64; ++w) {
+        before += w < wid ? wsum[w] : 0u;
+        total += wsum[w];
+      }
+      if (i < wn) {
+        cnt[i] = before + x - v;
+        off[w0 + i] = before + x - v;
+      }
+      carry += total;
+      __syncthreads();
+    }
+    for (uint32_t r = r0 + threadIdx.x; r < r1; r += kBucketThreads) {
+      const uint64_t sg = cseg[r];
+      if (sg >= w0 && sg < w0 + wn) out[atomicAdd(&cnt[sg - w0], 1u)] = cval[r];
+    }
+    __syncthreads();
+    base = carry;
+  }
+  if (b == C - 1 && threadIdx.x == 0) off[nseg] = r1;
+}
+
+// the CSR (off: nseg + 1, out) of the records of src; mat and moff hold
+// plan.words() and plan.words() + 1 words, cseg and cval one slot per record
+template <class Src>
+hipError_t group_records(const Src& src, const BucketPlan& plan, uint32_t* mat, uint32_t* moff, uint32_t* scan_tmp,
+                         uint32_t* cseg, uint64_t* cval, uint32_t* off, uint64_t* out, hipStream_t s) {
+  hipError_t e;
+  hipLaunchKernelGGL(bucket_count_kernel<Src>, dim3(plan.G), dim3(kBucketThreads), 0, s, src, plan.shift, plan.C, mat);
+  if ((e = exclusive_scan(mat, moff, plan.words(), scan_tmp, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(bucket_move_kernel<Src>, dim3(plan.G), dim3(kBucketThreads), 0, s, src, plan.shift, plan.C, moff,
+                     cseg, cval);
+  hipLaunchKernelGGL(bucket_place_kernel, dim3(plan.C), dim3(kBucketThreads), 0, s, moff, plan.G, plan.shift, plan.C,
+                     plan.nseg, cseg, cval, off, out);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // list conversion
 
 __global__ void to_keys_kernel(const uint32_t* ids, const float* dist, uint64_t nk, uint64_t* keys,
@@ -156,24 +363,6 @@ __global__ void copy_u32_kernel(const uint32_t* a, uint32_t* b, uint64_t n) {
 
 // ---------------------------------------------------------------------------
 // Visit: reverse lists
-
-// reverse entry of v in u's list: key (stored delta, u)
-// old entries of an inactive vertex's reverse list are not placed: no
-// join reads them (see rev_sizes_kernel)
-__global__ void rev_scatter_kernel(const uint64_t* keys, const uint32_t* flags, uint64_t nk, uint32_t k,
-                                   const uint32_t* active, uint32_t* cur, uint64_t* rev) {
-  for (uint64_t i = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; i < nk;
-       i += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint64_t kk = keys[i];
-    if (kk == kSentinel) continue;
-    const uint32_t t = key_id(kk);
-    const bool isnew = flags[i] & kFlagNew;
-    if (!isnew && !active[t]) continue;
-    const uint32_t seg = 2u * t + (isnew ? 0u : 1u);
-    const uint32_t pos = atomicAdd(&cur[seg], 1u);
-    rev[pos] = (kk & 0xFFFFFFFF00000000ull) | static_cast<uint32_t>(i / k);
-  }
-}
 
 // Visit of a streamlined range [lo, hi).  An entry (o -> t) is a new
 // reverse link of t when an earlier Visit of o recorded it and t has not
@@ -971,20 +1160,7 @@ __global__ void __launch_bounds__(256) recheck_kernel(JoinArgs a) {
 }
 
 // ---------------------------------------------------------------------------
-// proposals grouped by target, then applied
-
-__global__ void prop_count_kernel(const uint32_t* ptgt, const uint32_t* ptotal, uint32_t cap, uint32_t* cnt) {
-  const uint32_t n = min(*ptotal, cap);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    atomicAdd(&cnt[ptgt[i]], 1u);
-}
-
-__global__ void prop_scatter_kernel(const uint32_t* ptgt, const uint64_t* pkey, const uint32_t* ptotal, uint32_t cap,
-                                    uint32_t* cur, uint64_t* sorted) {
-  const uint32_t n = min(*ptotal, cap);
-  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x)
-    sorted[atomicAdd(&cur[ptgt[i]], 1u)] = pkey[i];
-}
+// proposals, grouped by target (group_records), applied
 
 // first k of snapshot (old) U proposals (new), one entry per id; every
 // list's new entries turn old.  The indegrees T and the counts of new
@@ -1132,21 +1308,17 @@ __global__ void aux_refresh_kernel(const uint64_t* keys, uint64_t N, uint32_t k,
 
 // reverse-list segment sizes of the next Visit from the maintained counts:
 // 2v holds v's new in-edges, 2v+1 its old ones
-// Reverse-list sizes from the maintained counts.  A vertex is active when
-// its list holds a new entry or it has a new in-edge: otherwise its Cn is
-// empty, its join forms no pair and reads no reverse entry, so its old
-// reverse segment is left empty (the reverse lists of new entries are
-// always complete).
-__global__ void rev_sizes_kernel(const uint32_t* T, const uint32_t* newc, const uint32_t* flags, uint32_t k,
-                                 uint64_t N, uint32_t* cnt, uint32_t* active) {
+// A vertex is active when its list holds a new entry or it has a new
+// in-edge (a maintained count): otherwise its Cn is empty, its join forms no
+// pair and reads no reverse entry, so its old reverse segment is left empty
+// (the reverse lists of new entries are always complete).
+__global__ void rev_active_kernel(const uint32_t* newc, const uint32_t* flags, uint32_t k, uint64_t N,
+                                  uint32_t* active) {
   for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < N;
        v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    const uint32_t n = newc[v];
-    bool act = n > 0;
+    bool act = newc[v] > 0;
     for (uint32_t e = 0; e < k && !act; ++e) act = (flags[v * k + e] & kFlagNew) != 0;
     active[v] = act ? 1u : 0u;
-    cnt[2 * v] = n;
-    cnt[2 * v + 1] = act ? T[v] - n : 0u;
   }
 }
 
@@ -1768,11 +1940,12 @@ struct RefineBufs {
   uint32_t* rev_cur;
   uint64_t* rev;
   uint32_t* ptgt;
-  uint64_t* pkey;
-  uint32_t* pcnt;
+  uint64_t* pkey;   // appended proposals, then (after grouping) their keys by target
   uint32_t* poff;
-  uint32_t* pcur;
-  uint64_t* psorted;
+  uint32_t* bmat;   // grouping: bucket-major count matrix and its scan
+  uint32_t* bmoff;
+  uint32_t* cseg;   // grouping: records in bucket order
+  uint64_t* cval;
   uint32_t* T;
   uint32_t* zmask;
   uint32_t* zoff;
@@ -1814,6 +1987,7 @@ struct RoundPlan {
   uint32_t join_grid, cand_grid, recheck_grid;
   size_t join_smem;
   bool use_mfma;
+  BucketPlan prop_plan, rev_plan;
   uint32_t batches;  // > 1: streamlined rounds of this many vertex ranges
   uint32_t chunks;   // Update of a synchronous round in this many vertex chunks (MFMA join)
 };
@@ -1854,16 +2028,14 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   if (rp.batches > 1) return run_stream_round(rp, b, s);
   const uint64_t N = rp.N, nk = N * rp.k;
   hipError_t e;
-  // Visit: reverse-list sizes from the maintained indegrees (T) and new
-  // in-edge counts, then the reverse CSR
-  // (b.zmask holds the active flags until the repair reuses it)
-  hipLaunchKernelGGL(rev_sizes_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.T, b.newc, b.flags, rp.k, N, b.rev_cnt,
-                     b.zmask);
-  if ((e = exclusive_scan(b.rev_cnt, b.rev_off, 2 * N, b.scan_tmp, s)) != hipSuccess) return e;
+  // Visit: active vertices from the maintained new in-edge counts, then
+  // the reverse CSR (b.zmask holds the active flags until the repair
+  // reuses it)
+  hipLaunchKernelGGL(rev_active_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.newc, b.flags, rp.k, N, b.zmask);
   if ((e = fill_u32(b.newc, 0u, N, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(2 * N)), dim3(256), 0, s, b.rev_off, b.rev_cur, 2 * N);
-  hipLaunchKernelGGL(rev_scatter_kernel, dim3(grid_for(nk)), dim3(256), 0, s, b.keys, b.flags, nk, rp.k, b.zmask, b.rev_cur,
-                     b.rev);
+  if ((e = group_records(RevRecords{b.keys, b.flags, b.zmask, nk, rp.k}, rp.rev_plan, b.bmat, b.bmoff, b.scan_tmp,
+                         b.cseg, b.cval, b.rev_off, b.rev, s)) != hipSuccess)
+    return e;
   // Update, in vertex chunks that share one pair buffer: every chunk joins
   // against the same snapshot, and the proposals of all of them are applied
   // together, so the chunking changes no result
@@ -1894,18 +2066,15 @@ hipError_t run_round(const RoundPlan& rp, const RefineBufs& b, hipStream_t s) {
   } else if ((e = launch_join(rp.ja, rp.nr, rp.mmax, rp.join_grid, rp.join_smem, s)) != hipSuccess) {
     return e;
   }
-  if ((e = fill_u32(b.pcnt, 0u, N, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(prop_count_kernel, dim3(4096), dim3(256), 0, s, b.ptgt, b.hdr, rp.cap, b.pcnt);
-  if ((e = exclusive_scan(b.pcnt, b.poff, N, b.scan_tmp, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.poff, b.pcur, N);
-  hipLaunchKernelGGL(prop_scatter_kernel, dim3(4096), dim3(256), 0, s, b.ptgt, b.pkey, b.hdr, rp.cap, b.pcur,
-                     b.psorted);
+  if ((e = group_records(PropRecords{b.ptgt, b.pkey, b.hdr, rp.cap}, rp.prop_plan, b.bmat, b.bmoff, b.scan_tmp,
+                         b.cseg, b.cval, b.poff, b.pkey, s)) != hipSuccess)
+    return e;
   if (rp.nr == 1)
     hipLaunchKernelGGL(apply_kernel<1>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, b.poff,
-                       b.psorted, b.hdr + 1, b.hdr, b.T, b.newc);
+                       b.pkey, b.hdr + 1, b.hdr, b.T, b.newc);
   else
     hipLaunchKernelGGL(apply_kernel<2>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, b.poff,
-                       b.psorted, b.hdr + 1, b.hdr, b.T, b.newc);
+                       b.pkey, b.hdr + 1, b.hdr, b.T, b.newc);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   if (!rp.repair) return hipSuccess;
   return launch_repair(b, N, rp.k, s);
@@ -1956,18 +2125,15 @@ hipError_t run_stream_round(const RoundPlan& rp, const RefineBufs& b, hipStream_
                                 s)) != hipSuccess) {
       return e;
     }
-    if ((e = fill_u32(b.pcnt, 0u, N, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(prop_count_kernel, dim3(4096), dim3(256), 0, s, b.ptgt, b.hdr, rp.cap, b.pcnt);
-    if ((e = exclusive_scan(b.pcnt, b.poff, N, b.scan_tmp, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(copy_u32_kernel, dim3(grid_for(N)), dim3(256), 0, s, b.poff, b.pcur, N);
-    hipLaunchKernelGGL(prop_scatter_kernel, dim3(4096), dim3(256), 0, s, b.ptgt, b.pkey, b.hdr, rp.cap, b.pcur,
-                       b.psorted);
+    if ((e = group_records(PropRecords{b.ptgt, b.pkey, b.hdr, rp.cap}, rp.prop_plan, b.bmat, b.bmoff, b.scan_tmp,
+                           b.cseg, b.cval, b.poff, b.pkey, s)) != hipSuccess)
+      return e;
     if (rp.nr == 1)
       hipLaunchKernelGGL(apply_stream_kernel<1>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, lo, hi,
-                         b.poff, b.psorted, b.hdr + 1, b.hdr, b.T);
+                         b.poff, b.pkey, b.hdr + 1, b.hdr, b.T);
     else
       hipLaunchKernelGGL(apply_stream_kernel<2>, dim3(grid_for(N, 4)), dim3(256), 0, s, b.keys, b.flags, N, rp.k, lo, hi,
-                         b.poff, b.psorted, b.hdr + 1, b.hdr, b.T);
+                         b.poff, b.pkey, b.hdr + 1, b.hdr, b.T);
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }
   if (!rp.repair) return hipSuccess;
@@ -2090,10 +2256,13 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     FGIM_TRY(scr.get(&b.rev, nk));
     FGIM_TRY(scr.get(&b.ptgt, cap));
     FGIM_TRY(scr.get(&b.pkey, cap));
-    FGIM_TRY(scr.get(&b.pcnt, N + 1));
     FGIM_TRY(scr.get(&b.poff, N + 1));
-    FGIM_TRY(scr.get(&b.pcur, N + 1));
-    FGIM_TRY(scr.get(&b.psorted, cap));
+    const BucketPlan prop_plan = bucket_plan(N, cap), rev_plan = bucket_plan(2 * N, nk);
+    const uint64_t mat_words = std::max(prop_plan.words(), rev_plan.words());
+    FGIM_TRY(scr.get(&b.bmat, mat_words));
+    FGIM_TRY(scr.get(&b.bmoff, mat_words + 1));
+    FGIM_TRY(scr.get(&b.cseg, std::max<uint64_t>(cap, nk)));
+    FGIM_TRY(scr.get(&b.cval, std::max<uint64_t>(cap, nk)));
     FGIM_TRY(scr.get(&b.T, N));
     FGIM_TRY(scr.get(&b.newc, N));
     FGIM_TRY(scr.get(&b.zmask, N + 1));
@@ -2122,7 +2291,7 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
       hipLaunchKernelGGL(row_norms_kernel, dim3(grid_for(N, 4)), dim3(256), 0, s, d->base, N, dim, d->ld, nrm2, qerr2);
       HIP_TRY(hipGetLastError());
     }
-    FGIM_TRY(scr.get(&b.scan_tmp, scan_tmp_words(2 * N + 1) + 16));
+    FGIM_TRY(scr.get(&b.scan_tmp, std::max(scan_tmp_words(2 * N + 1), scan_tmp_words(mat_words)) + 16));
     FGIM_TRY(scr.get(&b.sub_off, d->h));
     std::vector<uint64_t> hoff(d->h);
     for (uint32_t i = 0; i < d->h; ++i) hoff[i] = d->subs[i].row_offset;
@@ -2184,6 +2353,8 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
     ja.u_lo = 0;
     ja.u_hi = N;
     rp.use_mfma = use_mfma;
+    rp.prop_plan = prop_plan;
+    rp.rev_plan = rev_plan;
     rp.join_smem = use_mfma ? mfma_smem : base_smem + (stage_rows ? rows_smem : 0);
     rp.join_grid = static_cast<uint32_t>(std::min<uint64_t>(N, static_cast<uint64_t>(device_cus()) * 8));
     rp.cand_grid = static_cast<uint32_t>(std::min<uint64_t>((N + 3) / 4, static_cast<uint64_t>(device_cus()) * 16));
