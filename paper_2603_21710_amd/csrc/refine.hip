@@ -180,6 +180,8 @@ struct PropRecords {
 // reverse entries of a synchronous Visit: list entry i, u -> t with u = i / k,
 // gives the record (2t if the entry is new, else 2t + 1; key (stored delta,
 // u)).  Old entries of an inactive target give none: no join reads them.
+// active: one bit per vertex (bit t & 31 of word t >> 5), small enough to
+// stay in L2 for the random lookups.
 struct RevRecords {
   const uint64_t* keys;
   const uint32_t* flags;
@@ -192,7 +194,7 @@ struct RevRecords {
     if (kk == kSentinel) return false;
     const uint32_t t = key_id(kk);
     const bool isnew = flags[i] & kFlagNew;
-    if (!isnew && !active[t]) return false;
+    if (!isnew && !((active[t >> 5] >> (t & 31u)) & 1u)) return false;
     seg = 2u * t + (isnew ? 0u : 1u);
     return true;
   }
@@ -1311,14 +1313,23 @@ __global__ void aux_refresh_kernel(const uint64_t* keys, uint64_t N, uint32_t k,
 // A vertex is active when its list holds a new entry or it has a new
 // in-edge (a maintained count): otherwise its Cn is empty, its join forms no
 // pair and reads no reverse entry, so its old reverse segment is left empty
-// (the reverse lists of new entries are always complete).
+// (the reverse lists of new entries are always complete).  The result is
+// one bit per vertex, written a wave's 64 vertices at a time (the loop bound
+// is wave-uniform).
 __global__ void rev_active_kernel(const uint32_t* newc, const uint32_t* flags, uint32_t k, uint64_t N,
-                                  uint32_t* active) {
-  for (uint64_t v = blockIdx.x * static_cast<uint64_t>(blockDim.x) + threadIdx.x; v < N;
-       v += static_cast<uint64_t>(gridDim.x) * blockDim.x) {
-    bool act = newc[v] > 0;
-    for (uint32_t e = 0; e < k && !act; ++e) act = (flags[v * k + e] & kFlagNew) != 0;
-    active[v] = act ? 1u : 0u;
+                                  uint32_t* active_bits) {
+  const uint64_t nw = static_cast<uint64_t>(gridDim.x) * (blockDim.x / 64);
+  const uint64_t wave = uniform(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+  for (uint64_t base = wave * 64; base < N; base += nw * 64) {
+    const uint64_t v = base + lane_id();
+    bool act = false;
+    if (v < N) {
+      act = newc[v] > 0;
+      for (uint32_t e = 0; e < k && !act; ++e) act = (flags[v * k + e] & kFlagNew) != 0;
+    }
+    const uint64_t m = ballot(act);
+    if (lane_id() == 0) active_bits[base >> 5] = static_cast<uint32_t>(m);
+    if (lane_id() == 32 && base + 32 < N) active_bits[(base >> 5) + 1] = static_cast<uint32_t>(m >> 32);
   }
 }
 
