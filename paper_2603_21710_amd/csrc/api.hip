@@ -447,7 +447,13 @@ fgim_status check_dataset(const fgim_dataset* d, bool need_cross) {
   return FGIM_OK;
 }
 
-fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* p, BeamShape* out) {
+uint32_t max_stride(const fgim_dataset* d) {
+  uint32_t m = 0;
+  for (uint32_t i = 0; i < d->h; ++i) m = std::max(m, d->subs[i].adj_stride);
+  return m;
+}
+
+fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* p, BeamShape* out, uint32_t stride) {
   const uint32_t nc = dim / 4;
   const uint32_t N = ceil_pow2(nc);
   // defaults measured on 2 x 500k rows, d=128, L=64: four chunks per lane
@@ -464,6 +470,16 @@ fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* 
   // 2048 slots (8 KB per wave) still fit the 16 resident waves of the
   // default shape and re-score 2.7 % fewer ids than 1024 (93 vs 96 ms)
   uint32_t slots = p && p->visited_slots ? p->visited_slots : std::min<uint32_t>(2048, std::max<uint32_t>(1024, ceil_pow2(32 * L)));
+  // The FP32 kernel needs fewer registers than the BF16 / FP8 ones (20
+  // resident waves per CU against 16), so at 2048 slots its LDS, not its
+  // registers, sets residency (17 waves).  Short searches (L x R_in < 2048,
+  // R_in the widest adjacency row) remember few ids, and 1024 slots re-score
+  // few extra: 8 uneven sub-indexes of 2 M rows, d = 96, L = 48, R_in = 24
+  // run 6.6 % faster with 1024 (0.7 % more distances); 2 x 500k rows,
+  // d = 128, L = 64, R_in = 32 run 2.6 % slower (2.8 % more distances).
+  if (!(p && p->visited_slots) && (!p || p->precision == FGIM_FP32) && stride &&
+      static_cast<uint64_t>(L) * stride < 2048)
+    slots = std::min<uint32_t>(slots, 1024);
   if (!is_pow2(slots) || slots < 64 || slots > 16384) return fail(FGIM_ERR_INVALID_ARG, "visited_slots %u must be a power of 2 in 64..16384", slots);
   uint32_t waves = p && p->waves_per_cu ? p->waves_per_cu : 32;
   if (waves > 64) return fail(FGIM_ERR_INVALID_ARG, "waves_per_cu %u > 64", waves);
@@ -521,7 +537,7 @@ fgim_status cross_query_check(const fgim_dataset* d, const fgim_params* p, const
   uint32_t rr = 0;
   BeamShape sh;
   FGIM_TRY(rerank_for(p, p->L, &rr));
-  FGIM_TRY(beam_shape(d->dim, p->L, p->k, p, &sh));
+  FGIM_TRY(beam_shape(d->dim, p->L, p->k, p, &sh, max_stride(d)));
   return FGIM_OK;
 }
 
@@ -577,7 +593,7 @@ fgim_status cross_query_run(const fgim_dataset* d, const fgim_params* p, uint32_
     if (p->precision != FGIM_FP32 && p->rerank) lo = std::max(lo, p->rerank);
     FGIM_TRY(tune_stage1(a, d, p, fmt, l2, lo, &L, &shape, &ms_tune, s));
   } else {
-    FGIM_TRY(beam_shape(d->dim, L, p->k, p, &shape));
+    FGIM_TRY(beam_shape(d->dim, L, p->k, p, &shape, max_stride(d)));
   }
   uint32_t rerank = 0;
   FGIM_TRY(rerank_for(p, L, &rerank));
