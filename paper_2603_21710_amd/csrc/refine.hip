@@ -1313,23 +1313,45 @@ __global__ void aux_refresh_kernel(const uint64_t* keys, uint64_t N, uint32_t k,
 // A vertex is active when its list holds a new entry or it has a new
 // in-edge (a maintained count): otherwise its Cn is empty, its join forms no
 // pair and reads no reverse entry, so its old reverse segment is left empty
-// (the reverse lists of new entries are always complete).  The result is
-// one bit per vertex, written a wave's 64 vertices at a time (the loop bound
-// is wave-uniform).
+// (the reverse lists of new entries are always complete).  A wave takes 64
+// consecutive vertices, whose flags are 64 k consecutive words: it reads
+// them 64 at a time (coalesced, eight loads in flight), and each lane tests
+// the bits of the ballot that belong to its own vertex.  The result is one
+// bit per vertex, written 64 at a time; every loop bound is wave-uniform.
 __global__ void rev_active_kernel(const uint32_t* newc, const uint32_t* flags, uint32_t k, uint64_t N,
                                   uint32_t* active_bits) {
+  constexpr uint32_t kIn = 8;
   const uint64_t nw = static_cast<uint64_t>(gridDim.x) * (blockDim.x / 64);
   const uint64_t wave = uniform(blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64);
+  const uint32_t l = static_cast<uint32_t>(lane_id());
+  const uint64_t nk = N * k;
   for (uint64_t base = wave * 64; base < N; base += nw * 64) {
-    const uint64_t v = base + lane_id();
-    bool act = false;
-    if (v < N) {
-      act = newc[v] > 0;
-      for (uint32_t e = 0; e < k && !act; ++e) act = (flags[v * k + e] & kFlagNew) != 0;
+    const uint64_t v = base + l;
+    bool act = v < N && newc[v] > 0;
+    const uint64_t w0 = base * k;  // first flag word of the block
+    const uint32_t my_lo = l * k, my_hi = l * k + k;  // my vertex's words, block-relative
+    for (uint32_t j0 = 0; j0 < k; j0 += kIn) {
+      uint32_t f[kIn];
+#pragma unroll
+      for (uint32_t t = 0; t < kIn; ++t) {
+        const uint64_t w = w0 + static_cast<uint64_t>(j0 + t) * 64 + l;
+        f[t] = j0 + t < k && w < nk ? flags[w] : 0u;
+      }
+#pragma unroll
+      for (uint32_t t = 0; t < kIn; ++t) {
+        const uint64_t m = ballot((f[t] & kFlagNew) != 0u);
+        const uint32_t c0 = (j0 + t) * 64;  // block-relative words of this row
+        const uint32_t lo = my_lo > c0 ? my_lo : c0, hi = my_hi < c0 + 64 ? my_hi : c0 + 64;
+        if (lo < hi) {
+          const uint32_t len = hi - lo;
+          const uint64_t bits = len == 64 ? ~0ull : ((1ull << len) - 1ull);
+          act = act || ((m >> (lo - c0)) & bits) != 0ull;
+        }
+      }
     }
-    const uint64_t m = ballot(act);
-    if (lane_id() == 0) active_bits[base >> 5] = static_cast<uint32_t>(m);
-    if (lane_id() == 32 && base + 32 < N) active_bits[(base >> 5) + 1] = static_cast<uint32_t>(m >> 32);
+    const uint64_t mv = ballot(act);
+    if (l == 0) active_bits[base >> 5] = static_cast<uint32_t>(mv);
+    if (l == 32 && base + 32 < N) active_bits[(base >> 5) + 1] = static_cast<uint32_t>(mv >> 32);
   }
 }
 
