@@ -461,7 +461,20 @@ fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* 
   // CU (VGPR-limited to 16 resident): 95 ms with a 1024-slot visited cache,
   // against 100 ms for two chunks per lane and 129 ms for the first shape
   // (90.6 ms now, with 2048 two-choice slots and empty batches skipped)
-  uint32_t P = p && p->lanes_per_dist ? p->lanes_per_dist : std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, N), N / 4));
+  // Short searches (L x R_in < 2048, R_in the widest adjacency row) score
+  // few rows per expansion and wait on their chains of dependent loads, so
+  // residency decides: two chunks per lane take the kernels with the fewest
+  // registers (67 / 87 / 92 VGPRs for FP32 / BF16 / FP8 against 92 / 122 /
+  // 124 with four), and a 1024-slot visited cache lets that many waves fit
+  // in LDS (a short search remembers few ids, so it re-scores few extra).
+  // 8 uneven sub-indexes of 2 M rows, d = 96, L = 48, R_in = 24: stage 1
+  // FP32 / BF16 / FP8 294 / 343 / 350 ms -> 266 / 332 / 339 ms.  Longer
+  // searches keep the shape below: 2 x 500k rows, d = 128, L = 64, R_in = 32
+  // ran 1-14 % slower with either change.
+  const bool short_search = stride && static_cast<uint64_t>(L) * stride < 2048;
+  uint32_t P = p && p->lanes_per_dist ? p->lanes_per_dist
+                                      : std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, N),
+                                                                                   short_search ? N / 2 : N / 4));
   if (!is_pow2(P) || P > 64 || P > N) return fail(FGIM_ERR_INVALID_ARG, "lanes_per_dist %u must be a power of 2 <= min(64, %u)", P, N);
   const uint32_t M = N / P;
   if (M > 16) return fail(FGIM_ERR_INVALID_ARG, "lanes_per_dist %u too small for dim %u", P, dim);
@@ -470,16 +483,7 @@ fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* 
   // 2048 slots (8 KB per wave) still fit the 16 resident waves of the
   // default shape and re-score 2.7 % fewer ids than 1024 (93 vs 96 ms)
   uint32_t slots = p && p->visited_slots ? p->visited_slots : std::min<uint32_t>(2048, std::max<uint32_t>(1024, ceil_pow2(32 * L)));
-  // The FP32 kernel needs fewer registers than the BF16 / FP8 ones (20
-  // resident waves per CU against 16), so at 2048 slots its LDS, not its
-  // registers, sets residency (17 waves).  Short searches (L x R_in < 2048,
-  // R_in the widest adjacency row) remember few ids, and 1024 slots re-score
-  // few extra: 8 uneven sub-indexes of 2 M rows, d = 96, L = 48, R_in = 24
-  // run 6.6 % faster with 1024 (0.7 % more distances); 2 x 500k rows,
-  // d = 128, L = 64, R_in = 32 run 2.6 % slower (2.8 % more distances).
-  if (!(p && p->visited_slots) && (!p || p->precision == FGIM_FP32) && stride &&
-      static_cast<uint64_t>(L) * stride < 2048)
-    slots = std::min<uint32_t>(slots, 1024);
+  if (!(p && p->visited_slots) && short_search) slots = std::min<uint32_t>(slots, 1024);
   if (!is_pow2(slots) || slots < 64 || slots > 16384) return fail(FGIM_ERR_INVALID_ARG, "visited_slots %u must be a power of 2 in 64..16384", slots);
   uint32_t waves = p && p->waves_per_cu ? p->waves_per_cu : 32;
   if (waves > 64) return fail(FGIM_ERR_INVALID_ARG, "waves_per_cu %u > 64", waves);
