@@ -186,19 +186,22 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
 }
 
 // One wavefront per adjacency row: every id must be FGIM_NONE or < n, not
-// the row's own id, and unique within the row.  Sets *err on a violation and,
-// when min_deg is given, lowers *min_deg to the smallest out-degree seen.
+// the row's own id, and unique within the row.  Sets *err on a violation;
+// when min_deg is given, lowers *min_deg to the smallest out-degree seen, and
+// when edges is given, adds the sum of the out-degrees to *edges.
 __global__ void __launch_bounds__(256) validate_graph_kernel(const uint32_t* adj, uint32_t n,
                                                              uint32_t stride, uint32_t* err,
-                                                             uint32_t* min_deg) {
+                                                             uint32_t* min_deg, unsigned long long* edges) {
   const uint32_t wave = threadIdx.x / 64;
   const int lane = lane_id();
   uint32_t mdeg = 0xFFFFFFFFu;
+  unsigned long long esum = 0;
   for (uint64_t row = blockIdx.x * 4ull + wave; row < n; row += gridDim.x * 4ull) {
     const uint32_t v0 = lane < static_cast<int>(stride) ? adj[row * stride + lane] : kNone;
     const uint32_t v1 = lane + 64 < static_cast<int>(stride) ? adj[row * stride + 64 + lane] : kNone;
     const uint32_t deg = static_cast<uint32_t>(popc64(ballot(v0 != kNone)) + popc64(ballot(v1 != kNone)));
     mdeg = deg < mdeg ? deg : mdeg;
+    esum += deg;
     bool bad = (v0 != kNone && (v0 >= n || v0 == row)) || (v1 != kNone && (v1 >= n || v1 == row));
     for (int s = 1; s < 64; ++s) {
       const uint32_t w0 = __shfl_xor(v0, s, 64);
@@ -217,12 +220,13 @@ __global__ void __launch_bounds__(256) validate_graph_kernel(const uint32_t* adj
     if (ballot(bad) != 0 && lane == 0) atomicOr(err, 1u);
   }
   if (min_deg && lane == 0 && mdeg != 0xFFFFFFFFu) atomicMin(min_deg, mdeg);
+  if (edges && lane == 0 && esum) atomicAdd(edges, esum);
 }
 
 hipError_t validate_graph(const uint32_t* adj, uint32_t n, uint32_t stride, uint32_t* err,
-                          hipStream_t s, uint32_t* min_deg = nullptr) {
+                          hipStream_t s, uint32_t* min_deg = nullptr, unsigned long long* edges = nullptr) {
   uint32_t blocks = std::min<uint32_t>((n + 3) / 4, 8192);
-  hipLaunchKernelGGL(validate_graph_kernel, dim3(blocks), dim3(256), 0, s, adj, n, stride, err, min_deg);
+  hipLaunchKernelGGL(validate_graph_kernel, dim3(blocks), dim3(256), 0, s, adj, n, stride, err, min_deg, edges);
   return hipGetLastError();
 }
 
@@ -447,13 +451,8 @@ fgim_status check_dataset(const fgim_dataset* d, bool need_cross) {
   return FGIM_OK;
 }
 
-uint32_t max_stride(const fgim_dataset* d) {
-  uint32_t m = 0;
-  for (uint32_t i = 0; i < d->h; ++i) m = std::max(m, d->subs[i].adj_stride);
-  return m;
-}
-
-fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* p, BeamShape* out, uint32_t stride) {
+fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* p, BeamShape* out,
+                       double mean_degree) {
   const uint32_t nc = dim / 4;
   const uint32_t N = ceil_pow2(nc);
   // defaults measured on 2 x 500k rows, d=128, L=64: four chunks per lane
@@ -461,17 +460,20 @@ fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* 
   // CU (VGPR-limited to 16 resident): 95 ms with a 1024-slot visited cache,
   // against 100 ms for two chunks per lane and 129 ms for the first shape
   // (90.6 ms now, with 2048 two-choice slots and empty batches skipped)
-  // Short searches (L x R_in < 2048, R_in the widest adjacency row) score
-  // few rows per expansion and wait on their chains of dependent loads, so
-  // residency decides: two chunks per lane take the kernels with the fewest
-  // registers (67 / 87 / 92 VGPRs for FP32 / BF16 / FP8 against 92 / 122 /
-  // 124 with four), and a 1024-slot visited cache lets that many waves fit
-  // in LDS (a short search remembers few ids, so it re-scores few extra).
-  // 8 uneven sub-indexes of 2 M rows, d = 96, L = 48, R_in = 24: stage 1
-  // FP32 / BF16 / FP8 294 / 343 / 350 ms -> 266 / 332 / 339 ms.  Longer
-  // searches keep the shape below: 2 x 500k rows, d = 128, L = 64, R_in = 32
-  // ran 1-14 % slower with either change.
-  const bool short_search = stride && static_cast<uint64_t>(L) * stride < 2048;
+  // Searches on sparse graphs (mean out-degree <= 12) score few rows per
+  // expansion and wait on their chains of dependent loads, so residency
+  // decides: two chunks per lane take the kernels with the fewest registers
+  // (67 / 87 / 92 VGPRs for FP32 / BF16 / FP8 against 92 / 122 / 124 with
+  // four), and a 1024-slot visited cache lets that many waves fit in LDS
+  // (a search that scores few rows remembers few ids).  Measured, stage 1
+  // FP32 / BF16 / FP8: 8 uneven sub-indexes of 2 M rows, d = 96, L = 48,
+  // mean degree 9.4: 294 / 343 / 350 ms -> 266 / 332 / 338 ms; 20 uneven
+  // sub-indexes of 11.4 M rows, d = 128, L = 96, mean degree 9.9: 15.5 /
+  // 15.7 / 15.6 s -> 13.6 / 15.0 / 15.0 s.  Denser graphs keep the shape
+  // below: at mean degree 13.5 (2 x 500k rows, d = 128) either change was
+  // 1-14 % slower, at 18.6 (the 2 M-row set with navigable inputs) both
+  // together 4-9 % slower.
+  const bool short_search = mean_degree > 0.0 && mean_degree <= 12.0;
   uint32_t P = p && p->lanes_per_dist ? p->lanes_per_dist
                                       : std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, N),
                                                                                    short_search ? N / 2 : N / 4));
@@ -541,7 +543,7 @@ fgim_status cross_query_check(const fgim_dataset* d, const fgim_params* p, const
   uint32_t rr = 0;
   BeamShape sh;
   FGIM_TRY(rerank_for(p, p->L, &rr));
-  FGIM_TRY(beam_shape(d->dim, p->L, p->k, p, &sh, max_stride(d)));
+  FGIM_TRY(beam_shape(d->dim, p->L, p->k, p, &sh));
   return FGIM_OK;
 }
 
@@ -557,7 +559,7 @@ fgim_status cross_query_run(const fgim_dataset* d, const fgim_params* p, uint32_
   HIP_TRY(fill_u32(reinterpret_cast<uint32_t*>(b.cnt), 0u, 8, s));
   for (uint32_t i = 0; i < d->h; ++i)
     HIP_TRY(validate_graph(d->subs[i].adj, d->subs[i].n, d->subs[i].adj_stride, hdr + 1, s,
-                           p->autotune ? hdr + 2 : nullptr));
+                           p->autotune ? hdr + 2 : nullptr, b.cnt + 3));
   if (p->precision == FGIM_FP8_E4M3 && !b.lps) return fail(FGIM_ERR_INVALID_ARG, "FP8 copy given without scales");
 
   BeamArgs a{};
@@ -597,7 +599,11 @@ fgim_status cross_query_run(const fgim_dataset* d, const fgim_params* p, uint32_
     if (p->precision != FGIM_FP32 && p->rerank) lo = std::max(lo, p->rerank);
     FGIM_TRY(tune_stage1(a, d, p, fmt, l2, lo, &L, &shape, &ms_tune, s));
   } else {
-    FGIM_TRY(beam_shape(d->dim, L, p->k, p, &shape, max_stride(d)));
+    // the mean out-degree of the graphs (summed by the validation above)
+    unsigned long long edges = 0;
+    HIP_TRY(hipMemcpyAsync(&edges, b.cnt + 3, sizeof(edges), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    FGIM_TRY(beam_shape(d->dim, L, p->k, p, &shape, static_cast<double>(edges) / static_cast<double>(d->n_total)));
   }
   uint32_t rerank = 0;
   FGIM_TRY(rerank_for(p, L, &rerank));

@@ -26,9 +26,9 @@ struct BeamShape {
 
 // api.hip: the shape for (dim, L, k), taking every non-zero launch field of
 // p as given and the measured defaults for the rest
-// stride: the widest adjacency row of the graphs searched (0: unknown)
+// mean_degree: the mean out-degree of the graphs searched (0: unknown)
 fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* p, BeamShape* out,
-                       uint32_t stride = 0);
+                       double mean_degree = 0.0);
 size_t beam_smem(const BeamShape& s);
 hipError_t launch_beam(const BeamArgs& a, bool l2, int fmt, const BeamShape& s, hipStream_t st);
 // entries of each search re-scored in FP32 in the low-precision forms
