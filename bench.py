@@ -321,10 +321,14 @@ def beam_roofline(fg, m, cfg, X, graphs, precision, st, beam_ms, peak_meas, coun
     # Algorithm 1.  That counting launch uses another lanes-per-distance
     # (another kernel instance, the same count), so a kernel trace of this
     # script lists the timed launches under their own name.
+    # The other lane count halves P where that keeps at most four chunks per
+    # lane (doubling it from two chunks per lane leaves one, the slowest shape)
     used_p = st["lanes_per_dist"]
-    alt_p = used_p * 2 if used_p * 2 <= min(64, X.shape[1] // 4) else max(1, used_p // 2)
+    chunks = max(1, X.shape[1] // 4)
+    alt_p = used_p // 2 if used_p >= 2 and chunks // (used_p // 2) <= 4 else min(64, used_p * 2)
     st_big = st
     if count_launch:
+        log(f"{cfg.name} {precision}: counting launch ({alt_p} lanes per distance, 16384 visited slots)")
         _, _, st_big = fg.cross_query(m, fg.params(k=cfg.k, L=st["L_used"], precision=precision,
                                                    visited_slots=16384, waves_per_cu=8,
                                                    lanes_per_dist=alt_p), stats=True)
@@ -462,13 +466,17 @@ def measure(fg, cfg, forms, args, dev, peak_meas, with_parity, with_recall):
         for _ in range(args.warmup):
             _, _, _, stw = fg.merge(m, p, stats=True)
             tune_ms = stw["ms_tune"] if tune_ms is None else tune_ms
+            if sum(stw["ms_stage"]) > 5000:
+                log(f"{cfg.name} {form}: warm-up merge {sum(stw['ms_stage']):.0f} ms")
         torch.cuda.synchronize()
         beam_ms, stage_ms = [], []
         t1 = time.perf_counter()
-        for _ in range(args.steps):
+        for step in range(args.steps):
             pg, deg, entry, st = fg.merge(m, p, stats=True)
             beam_ms.append(st["ms_beam_kernel"])
             stage_ms.append(st["ms_stage"])
+            if sum(st["ms_stage"]) > 5000:  # long merges: a line per step
+                log(f"{cfg.name} {form}: step {step + 1}/{args.steps} {sum(st['ms_stage']):.0f} ms")
         torch.cuda.synchronize()
         wall = time.perf_counter() - t1
         ms = wall * 1e3 / args.steps

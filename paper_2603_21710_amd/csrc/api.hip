@@ -220,12 +220,20 @@ __global__ void __launch_bounds__(256) validate_graph_kernel(const uint32_t* adj
     if (ballot(bad) != 0 && lane == 0) atomicOr(err, 1u);
   }
   if (min_deg && lane == 0 && mdeg != 0xFFFFFFFFu) atomicMin(min_deg, mdeg);
-  if (edges && lane == 0 && esum) atomicAdd(edges, esum);
+  // one atomic per workgroup: every wave adding to the one counter would
+  // serialise thousands of device-scope atomics
+  __shared__ unsigned long long s_e[4];
+  if (lane == 0) s_e[wave] = esum;
+  __syncthreads();
+  if (edges && threadIdx.x == 0) {
+    const unsigned long long t = s_e[0] + s_e[1] + s_e[2] + s_e[3];
+    if (t) atomicAdd(edges, t);
+  }
 }
 
 hipError_t validate_graph(const uint32_t* adj, uint32_t n, uint32_t stride, uint32_t* err,
                           hipStream_t s, uint32_t* min_deg = nullptr, unsigned long long* edges = nullptr) {
-  uint32_t blocks = std::min<uint32_t>((n + 3) / 4, 8192);
+  uint32_t blocks = std::min<uint32_t>((n + 3) / 4, 2048);
   hipLaunchKernelGGL(validate_graph_kernel, dim3(blocks), dim3(256), 0, s, adj, n, stride, err, min_deg, edges);
   return hipGetLastError();
 }

@@ -63,6 +63,33 @@ def test_launch_shape_does_not_change_bits():
         assert torch.equal(ids, ref)
 
 
+def _random_graphs(X, sizes, degree, seed):
+    """Sub-indexes whose rows hold `degree` random distinct other local ids."""
+    rng = np.random.default_rng(seed)
+    graphs, off = [], 0
+    for n in sizes:
+        adj = np.full((n, 24), NONE, np.uint32)
+        for u in range(n):
+            adj[u, :degree] = rng.choice(np.delete(np.arange(n), u), degree, replace=False)
+        graphs.append((off, adj, 0))
+        off += n
+    return graphs
+
+
+@pytest.mark.parametrize("degree,P,slots", [(6, 16, 1024), (20, 8, 2048)])
+def test_sparse_graphs_take_the_two_chunk_shape(degree, P, slots):
+    # d = 128: the default shape has four chunks per lane (P = 8) and, at
+    # L = 64, 2048 visited slots; graphs of mean out-degree <= 12 take two
+    # chunks per lane and 1024 slots.  Either way the result is the oracle's.
+    cfg, X, _, _ = workload("cfg2", (1500, 1200))
+    graphs = _random_graphs(X, (1500, 1200), degree, 40 + degree)
+    m = to_gpu(X, graphs, cfg.metric)
+    ids, dist, st = fg.cross_query(m, fg.params(k=cfg.k, L=cfg.L), stats=True)
+    assert (st["lanes_per_dist"], st["visited_slots"]) == (P, slots)
+    oi, od, _ = oracle.cross_query(X, graphs, cfg.k, cfg.L, cfg.metric)
+    assert _cmp(ids, dist, oi, od, f"degree {degree}")
+
+
 @pytest.mark.parametrize("k,L", [(16, 1), (16, 5), (100, 64), (24, 128), (32, 200), (128, 256)])
 def test_pool_and_topk_sizes(k, L):
     cfg, X, graphs, _ = workload("cfg3", (300, 500, 700, 150, 900, 400, 1200, 650))
