@@ -475,12 +475,14 @@ fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* 
   // four), and a 1024-slot visited cache lets that many waves fit in LDS
   // (a search that scores few rows remembers few ids).  Measured, stage 1
   // FP32 / BF16 / FP8: 8 uneven sub-indexes of 2 M rows, d = 96, L = 48,
-  // mean degree 9.4: 294 / 343 / 350 ms -> 266 / 332 / 338 ms; 20 uneven
-  // sub-indexes of 11.4 M rows, d = 128, L = 96, mean degree 9.9: 15.5 /
-  // 15.7 / 15.6 s -> 13.6 / 15.0 / 15.0 s.  Denser graphs keep the shape
-  // below: at mean degree 13.5 (2 x 500k rows, d = 128) either change was
-  // 1-14 % slower, at 18.6 (the 2 M-row set with navigable inputs) both
-  // together 4-9 % slower.
+  // mean degree 9.4: 294 / 343 / 350 ms -> 266 / 332 / 338 ms.  Denser graphs
+  // keep the shape below: at mean degree 13.5 (2 x 500k rows, d = 128)
+  // either change was 1-14 % slower, at 18.6 (the 2 M-row set with
+  // navigable inputs) both together 4-9 % slower.  (20 uneven sub-indexes of
+  // 11.4 M rows, d = 128, L = 96, ran 15.5 / 15.7 / 15.6 s -> 13.6 / 15.0 /
+  // 15.0 s with this shape forced, but their mean degree, weighted by rows,
+  // is above 12: the rule leaves them on the default.)  The mean is over
+  // rows, edges / n_total.
   const bool short_search = mean_degree > 0.0 && mean_degree <= 12.0;
   uint32_t P = p && p->lanes_per_dist ? p->lanes_per_dist
                                       : std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, N),
