@@ -810,6 +810,37 @@ FGIM_DEV uint32_t wave_sort64(uint32_t v) {
   return v;
 }
 
+// bitonic sort of one 64-bit key per lane, ascending
+FGIM_DEV uint64_t wave_sort64_keys(uint64_t v) {
+  const uint32_t lane = static_cast<uint32_t>(lane_id());
+#pragma unroll
+  for (uint32_t k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t o = shfl64(v, static_cast<int>(lane ^ j));
+      const bool lower = (lane & j) == 0;
+      const bool asc = (lane & k) == 0;
+      v = (lower == asc) ? (o < v ? o : v) : (o > v ? o : v);
+    }
+  }
+  return v;
+}
+
+// the 64 smallest of two ascending 64-key waves, ascending: lane l's
+// min(a[l], b[63 - l]) forms a bitonic sequence of exactly those keys, which
+// six half-cleaning steps sort
+FGIM_DEV uint64_t wave_merge_low64(uint64_t a, uint64_t b) {
+  const uint32_t lane = static_cast<uint32_t>(lane_id());
+  const uint64_t br = shfl64(b, static_cast<int>(63u - lane));
+  uint64_t v = a < br ? a : br;
+#pragma unroll
+  for (uint32_t j = 32; j > 0; j >>= 1) {
+    const uint64_t o = shfl64(v, static_cast<int>(lane ^ j));
+    v = (lane & j) == 0 ? (o < v ? o : v) : (o > v ? o : v);
+  }
+  return v;
+}
+
 // the unique non-NONE values of the sorted wave (one per lane) written to
 // out in order; returns their count (wave-uniform)
 FGIM_DEV uint32_t wave_unique64(uint32_t v, uint32_t* out) {
@@ -840,7 +871,10 @@ __global__ void __launch_bounds__(256) cand_kernel(JoinArgs a) {
     const bool in = static_cast<uint32_t>(lane) < a.k;
     const uint64_t kk = in ? a.keys[u * a.k + lane] : kSentinel;
     const uint32_t fl = in ? a.flags[u * a.k + lane] : 0u;
-    const uint32_t o0 = a.rev_off[2 * u], o1 = a.rev_off[2 * u + 1], o2 = a.rev_off[2 * u + 2];
+    // segment bounds are wave-uniform (readfirstlane): the selection below
+    // loops over them with cross-lane steps
+    const uint32_t o0 = uniform(a.rev_off[2 * u]), o1 = uniform(a.rev_off[2 * u + 1]),
+                   o2 = uniform(a.rev_off[2 * u + 2]);
     const float nrm = lane == 0 ? a.nrm2[u] : 0.0f, qe2 = lane == 0 ? a.qerr2[u] : 0.0f;
     const uint32_t len[2] = {o1 - o0, o2 - o1};
     const uint32_t off[2] = {o0, o1};
@@ -864,14 +898,15 @@ __global__ void __launch_bounds__(256) cand_kernel(JoinArgs a) {
       uint32_t* list = kind == 0 ? arr_n : arr_o;
       uint64_t pick = first[kind];
       if (len[kind] > a.k_rev) {
-        Pool<1> top;
-        top.clear();
-        top.insert_batch(first[kind], a.k_rev);
+        // the k_rev smallest keys (unique: one per owner) by sorting 64 at a
+        // time and keeping the 64 smallest (k_rev < 64 here), whatever order
+        // the segment holds them in
+        uint64_t top = wave_sort64_keys(first[kind]);
         for (uint32_t b = 64; b < len[kind]; b += 64) {
           const uint64_t ck = b + lane < len[kind] ? a.rev[off[kind] + b + lane] : kSentinel;
-          top.insert_batch(ck, a.k_rev);
+          top = wave_merge_low64(top, wave_sort64_keys(ck));
         }
-        pick = static_cast<uint32_t>(lane) < a.k_rev ? top.key[0] : kSentinel;
+        pick = static_cast<uint32_t>(lane) < a.k_rev ? top : kSentinel;
       }
       const bool take = pick != kSentinel;
       const uint64_t mt = ballot(take);
