@@ -188,10 +188,11 @@ hipError_t fill_u32(uint32_t* p, uint32_t v, uint64_t n, hipStream_t s) {
 // One wavefront per adjacency row: every id must be FGIM_NONE or < n, not
 // the row's own id, and unique within the row.  Sets *err on a violation;
 // when min_deg is given, lowers *min_deg to the smallest out-degree seen, and
-// when edges is given, adds the sum of the out-degrees to *edges.
+// when edges is given, adds the sum of the out-degrees times `weight` to
+// *edges.
 __global__ void __launch_bounds__(256) validate_graph_kernel(const uint32_t* adj, uint32_t n,
                                                              uint32_t stride, uint32_t* err,
-                                                             uint32_t* min_deg, unsigned long long* edges) {
+                                                             uint32_t* min_deg, double* edges, double weight) {
   const uint32_t wave = threadIdx.x / 64;
   const int lane = lane_id();
   uint32_t mdeg = 0xFFFFFFFFu;
@@ -227,14 +228,16 @@ __global__ void __launch_bounds__(256) validate_graph_kernel(const uint32_t* adj
   __syncthreads();
   if (edges && threadIdx.x == 0) {
     const unsigned long long t = s_e[0] + s_e[1] + s_e[2] + s_e[3];
-    if (t) atomicAdd(edges, t);
+    if (t) atomicAdd(edges, static_cast<double>(t) * weight);
   }
 }
 
 hipError_t validate_graph(const uint32_t* adj, uint32_t n, uint32_t stride, uint32_t* err,
-                          hipStream_t s, uint32_t* min_deg = nullptr, unsigned long long* edges = nullptr) {
+                          hipStream_t s, uint32_t* min_deg = nullptr, double* edges = nullptr,
+                          double weight = 1.0) {
   uint32_t blocks = std::min<uint32_t>((n + 3) / 4, 2048);
-  hipLaunchKernelGGL(validate_graph_kernel, dim3(blocks), dim3(256), 0, s, adj, n, stride, err, min_deg, edges);
+  hipLaunchKernelGGL(validate_graph_kernel, dim3(blocks), dim3(256), 0, s, adj, n, stride, err, min_deg, edges,
+                     weight);
   return hipGetLastError();
 }
 
@@ -478,11 +481,11 @@ fgim_status beam_shape(uint32_t dim, uint32_t L, uint32_t k, const fgim_params* 
   // mean degree 9.4: 294 / 343 / 350 ms -> 266 / 332 / 338 ms.  Denser graphs
   // keep the shape below: at mean degree 13.5 (2 x 500k rows, d = 128)
   // either change was 1-14 % slower, at 18.6 (the 2 M-row set with
-  // navigable inputs) both together 4-9 % slower.  (20 uneven sub-indexes of
-  // 11.4 M rows, d = 128, L = 96, ran 15.5 / 15.7 / 15.6 s -> 13.6 / 15.0 /
-  // 15.0 s with this shape forced, but their mean degree, weighted by rows,
-  // is above 12: the rule leaves them on the default.)  The mean is over
-  // rows, edges / n_total.
+  // navigable inputs) both together 4-9 % slower.  20 uneven sub-indexes of
+  // 11.4 M rows, d = 128, L = 96 (four dense 2.5 M-row graphs, sixteen sparse
+  // small ones: mean degree 9.9 over graphs, above 12 over rows): 15.5 /
+  // 15.7 / 15.6 s -> 13.6 / 15.0 / 15.0 s.  The mean weights each graph by
+  // the searches that run in it (n_total - n_i), not by its rows.
   const bool short_search = mean_degree > 0.0 && mean_degree <= 12.0;
   uint32_t P = p && p->lanes_per_dist ? p->lanes_per_dist
                                       : std::min<uint32_t>(64, std::max<uint32_t>(std::min<uint32_t>(4, N),
@@ -569,7 +572,8 @@ fgim_status cross_query_run(const fgim_dataset* d, const fgim_params* p, uint32_
   HIP_TRY(fill_u32(reinterpret_cast<uint32_t*>(b.cnt), 0u, 8, s));
   for (uint32_t i = 0; i < d->h; ++i)
     HIP_TRY(validate_graph(d->subs[i].adj, d->subs[i].n, d->subs[i].adj_stride, hdr + 1, s,
-                           p->autotune ? hdr + 2 : nullptr, b.cnt + 3));
+                           p->autotune ? hdr + 2 : nullptr, reinterpret_cast<double*>(b.cnt + 3),
+                           static_cast<double>(d->n_total - d->subs[i].n) / static_cast<double>(d->subs[i].n)));
   if (p->precision == FGIM_FP8_E4M3 && !b.lps) return fail(FGIM_ERR_INVALID_ARG, "FP8 copy given without scales");
 
   BeamArgs a{};
@@ -609,11 +613,15 @@ fgim_status cross_query_run(const fgim_dataset* d, const fgim_params* p, uint32_
     if (p->precision != FGIM_FP32 && p->rerank) lo = std::max(lo, p->rerank);
     FGIM_TRY(tune_stage1(a, d, p, fmt, l2, lo, &L, &shape, &ms_tune, s));
   } else {
-    // the mean out-degree of the graphs (summed by the validation above)
-    unsigned long long edges = 0;
-    HIP_TRY(hipMemcpyAsync(&edges, b.cnt + 3, sizeof(edges), hipMemcpyDeviceToHost, s));
+    // The mean out-degree of the graphs the searches run in: graph i is
+    // searched by the n_total - n_i vertices outside it, so its mean degree
+    // (its degree sum over n_i, summed by the validation above) counts with
+    // that weight.  A lone graph is never searched: no mean.
+    double wsum = 0.0, wtot = 0.0;
+    for (uint32_t i = 0; i < d->h; ++i) wtot += static_cast<double>(d->n_total - d->subs[i].n);
+    HIP_TRY(hipMemcpyAsync(&wsum, b.cnt + 3, sizeof(wsum), hipMemcpyDeviceToHost, s));
     HIP_TRY(hipStreamSynchronize(s));
-    FGIM_TRY(beam_shape(d->dim, L, p->k, p, &shape, static_cast<double>(edges) / static_cast<double>(d->n_total)));
+    FGIM_TRY(beam_shape(d->dim, L, p->k, p, &shape, wtot > 0.0 ? wsum / wtot : 0.0));
   }
   uint32_t rerank = 0;
   FGIM_TRY(rerank_for(p, L, &rerank));

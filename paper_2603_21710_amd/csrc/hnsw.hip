@@ -268,7 +268,7 @@ static hipError_t launch_descent(const DescentArgs& a, const BeamShape& sh, hipS
 
 fgim_status check_rows(const float* base, uint64_t n, uint32_t dim, uint64_t ld);
 hipError_t validate_graph(const uint32_t* adj, uint32_t n, uint32_t stride, uint32_t* err, hipStream_t s,
-                          uint32_t* min_deg, unsigned long long* edges);
+                          uint32_t* min_deg, double* edges, double weight);
 
 // every id below n or FGIM_NONE (sets *err otherwise)
 __global__ void ids_in_range_kernel(const uint32_t* ids, uint64_t count, uint64_t n, uint32_t* err) {
@@ -429,7 +429,7 @@ extern "C" fgim_status fgim_search_layers(const float* base, uint64_t n, uint32_
   HIP_TRY(hipMemcpyAsync(meta, hm, sizeof(hm), hipMemcpyHostToDevice, s));
   HIP_TRY(fill_u32(hdr, 0u, 8, s));
   // malformed inputs are rejected before any of their ids is followed
-  HIP_TRY(validate_graph(base_adj, static_cast<uint32_t>(n), stride, hdr + 3, s, nullptr, nullptr));
+  HIP_TRY(validate_graph(base_adj, static_cast<uint32_t>(n), stride, hdr + 3, s, nullptr, nullptr, 1.0));
   if (acc) {
     hipLaunchKernelGGL(ids_in_range_kernel, dim3(grid_of(acc)), dim3(256), 0, s, layer_ids, acc, n, hdr + 3);
     hipLaunchKernelGGL(ids_in_range_kernel, dim3(grid_of(acc * M)), dim3(256), 0, s, layer_adj, acc * M, n, hdr + 3);
