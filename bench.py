@@ -321,11 +321,17 @@ def beam_roofline(fg, m, cfg, X, graphs, precision, st, beam_ms, peak_meas, coun
     # Algorithm 1.  That counting launch uses another lanes-per-distance
     # (another kernel instance, the same count), so a kernel trace of this
     # script lists the timed launches under their own name.
-    # The other lane count halves P where that keeps at most four chunks per
-    # lane (doubling it from two chunks per lane leaves one, the slowest shape)
+    # The other lane count is half of P where that keeps at most four chunks
+    # per lane (doubling from two chunks per lane leaves one, the slowest
+    # shape), else double P where it fits, else half of P: never P itself.
     used_p = st["lanes_per_dist"]
     chunks = max(1, X.shape[1] // 4)
-    alt_p = used_p // 2 if used_p >= 2 and chunks // (used_p // 2) <= 4 else min(64, used_p * 2)
+    if used_p >= 2 and chunks // (used_p // 2) <= 4:
+        alt_p = used_p // 2
+    elif used_p * 2 <= min(64, chunks):
+        alt_p = used_p * 2
+    else:
+        alt_p = max(1, used_p // 2)
     st_big = st
     if count_launch:
         log(f"{cfg.name} {precision}: counting launch ({alt_p} lanes per distance, 16384 visited slots)")
