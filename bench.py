@@ -314,6 +314,20 @@ def build_inputs(cfg, device):
     return X, graphs, reach, build_s
 
 
+def counting_lanes(used_p, dim):
+    """Lanes per distance of the distance-counting launch: half of the timed
+    launch's P where that keeps at most four chunks per lane (doubling from two
+    chunks per lane leaves one, the slowest shape), else double P where it
+    fits, else half of P; never P itself, so a kernel trace tells the two
+    launches apart."""
+    chunks = max(1, dim // 4)
+    if used_p >= 2 and chunks // (used_p // 2) <= 4:
+        return used_p // 2
+    if used_p * 2 <= min(64, chunks):
+        return used_p * 2
+    return max(1, used_p // 2)
+
+
 def beam_roofline(fg, m, cfg, X, graphs, precision, st, beam_ms, peak_meas, count_launch=True):
     """Roofline of the beam kernel for one form (see the module docstring)."""
     # The distance count is measured with the largest visited cache, which
@@ -321,17 +335,8 @@ def beam_roofline(fg, m, cfg, X, graphs, precision, st, beam_ms, peak_meas, coun
     # Algorithm 1.  That counting launch uses another lanes-per-distance
     # (another kernel instance, the same count), so a kernel trace of this
     # script lists the timed launches under their own name.
-    # The other lane count is half of P where that keeps at most four chunks
-    # per lane (doubling from two chunks per lane leaves one, the slowest
-    # shape), else double P where it fits, else half of P: never P itself.
     used_p = st["lanes_per_dist"]
-    chunks = max(1, X.shape[1] // 4)
-    if used_p >= 2 and chunks // (used_p // 2) <= 4:
-        alt_p = used_p // 2
-    elif used_p * 2 <= min(64, chunks):
-        alt_p = used_p * 2
-    else:
-        alt_p = max(1, used_p // 2)
+    alt_p = counting_lanes(used_p, X.shape[1])
     st_big = st
     if count_launch:
         log(f"{cfg.name} {precision}: counting launch ({alt_p} lanes per distance, 16384 visited slots)")

@@ -14,15 +14,15 @@ import bench  # noqa: E402
 
 
 def test_traffic_from_committed_summary_matches_sources():
-    path = os.path.join(ROOT, "profiles", "beam_kernel_cfg2_fp32_counters.md")
+    path = os.path.join(ROOT, "profiles", "beam_kernel_cfg4_fp32_counters.md")
     if not os.path.exists(path):
         pytest.skip("no committed counter summary")
     text = open(path).read()
     if f"`{bench.beam_source_hash()}`" in text:
-        t = bench.measured_traffic("cfg2", "fp32")
+        t = bench.measured_traffic("cfg4", "fp32")
         assert t is not None and t > 1e9
     else:
-        assert bench.measured_traffic("cfg2", "fp32") is None
+        assert bench.measured_traffic("cfg4", "fp32") is None
 
 
 def test_traffic_absent_for_unprofiled_workloads():
@@ -57,3 +57,19 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode != 0
     assert "one GPU" in r.stderr
+
+
+@pytest.mark.parametrize("used_p,dim,want", [
+    (64, 768, 32),   # d = 768: doubling is capped and halving leaves six chunks per lane
+    (8, 128, 16),    # four chunks per lane: halving would leave eight
+    (16, 128, 8),    # two chunks per lane: doubling would leave one
+    (16, 96, 8),
+    (8, 96, 16),
+    (4, 32, 2),
+    (1, 4, 1),       # one chunk: nothing else exists
+])
+def test_counting_launch_lanes(used_p, dim, want):
+    got = bench.counting_lanes(used_p, dim)
+    assert got == want
+    if dim > 4:
+        assert got != used_p
