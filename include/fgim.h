@@ -120,7 +120,11 @@ typedef struct {
                             minimum-querying bound of Section 4.1.2 and picks
                             the launch shape */
     /* Launch shape (0 = choose automatically).  None of these changes an
-     * FP32 result bit. */
+     * FP32 result bit.  The automatic shape gives each lane four chunks of
+     * four coordinates (at most 64 lanes), 32 waves per CU and 1024 visited
+     * slots for L <= 32, else 2048; when the graphs searched have a mean
+     * out-degree of at most 12 (each graph weighted by the searches run in
+     * it), two chunks per lane and 1024 slots. */
     uint32_t lanes_per_dist;   /* lanes that share one distance: 1..64, power of 2 */
     uint32_t waves_per_cu;     /* resident waves per compute unit of the beam kernel */
     uint32_t visited_slots;    /* entries of the per-wave LDS visited cache (power of 2) */
