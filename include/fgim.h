@@ -121,7 +121,8 @@ typedef struct {
                             the launch shape */
     /* Launch shape (0 = choose automatically).  None of these changes an
      * FP32 result bit.  The automatic shape gives each lane four chunks of
-     * four coordinates (at most 64 lanes), 32 waves per CU and 1024 visited
+     * four coordinates (fewer below d = 64; at most 64 lanes, so more above
+     * d = 1024), 32 waves per CU and 1024 visited
      * slots for L <= 32, else 2048; when the graphs searched have a mean
      * out-degree of at most 12 (each graph weighted by the searches run in
      * it), two chunks per lane and 1024 slots. */
