@@ -2409,7 +2409,8 @@ fgim_status refine_impl(const fgim_dataset* d, const fgim_params* p, uint32_t* i
       hipLaunchKernelGGL(row_norms_kernel, dim3(grid_for(N, 4)), dim3(256), 0, s, d->base, N, dim, d->ld, nrm2, qerr2);
       HIP_TRY(hipGetLastError());
     }
-    FGIM_TRY(scr.get(&b.scan_tmp, std::max(scan_tmp_words(2 * N + 1), scan_tmp_words(mat2_words)) + 16));
+    FGIM_TRY(scr.get(&b.scan_tmp,
+                     scan_tmp_words(std::max(std::max<uint64_t>(2 * N + 1, mat_words), mat2_words)) + 16));
     FGIM_TRY(scr.get(&b.sub_off, d->h));
     std::vector<uint64_t> hoff(d->h);
     for (uint32_t i = 0; i < d->h; ++i) hoff[i] = d->subs[i].row_offset;
